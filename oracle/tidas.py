@@ -1,0 +1,74 @@
+"""The tiDAS line model as an operator on a reflectivity map (oracle; test
+infrastructure only).
+
+Sec. 2.4, eqn:line_conv: along an image line the reconstruction is a
+convolution with fixed parameters, scaled per output point by the weight set
+Theta.  Written against the reflectivity map R (Born linearity, Sec. 2), each
+lateral column is convolved along depth, and the kernel is chosen by the
+OUTPUT row (gather form: Theta multiplies the output):
+
+    Y[b][i][j] = sum_{m=-h..h} K[i][m+h] * R[b][i-m][j],   R = 0 outside [0, Z)
+
+The adjoint (transpose) is
+
+    Rbar[b][s][j] = sum_{m=-h..h} K[s+m][m+h] * Ybar[b][s+m][j],
+
+terms with s + m outside [0, Z) dropped.  Both are written as plain loops
+over the tap index m.
+"""
+import numpy as np
+
+
+def _check(K):
+    K = np.asarray(K, np.float64)
+    if K.ndim != 2 or K.shape[1] % 2 != 1:
+        raise ValueError("kernel bank must be [Z][K] with K odd")
+    return K, (K.shape[1] - 1) // 2
+
+
+def apply(K, R):
+    """Y = A R.  K [Z][K]; R [Z][X] or [B][Z][X]."""
+    K, h = _check(K)
+    R = np.asarray(R, np.float64)
+    squeeze = R.ndim == 2
+    R3 = R[None] if squeeze else R
+    B, Z, X = R3.shape
+    if K.shape[0] != Z:
+        raise ValueError("kernel bank rows must equal image rows")
+    Y = np.zeros_like(R3)
+    for m in range(-h, h + 1):
+        for i in range(Z):
+            s = i - m
+            if 0 <= s < Z:
+                Y[:, i, :] += K[i, m + h] * R3[:, s, :]
+    return Y[0] if squeeze else Y
+
+
+def adjoint(K, Yb):
+    """Rbar = A^T Ybar.  Same shapes as ``apply``."""
+    K, h = _check(K)
+    Yb = np.asarray(Yb, np.float64)
+    squeeze = Yb.ndim == 2
+    Y3 = Yb[None] if squeeze else Yb
+    B, Z, X = Y3.shape
+    if K.shape[0] != Z:
+        raise ValueError("kernel bank rows must equal image rows")
+    Rb = np.zeros_like(Y3)
+    for m in range(-h, h + 1):
+        for s in range(Z):
+            i = s + m
+            if 0 <= i < Z:
+                Rb[:, s, :] += K[i, m + h] * Y3[:, i, :]
+    return Rb[0] if squeeze else Rb
+
+
+def matrix(K):
+    """The banded Z x Z matrix M of the column operator: M[i][i-m] = K[i][m+h]."""
+    K, h = _check(K)
+    Z = K.shape[0]
+    M = np.zeros((Z, Z), np.float64)
+    for i in range(Z):
+        for m in range(-h, h + 1):
+            if 0 <= i - m < Z:
+                M[i, i - m] = K[i, m + h]
+    return M

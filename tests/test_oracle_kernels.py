@@ -1,0 +1,168 @@
+"""Pins of the oracle's kernel construction: exact DAS PSF kernels
+(Sec. 2.2 eq:PSF) and paper-mode fixed-delay + theta kernels (Sec. 2.3
+eqn:tDAS, eqn:theta; Sec. 3.1-3.2 FWHM window)."""
+import numpy as np
+import pytest
+
+from oracle import das, kernels, pulse, simulate
+from workloads import config
+from tests.helpers import das_kw, sim_kw, oracle_kw
+
+C1 = config(1)
+
+
+def test_exact_kernel_rows_equal_das_of_materialised_echo():
+    """The analytic unit-echo path equals RF synthesis (FP64) followed by DAS at
+    the pixels (0, z_i + m dz)."""
+    s = C1.replace(n_samples=1500, angles=(-0.06, 0.0, 0.1))
+    K = 9
+    h = (K - 1) // 2
+    zr = np.array([4.1e-3, 11.37e-3, 17.9e-3])
+    kb = kernels.exact_kernels(zr, s.dz, K, **oracle_kw(s))
+    for i, z in enumerate(zr):
+        rf = simulate.simulate_rf([0.0], [z], [1.0], **sim_kw(s))
+        col = das.das(rf, [0.0], z + np.arange(-h, h + 1) * s.dz, **das_kw(s))[:, 0]
+        assert np.max(np.abs(kb[i] - col)) <= 1e-13 * np.max(np.abs(col))
+        # centre tap = DAS value at the scatterer's own pixel
+        assert abs(kb[i, h] - col[h]) <= 1e-13 * abs(col[h])
+
+
+def test_exact_kernel_single_element_sample_aligned_is_sampled_pulse():
+    """C = 1, unsteered, dz and z_i on the sample grid: every read falls on a
+    sample, so K[i][m+h] = p(2 m dz / c)."""
+    s = C1.replace(n_elem=1, n_samples=4000)
+    dz = 3 * s.c / (2 * s.fs)
+    K = 21
+    h = 10
+    zr = np.array([200, 517, 1300]) * s.c / (2 * s.fs)
+    kb = kernels.exact_kernels(zr, dz, K, **oracle_kw(s))
+    ref = pulse.pulse(2 * np.arange(-h, h + 1) * dz / s.c, s.fc, s.sigma)
+    assert np.max(np.abs(kb - ref[None, :])) < 1e-13
+
+
+def pythagorean_setup():
+    """Two elements at x = +-30 l with l = c / fs; at reference depths 40 l and
+    72 l the receive distances are 50 l and 78 l (Pythagorean triples), so
+    every fractional sample index is an integer."""
+    s = C1.replace(n_elem=2, n_samples=4000, fnumber=0.5)
+    ell = s.c / s.fs
+    s = s.replace(pitch=60 * ell)
+    return s, ell
+
+
+def test_paper_kernel_fixed_delay_response_is_pure_pulse_exact_case():
+    s, ell = pythagorean_setup()
+    dz = ell / 2                           # one sample of two-way time
+    K = 15
+    h = 7
+    for zr in (40 * ell, 72 * ell):
+        hr = kernels.fixed_delay_line(zr + np.arange(-h, h + 1) * dz, zr, zr, **oracle_kw(s))
+        from oracle import geometry
+        wsum = np.sum(geometry.hann_apod(-geometry.element_x(2, s.pitch), zr, s.fnumber))
+        ref = wsum * pulse.pulse(2 * np.arange(-h, h + 1) * dz / s.c, s.fc, s.sigma)
+        assert wsum > 0
+        assert np.max(np.abs(hr - ref)) < 1e-13
+
+
+def test_paper_kernel_general_case_pulse_up_to_lerp_error():
+    """With arbitrary phases the fixed-delay response of the reference
+    scatterer is the pulse up to the linear-interpolation error
+    (bounded by (pi fc / fs)^2 / 2 relative to the peak)."""
+    s = C1
+    K = 65
+    h = 32
+    zr = 21.3e-3
+    hr = kernels.fixed_delay_line(zr + np.arange(-h, h + 1) * s.dz, zr, zr, **oracle_kw(s))
+    from oracle import geometry
+    wsum = np.sum(geometry.hann_apod(-geometry.element_x(s.n_elem, s.pitch), zr, s.fnumber))
+    ref = wsum * pulse.pulse(2 * np.arange(-h, h + 1) * s.dz / s.c, s.fc, s.sigma)
+    bound = 0.5 * (np.pi * s.fc / s.fs) ** 2
+    assert np.max(np.abs(hr - ref)) <= bound * wsum
+    assert np.max(np.abs(hr - ref)) > 0
+
+
+def test_theta_time_domain_equals_frequency_domain():
+    """Plancherel (Sec. 2.3): the time-domain least-squares weight equals the
+    first line of eqn:theta evaluated on DFTs."""
+    rng = np.random.default_rng(5)
+    for n in (1, 7, 64, 101):
+        a = rng.standard_normal(n)
+        b = rng.standard_normal(n) + 0.7 * a
+        assert abs(kernels.theta_ls(a, b) - kernels.theta_frequency(a, b)) < 1e-12 * max(1, abs(kernels.theta_ls(a, b)))
+
+
+def test_theta_properties():
+    rng = np.random.default_rng(6)
+    a = rng.standard_normal(33)
+    b = rng.standard_normal(33)
+    t = kernels.theta_ls(a, b)
+    assert abs(kernels.theta_ls(a, 3.5 * b) - 3.5 * t) < 1e-12
+    assert abs(kernels.theta_ls(a, a) - 1.0) < 1e-15
+    assert kernels.theta_ls(np.zeros(5), b[:5]) == 0.0
+
+    def J(th):
+        return np.sum((th * a - b) ** 2)
+    for d in (1e-3, 0.1, 1.0):
+        assert J(t + d) >= J(t) and J(t - d) >= J(t)
+
+
+def test_fwhm_exact_on_triangle_and_gaussian_envelope():
+    # triangle of height 1 (peak on a sample) and half base 10.6: FWHM = 10.6
+    # exactly, the crossings fall between samples on the linear pieces
+    x = np.arange(-30, 31, dtype=float)
+    tri = np.maximum(0.0, 1.0 - np.abs(x) / 10.6)
+    assert abs(kernels.fwhm(tri, 1.0) - 10.6) < 1e-12
+    assert abs(kernels.fwhm(tri, 0.5) - 5.3) < 1e-12
+    # an asymmetric triangle: left half base 4.2, right 7.8 -> FWHM 6.0
+    asym = np.where(x < 0, np.maximum(0.0, 1.0 + x / 4.2), np.maximum(0.0, 1.0 - x / 7.8))
+    assert abs(kernels.fwhm(asym, 1.0) - 6.0) < 1e-12
+    # Gaussian-modulated carrier with many cycles: envelope FWHM -> 2 sqrt(2 ln 2) sigma
+    t = np.arange(-400, 401, dtype=float)
+    sig = 40.0
+    sigl = np.exp(-t * t / (2 * sig * sig)) * np.cos(2 * np.pi * 0.21 * t)
+    env = kernels.envelope(sigl)
+    assert abs(kernels.fwhm(env, 1.0) - pulse.FWHM_PER_SIGMA * sig) < 0.05
+    assert np.all(env >= np.abs(sigl) - 1e-12)
+
+
+def test_envelope_of_cosine_is_flat():
+    n = 256
+    k = np.arange(n)
+    x = 2.0 * np.cos(2 * np.pi * 32 * k / n)   # periodic in the padded length -> exact
+    env = kernels.envelope(x)
+    assert np.all(env > 0.9)
+
+
+def test_paper_theta_single_element_is_one():
+    """C = 1: the fixed and the dynamic delay laws coincide (one element on the
+    axis), so a_i = b_i and theta_i = 1."""
+    s = C1.replace(n_elem=1, n_samples=3000)
+    zr = s.z0 + np.arange(40, 60) * s.dz
+    kb, th, W = kernels.paper_kernels(zr, s.dz, 33, **oracle_kw(s))
+    assert np.max(np.abs(th - 1.0)) < 1e-13
+    ref = kernels.exact_kernels(zr, s.dz, 33, **oracle_kw(s))
+    assert np.max(np.abs(kb - ref)) < 1e-13
+    assert np.all(W > 0)
+
+
+def test_paper_theta_near_one_on_own_row_and_window_is_psf_fwhm():
+    s = C1
+    zr = s.z0 + np.array([60, 120, 200]) * s.dz
+    kb, th, W = kernels.paper_kernels(zr, s.dz, 65, **oracle_kw(s))
+    assert np.all(np.abs(th - 1.0) < 0.05)
+    # PSF FWHM is close to the pulse's two-way envelope FWHM (cycles / fc in time)
+    pulse_fwhm_depth = s.cycles / s.fc * s.c / 2
+    assert np.all(np.abs(W - pulse_fwhm_depth) < 0.25 * pulse_fwhm_depth)
+
+
+def test_paper_theta_drops_away_from_reference():
+    """Sec. 3.3: the approximation degrades away from the reference depth; a
+    frozen receive law defocuses distant scatterers, so theta moves away from
+    the own-row value."""
+    s = C1
+    rows = np.array([40, 100, 150, 200, 240])
+    zr = s.z0 + np.arange(s.nz) * s.dz
+    ref = np.full(s.nz, 150)
+    kb, th, W = kernels.paper_kernels(zr[rows], s.dz, 65, ref_rows=np.searchsorted(rows, ref[rows]), **oracle_kw(s))
+    assert abs(th[2] - 1.0) < 0.05
+    assert abs(th[0] - 1.0) > abs(th[2] - 1.0)
