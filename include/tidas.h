@@ -1,0 +1,181 @@
+/*
+ * tidas.h -- C ABI of the MI355X (gfx950) tiDAS library.
+ *
+ * Implements the hot path of "tiDAS: a time invariant approximation of the
+ * Delay and Sum algorithm for biomedical ultrasound PSF reconstructions"
+ * (arXiv 2507.15464):
+ *
+ *   das_beamform         exact Delay-and-Sum (Sec. 2, eqn:appF)
+ *   tidas_build_kernels  per-depth-row kernels derived from DAS
+ *                        (Sec. 2.2 eq:PSF; Sec. 2.3 eqn:tDAS, eqn:theta;
+ *                        Sec. 3.1-3.2 FWHM correction window)
+ *   tidas_apply          the time-invariant line model (Sec. 2.4, eqn:line_conv)
+ *   tidas_adjoint        its transpose
+ *   tidas_simulate_rf    Born-approximation RF synthesis (Sec. 2, eqn:SRX),
+ *                        the input generator of the path
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units are SI (m, s, Hz, rad).  Device arrays are float32, C-order and
+ * contiguous.  Layouts:
+ *   RF channel data   [B][A][C][T]  frames x angles x elements x samples
+ *   images, maps      [B][Z][X]     frames x depth rows x lateral columns
+ *   kernel bank       [Z][K]        one K-tap kernel per OUTPUT depth row
+ * Geometry: element n (0 <= n < C) sits at x_n = (n - (C-1)/2) * pitch,
+ * depth 0; pixel (i, j) sits at (x0 + j dx, z0 + i dz).  A plane wave of angle
+ * a reaches (x, z) at (x sin a + z cos a) / c; RF sample k is taken at time
+ * t0 + k / fs.  Receive apodization is a Hann window of half width
+ * z / (2 F) (weight 0.5 (1 + cos(pi d / (z / 2F))), zero outside).  Channel
+ * data are read with linear interpolation, zero outside [0, T-1].
+ *
+ * Pointers marked DEV are device pointers owned by the caller; HOST pointers
+ * are read during the call only.  The library keeps no pointer after a call
+ * returns.  Work is enqueued on `stream` (a hipStream_t; NULL = the legacy
+ * default stream) and is asynchronous: execution errors surface at the
+ * caller's next synchronisation.  Outputs must not overlap inputs.
+ *
+ * Return codes: 0 = OK; TIDAS_EINVAL (-1) invalid argument, checked before
+ * any work is enqueued, in which case nothing is written; TIDAS_EHIP (-2) a
+ * HIP runtime or launch error; TIDAS_ENOMEM (-3) a temporary device
+ * allocation failed; TIDAS_EUNSUPPORTED (-4) a valid request this build does
+ * not handle.  tidas_last_error() returns a thread-local message describing
+ * the last non-zero status of the calling thread.
+ */
+#ifndef TIDAS_H
+#define TIDAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TIDAS_OK 0
+#define TIDAS_EINVAL (-1)
+#define TIDAS_EHIP (-2)
+#define TIDAS_ENOMEM (-3)
+#define TIDAS_EUNSUPPORTED (-4)
+
+#define TIDAS_MODE_EXACT 0 /* kernel = DAS PSF of a unit scatterer (Sec. 2.2 eq:PSF)        */
+#define TIDAS_MODE_PAPER 1 /* kernel = theta x fixed-delay response (Sec. 2.3, eqn:theta)  */
+
+/* Linear array: element count C >= 1, pitch > 0, speed of sound c > 0 (Sec. 2.1). */
+typedef struct tidas_array {
+    int32_t n_elem;
+    double pitch;
+    double c;
+} tidas_array;
+
+/* Transmit and sampling.  n_angles >= 1 plane waves whose angles (radians)
+ * are read from the HOST array `angles`; sampling rate fs > 0; time of RF
+ * sample 0, t0; pulse p(t) = exp(-t^2 / (2 s^2)) cos(2 pi fc t) for
+ * |t| <= 4 s, zero beyond, with the envelope FWHM 2 sqrt(2 ln 2) s spanning
+ * `cycles` periods of fc (fc > 0, cycles > 0).  The pulse is used only where
+ * echoes are synthesised (kernel building, RF synthesis). */
+typedef struct tidas_tx {
+    int32_t n_angles;
+    const double* angles; /* HOST [n_angles] */
+    double fs;
+    double t0;
+    double fc;
+    double cycles;
+} tidas_tx;
+
+/* Receive: F-number of the Hann aperture (> 0). */
+typedef struct tidas_rx {
+    double fnumber;
+} tidas_rx;
+
+/* Image grid: nz >= 1 depth rows, nx >= 1 lateral columns; pixel (i, j) at
+ * (x0 + j dx, z0 + i dz); dz > 0 and dx > 0. */
+typedef struct tidas_grid {
+    int32_t nz, nx;
+    double z0, dz, x0, dx;
+} tidas_grid;
+
+/* Library version string (static storage). */
+const char* tidas_version(void);
+
+/* Message for the last non-zero status returned on the calling thread. */
+const char* tidas_last_error(void);
+
+/*
+ * Exact Delay-and-Sum, Sec. 2 eqn:appF: every pixel gets its own delay
+ * profile.  For each frame b
+ *   image[b][i][j] = sum_a sum_n w(x_j - x_n, z_i) *
+ *                    L(rf[b][a][n], (tau_n(x_j, z_i; a) - t0) * fs)
+ * with tau_n = (x sin a + z cos a) / c + sqrt((x - x_n)^2 + z^2) / c, the
+ * angles coherently compounded.  rf is DEV [n_frames][A][C][n_samples],
+ * image DEV [n_frames][nz][nx] (overwritten).  n_frames >= 1,
+ * n_samples >= 2.  All frames share one geometry.
+ */
+int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
+                     const tidas_grid* grid, const float* rf, int32_t n_samples,
+                     int32_t n_frames, float* image, void* stream);
+
+/*
+ * Per-depth-row kernel bank of the line model, evaluated on the centre line
+ * x = 0 from the echo of a unit scatterer (computed analytically in float64
+ * over n_samples RF samples, zero outside the record).  h = (K-1)/2.
+ *
+ * mode TIDAS_MODE_EXACT (Sec. 2.2, eq:PSF):
+ *   kernels[i][m+h] = DAS of a unit scatterer at (0, z_i), evaluated at the
+ *   pixel (0, z_i + m dz); the grid's x0, dx and nx are not used.
+ * mode TIDAS_MODE_PAPER (Sec. 2.3 eqn:tDAS, eqn:diff, eqn:theta; Sec. 3.1-3.2):
+ *   the receive delays and weights are frozen at the depth of row
+ *   r = ref_row[i] (ref_row = NULL: r = i).  With the fixed-delay line
+ *   F_r[S](z) = sum_a sum_n w(-x_n, z_r) L(S[a][n], (t(z; a) - D_n(z_r) - t0) fs),
+ *   t(z; a) = z cos(a) / c + z / c and D_n the delay law of eqn:delay,
+ *     h_r[m]   = F_r[unit echo at z_r](z_r + m dz),
+ *     W_r      = FWHM of the envelope (|analytic signal|, DFT zero-padded to
+ *                the first power of two >= twice the length) of the DAS PSF
+ *                of the unit echo at z_r on the fine axis z_r + q c/(2 fs),
+ *                |q| <= ceil(8 s fs),
+ *     theta_i  = sum a b / sum a^2 over the fine points z_i + q c/(2 fs),
+ *                |q| <= floor(W_r / (2 c/(2 fs))), with a = F_r[unit echo at
+ *                z_i] and b = DAS of the unit echo at z_i (first line of
+ *                eqn:theta, time domain), 0 when sum a^2 = 0,
+ *     kernels[i][m+h] = theta_i * h_r[m].
+ * kernels DEV [nz][K]; theta DEV [nz] or NULL (exact mode writes 1).
+ * ref_row HOST [nz] with 0 <= ref_row[i] < nz, or NULL.  K odd, >= 1.
+ * Paper mode allocates and frees a small temporary device buffer,
+ * stream-ordered, and may return TIDAS_ENOMEM.
+ */
+int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
+                            const tidas_grid* grid, int32_t n_samples, int32_t K, int32_t mode,
+                            const int32_t* ref_row, float* kernels, float* theta, void* stream);
+
+/*
+ * The tiDAS line model, Sec. 2.4 eqn:line_conv, applied to a reflectivity
+ * map along depth in every lateral column, kernel chosen by the output row:
+ *   image[b][i][j] = sum_{m=-h..h} kernels[i][m+h] * refl[b][i-m][j],
+ * refl taken as zero outside [0, Z).  kernels DEV [Z][K], K odd >= 1;
+ * refl, image DEV [B][Z][X], B, Z, X >= 1.
+ */
+int32_t tidas_apply(const float* kernels, int32_t K, const float* refl, int32_t B, int32_t Z,
+                    int32_t X, float* image, void* stream);
+
+/*
+ * Transpose of tidas_apply:
+ *   refl_bar[b][s][j] = sum_{m=-h..h} kernels[s+m][m+h] * image_bar[b][s+m][j],
+ * terms with s + m outside [0, Z) dropped.  Shapes as tidas_apply.
+ */
+int32_t tidas_adjoint(const float* kernels, int32_t K, const float* image_bar, int32_t B,
+                      int32_t Z, int32_t X, float* refl_bar, void* stream);
+
+/*
+ * Born-approximation RF synthesis, Sec. 2 eqn:SRX with linear superposition:
+ *   rf[a][n][k] = sum_s amp[s] * p(t0 + k/fs - tau_n(x_s, z_s; a))
+ * accumulated in float64 and rounded once to float32.  scat is DEV
+ * [n_scat][3] float64 rows (x, z, amplitude); rf DEV [A][C][n_samples]
+ * (overwritten).  n_scat >= 0.  Allocates and frees a float64 accumulation
+ * buffer of A*C*n_samples values, stream-ordered (TIDAS_ENOMEM possible).
+ */
+int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* tx, const double* scat,
+                          int32_t n_scat, int32_t n_samples, float* rf, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TIDAS_H */

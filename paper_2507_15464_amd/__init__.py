@@ -1,0 +1,4 @@
+"""MI355X-native tiDAS (arXiv 2507.15464): exact DAS, per-depth-row kernel
+banks, the time-invariant line model and its adjoint, as hand-written HIP
+kernels for gfx950 behind a C ABI (include/tidas.h)."""
+from .api import adjoint, apply, build_kernels, das_beamform, simulate_rf, version  # noqa: F401

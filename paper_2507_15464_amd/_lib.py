@@ -1,0 +1,112 @@
+"""ctypes binding of ``libtidas.so`` (the C ABI declared in include/tidas.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  torch is imported before the library is loaded so that the
+library binds to the HIP runtime torch already loaded (one runtime per
+process).  A missing or stale library raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtidas.so")
+
+TIDAS_OK = 0
+TIDAS_EINVAL = -1
+TIDAS_EHIP = -2
+TIDAS_ENOMEM = -3
+TIDAS_EUNSUPPORTED = -4
+MODE_EXACT = 0
+MODE_PAPER = 1
+
+
+class TidasError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tidas error {code}: {msg}")
+        self.code = code
+
+
+class Array(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int32), ("pitch", ctypes.c_double), ("c", ctypes.c_double)]
+
+
+class Tx(ctypes.Structure):
+    _fields_ = [("n_angles", ctypes.c_int32), ("angles", ctypes.POINTER(ctypes.c_double)),
+                ("fs", ctypes.c_double), ("t0", ctypes.c_double), ("fc", ctypes.c_double),
+                ("cycles", ctypes.c_double)]
+
+
+class Rx(ctypes.Structure):
+    _fields_ = [("fnumber", ctypes.c_double)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int32), ("nx", ctypes.c_int32), ("z0", ctypes.c_double),
+                ("dz", ctypes.c_double), ("x0", ctypes.c_double), ("dx", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_SIGS = {
+    "tidas_version": (ctypes.c_char_p, []),
+    "tidas_last_error": (ctypes.c_char_p, []),
+    "das_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),
+                          _P, _I, _I, _P, _P]),
+    "tidas_build_kernels": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx),
+                                 ctypes.POINTER(Grid), _I, _I, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P]),
+    "tidas_apply": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
+    "tidas_adjoint": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
+    "tidas_simulate_rf": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), _P, _I, _I, _P, _P]),
+}
+
+_lib = None
+
+
+def exported_symbols():
+    """Names of the C entry points this binding expects."""
+    return list(_SIGS)
+
+
+def load(path=None):
+    """Load the library once (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    import torch  # noqa: F401  -- binds the HIP runtime first
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with paper_2507_15464_amd.build.build()")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def check(code):
+    if code != TIDAS_OK:
+        msg = load().tidas_last_error().decode(errors="replace")
+        raise TidasError(code, msg)
+
+
+def make_array(n_elem, pitch, c):
+    return Array(int(n_elem), float(pitch), float(c))
+
+
+def make_tx(angles, fs, t0, fc, cycles):
+    buf = (ctypes.c_double * max(1, len(angles)))(*[float(a) for a in angles])
+    tx = Tx(len(angles), ctypes.cast(buf, ctypes.POINTER(ctypes.c_double)), float(fs), float(t0), float(fc),
+            float(cycles))
+    tx._keep = buf  # keep the HOST angle array alive with the descriptor
+    return tx
+
+
+def make_rx(fnumber):
+    return Rx(float(fnumber))
+
+
+def make_grid(nz, nx, z0, dz, x0, dx):
+    return Grid(int(nz), int(nx), float(z0), float(dz), float(x0), float(dx))

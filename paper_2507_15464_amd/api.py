@@ -1,0 +1,128 @@
+"""Python entry points of the tiDAS library: thin wrappers over the C ABI.
+
+Geometry arguments are duck-typed: ``setup`` needs ``n_elem, pitch, c, fs, t0,
+fc, cycles, angles, fnumber``; ``grid`` needs ``nz, nx, z0, dz, x0, dx`` (one
+object may provide both).  Tensors must be float32, contiguous and on the
+current HIP device; results are enqueued on torch's current stream.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+__all__ = ["das_beamform", "build_kernels", "apply", "adjoint", "simulate_rf", "version"]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_tensor(t, name, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _descs(setup, grid=None):
+    arr = _lib.make_array(setup.n_elem, setup.pitch, setup.c)
+    tx = _lib.make_tx(list(setup.angles), setup.fs, setup.t0, setup.fc, setup.cycles)
+    rx = _lib.make_rx(setup.fnumber)
+    g = _lib.make_grid(grid.nz, grid.nx, grid.z0, grid.dz, grid.x0, grid.dx) if grid is not None else None
+    return arr, tx, rx, g
+
+
+def version():
+    return _lib.load().tidas_version().decode()
+
+
+def das_beamform(rf, setup, grid=None, out=None):
+    """Exact DAS.  rf [B][A][C][T] (or [A][C][T]) -> image [B][Z][X] (or [Z][X])."""
+    grid = grid or setup
+    lib = _lib.load()
+    _check_tensor(rf, "rf")
+    squeeze = rf.dim() == 3
+    r4 = rf.unsqueeze(0) if squeeze else rf
+    if r4.dim() != 4 or r4.shape[1] != len(setup.angles) or r4.shape[2] != setup.n_elem:
+        raise ValueError("rf must be [B][A][C][T] matching the setup")
+    B, T = r4.shape[0], r4.shape[3]
+    if out is None:
+        out = torch.empty((B, grid.nz, grid.nx), device=rf.device, dtype=torch.float32)
+    _check_tensor(out, "out")
+    arr, tx, rx, g = _descs(setup, grid)
+    _lib.check(lib.das_beamform(ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g),
+                                _ptr(r4), T, B, _ptr(out), _stream()))
+    return out[0] if squeeze else out
+
+
+def build_kernels(setup, grid=None, K=None, mode="exact", ref_row=None, n_samples=None, with_theta=False):
+    """Kernel bank [Z][K] (and theta [Z] when with_theta)."""
+    grid = grid or setup
+    lib = _lib.load()
+    K = int(K if K is not None else setup.K)
+    T = int(n_samples if n_samples is not None else setup.n_samples)
+    m = {"exact": _lib.MODE_EXACT, "paper": _lib.MODE_PAPER}[mode]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    kb = torch.empty((grid.nz, K), device=dev, dtype=torch.float32)
+    th = torch.empty(grid.nz, device=dev, dtype=torch.float32) if with_theta else None
+    ref = None
+    if ref_row is not None:
+        vals = [int(v) for v in ref_row]
+        if len(vals) != grid.nz:
+            raise ValueError("ref_row must have one entry per depth row")
+        ref = (ctypes.c_int32 * len(vals))(*vals)
+    arr, tx, rx, g = _descs(setup, grid)
+    _lib.check(lib.tidas_build_kernels(ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g), T, K,
+                                       m, ref, _ptr(kb), _ptr(th), _stream()))
+    return (kb, th) if with_theta else kb
+
+
+def _conv(fn, kernels, x, out):
+    lib = _lib.load()
+    _check_tensor(kernels, "kernels")
+    _check_tensor(x, "input")
+    squeeze = x.dim() == 2
+    x3 = x.unsqueeze(0) if squeeze else x
+    if x3.dim() != 3 or kernels.dim() != 2 or kernels.shape[0] != x3.shape[1]:
+        raise ValueError("kernels must be [Z][K] and the input [B][Z][X] with the same Z")
+    B, Z, X = x3.shape
+    if out is None:
+        out = torch.empty_like(x3)
+    _check_tensor(out, "out")
+    _lib.check(getattr(lib, fn)(_ptr(kernels), kernels.shape[1], _ptr(x3), B, Z, X, _ptr(out), _stream()))
+    return out[0] if squeeze else out
+
+
+def apply(kernels, refl, out=None):
+    """tiDAS line model: image = A(refl), refl [B][Z][X] or [Z][X]."""
+    return _conv("tidas_apply", kernels, refl, out)
+
+
+def adjoint(kernels, image_bar, out=None):
+    """Transpose of ``apply``."""
+    return _conv("tidas_adjoint", kernels, image_bar, out)
+
+
+def simulate_rf(setup, scat, n_samples=None, out=None):
+    """RF [A][C][T] of scatterers ``scat`` (float64 device tensor [S][3]: x, z, amplitude)."""
+    lib = _lib.load()
+    T = int(n_samples if n_samples is not None else setup.n_samples)
+    _check_tensor(scat, "scat", torch.float64)
+    if scat.dim() != 2 or scat.shape[1] != 3:
+        raise ValueError("scat must be [S][3]")
+    if out is None:
+        out = torch.empty((len(setup.angles), setup.n_elem, T), device=scat.device, dtype=torch.float32)
+    _check_tensor(out, "out")
+    arr, tx, _, _ = _descs(setup)
+    _lib.check(lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), _ptr(scat), scat.shape[0], T, _ptr(out),
+                                     _stream()))
+    return out

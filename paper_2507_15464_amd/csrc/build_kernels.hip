@@ -1,0 +1,389 @@
+// Per-depth-row kernel banks of the line model, derived from DAS, and the
+// Born RF synthesis that feeds the path.  All arithmetic here is float64:
+// these run once per geometry (or once per phantom), not per frame.
+//
+// Exact mode (Sec. 2.2, eq:PSF): K[i][m+h] = DAS, at pixel (0, z_i + m dz), of
+// the echo of a unit scatterer at (0, z_i).  The echo is evaluated
+// analytically where DAS reads it: RF1[a][n][k] = p(t0 + k/fs - tau_n) for
+// 0 <= k < T, zero outside the record.
+//
+// Paper mode (Sec. 2.3 eqn:tDAS / eqn:theta; Sec. 3.1-3.2): receive delays and
+// apodization frozen at a reference depth z_r; the kernel is the fixed-delay
+// response h_r scaled by the least-squares weight theta_i fitted inside a
+// window as wide as the FWHM of the DAS PSF envelope at z_r.  Two launches:
+//   paper_ref_kernel  one workgroup per distinct reference row: h_r, the PSF on
+//                     a fine axis, its envelope by a direct DFT (analytic
+//                     signal), and the FWHM;
+//   paper_row_kernel  one workgroup per row: a_i and b_i on the window, the
+//                     two dot products, theta_i, and the scaled kernel row.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tidas {
+
+constexpr int BK_MAX_ANGLES = 32;
+
+struct Setup64 {
+    int32_t C, T, A;
+    double pitch, c, fs, t0, fc, sigma, fnumber, x_first;
+    double sin_a[BK_MAX_ANGLES];
+    double cos_a[BK_MAX_ANGLES];
+};
+
+__device__ __forceinline__ double pulse_d(double t, double fc, double sigma) {
+    if (fabs(t) > 4.0 * sigma) return 0.0;
+    return exp(-t * t / (2.0 * sigma * sigma)) * cospi(2.0 * fc * t);
+}
+
+__device__ __forceinline__ double hann_d(double d, double z, double F) {
+    const double a = z / (2.0 * F);
+    if (!(a > 0.0) || fabs(d) > a) return 0.0;
+    return 0.5 * (1.0 + cospi(d / a));
+}
+
+// Linear-interpolation read at fractional index u of the unit echo whose
+// arrival time is tau.
+__device__ __forceinline__ double unit_echo_read(const Setup64& s, double u, double tau) {
+    const double q = floor(u);
+    const double f = u - q;
+    double s0 = 0.0, s1 = 0.0;
+    if (q >= 0.0 && q < (double)s.T) s0 = pulse_d(s.t0 + q / s.fs - tau, s.fc, s.sigma);
+    if (q + 1.0 >= 0.0 && q + 1.0 < (double)s.T) s1 = pulse_d(s.t0 + (q + 1.0) / s.fs - tau, s.fc, s.sigma);
+    return (1.0 - f) * s0 + f * s1;
+}
+
+__device__ __forceinline__ double arrival(const Setup64& s, int a, double x, double z, double xn) {
+    const double dx = x - xn;
+    return (x * s.sin_a[a] + z * s.cos_a[a]) / s.c + sqrt(dx * dx + z * z) / s.c;
+}
+
+// DAS at pixel (0, z) of a unit scatterer at (0, zs).
+__device__ double unit_das(const Setup64& s, double z, double zs) {
+    double acc = 0.0;
+    for (int a = 0; a < s.A; ++a) {
+        for (int n = 0; n < s.C; ++n) {
+            const double xn = s.x_first + (double)n * s.pitch;
+            const double w = hann_d(-xn, z, s.fnumber);
+            if (w == 0.0) continue;
+            const double u = (arrival(s, a, 0.0, z, xn) - s.t0) * s.fs;
+            acc += w * unit_echo_read(s, u, arrival(s, a, 0.0, zs, xn));
+        }
+    }
+    return acc;
+}
+
+// Fixed-delay line F_r[unit echo at zs](z): delays and weights of depth zr.
+__device__ double fixed_delay(const Setup64& s, double z, double zr, double zs) {
+    double acc = 0.0;
+    for (int a = 0; a < s.A; ++a) {
+        const double t_centre = z * s.cos_a[a] / s.c + z / s.c;
+        for (int n = 0; n < s.C; ++n) {
+            const double xn = s.x_first + (double)n * s.pitch;
+            const double w = hann_d(-xn, zr, s.fnumber);
+            if (w == 0.0) continue;
+            const double D = (zr - sqrt(xn * xn + zr * zr)) / s.c;  // eqn:delay
+            const double u = (t_centre - D - s.t0) * s.fs;
+            acc += w * unit_echo_read(s, u, arrival(s, a, 0.0, zs, xn));
+        }
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------ exact mode ----
+__global__ __launch_bounds__(256) void exact_kernel(const Setup64 s, int32_t Z, int32_t K, double z0, double dz,
+                                                    float* __restrict__ kb, float* __restrict__ theta) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)Z * K) return;
+    const int i = (int)(idx / K);
+    const int t = (int)(idx % K);
+    const int h = (K - 1) / 2;
+    const double zi = z0 + (double)i * dz;
+    kb[idx] = (float)unit_das(s, zi + (double)(t - h) * dz, zi);
+    if (theta && t == 0) theta[i] = 1.0f;
+}
+
+// ------------------------------------------------------------ paper mode ----
+constexpr int PAPER_THREADS = 256;
+constexpr int FINE_MAX = 1024;  // max fine-axis length 2 Qf + 1 (DFT length <= 2 FINE_MAX)
+
+__device__ double block_sum(double v, double* red) {
+    // wave reduction then LDS across the 4 waves
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < PAPER_THREADS / 64; ++w) tot += red[w];
+        red[0] = tot;
+    }
+    __syncthreads();
+    tot = red[0];
+    __syncthreads();
+    return tot;
+}
+
+// One workgroup per distinct reference row.  Outputs h_ref[u][K] and
+// width[u] (metres).
+__global__ __launch_bounds__(PAPER_THREADS) void paper_ref_kernel(const Setup64 s, int32_t K, double z0, double dz,
+                                                                  int32_t Qf, const int32_t* __restrict__ refs,
+                                                                  double* __restrict__ h_ref,
+                                                                  double* __restrict__ width) {
+    __shared__ double b[FINE_MAX];
+    __shared__ double env[FINE_MAX];
+    __shared__ double Xr[FINE_MAX + 1];  // bins 0 .. N/2, N <= 2 FINE_MAX
+    __shared__ double Xi[FINE_MAX + 1];
+    const int u = blockIdx.x;
+    const int r = refs[u];
+    const double zr = z0 + (double)r * dz;
+    const int h = (K - 1) / 2;
+    const double dzf = s.c / (2.0 * s.fs);
+    const int L = 2 * Qf + 1;
+    int N = 1;
+    while (N < 2 * L) N *= 2;
+
+    for (int t = threadIdx.x; t < K; t += PAPER_THREADS)
+        h_ref[(size_t)u * K + t] = fixed_delay(s, zr + (double)(t - h) * dz, zr, zr);
+    for (int q = threadIdx.x; q < L; q += PAPER_THREADS) b[q] = unit_das(s, zr + (double)(q - Qf) * dzf, zr);
+    __syncthreads();
+    // DFT of the zero-padded sequence at k = 0 .. N/2 (the analytic signal
+    // keeps only those bins: weight 1 at 0 and N/2, 2 in between)
+    for (int k = threadIdx.x; k <= N / 2; k += PAPER_THREADS) {
+        double re = 0.0, im = 0.0;
+        for (int n = 0; n < L; ++n) {
+            const int m = (int)(((int64_t)k * n) & (N - 1));
+            double sn, cs;
+            sincospi(2.0 * (double)m / (double)N, &sn, &cs);
+            re += b[n] * cs;
+            im -= b[n] * sn;
+        }
+        const double wgt = (k == 0 || k == N / 2) ? 1.0 : 2.0;
+        Xr[k] = wgt * re;
+        Xi[k] = wgt * im;
+    }
+    __syncthreads();
+    for (int n = threadIdx.x; n < L; n += PAPER_THREADS) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k <= N / 2; ++k) {
+            const int m = (int)(((int64_t)k * n) & (N - 1));
+            double sn, cs;
+            sincospi(2.0 * (double)m / (double)N, &sn, &cs);
+            re += Xr[k] * cs - Xi[k] * sn;
+            im += Xr[k] * sn + Xi[k] * cs;
+        }
+        env[n] = sqrt(re * re + im * im) / (double)N;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // FWHM: first maximum, walk outwards to the half-maximum crossings
+        int p = 0;
+        for (int n = 1; n < L; ++n)
+            if (env[n] > env[p]) p = n;
+        const double half = 0.5 * env[p];
+        int lo = p;
+        while (lo > 0 && env[lo - 1] >= half) --lo;
+        const double xl = (lo == 0) ? 0.0 : (lo - 1) + (half - env[lo - 1]) / (env[lo] - env[lo - 1]);
+        int hi = p;
+        while (hi < L - 1 && env[hi + 1] >= half) ++hi;
+        const double xr = (hi == L - 1) ? (double)(L - 1) : hi + (env[hi] - half) / (env[hi] - env[hi + 1]);
+        width[u] = (xr - xl) * dzf;
+    }
+}
+
+// One workgroup per row i.
+__global__ __launch_bounds__(PAPER_THREADS) void paper_row_kernel(const Setup64 s, int32_t K, double z0, double dz,
+                                                                  const int32_t* __restrict__ ref_of_row,
+                                                                  const int32_t* __restrict__ refs,
+                                                                  const double* __restrict__ h_ref,
+                                                                  const double* __restrict__ width,
+                                                                  float* __restrict__ kb, float* __restrict__ theta) {
+    __shared__ double red[PAPER_THREADS / 64];
+    const int i = blockIdx.x;
+    const int u = ref_of_row[i];
+    const double zr = z0 + (double)refs[u] * dz;
+    const double zi = z0 + (double)i * dz;
+    const double dzf = s.c / (2.0 * s.fs);
+    // width <= 2 Qf dzf by construction; the clamp only guards non-finite input
+    const double wq = 0.5 * width[u] / dzf;
+    const int qmax = (wq >= 0.0 && wq <= (double)FINE_MAX) ? (int)floor(wq) : 0;
+    double ab = 0.0, aa = 0.0;
+    for (int q = -qmax + (int)threadIdx.x; q <= qmax; q += PAPER_THREADS) {
+        const double z = zi + (double)q * dzf;
+        const double a = fixed_delay(s, z, zr, zi);
+        const double bb = unit_das(s, z, zi);
+        ab += a * bb;
+        aa += a * a;
+    }
+    ab = block_sum(ab, red);
+    aa = block_sum(aa, red);
+    const double th = (aa > 0.0) ? ab / aa : 0.0;
+    for (int t = threadIdx.x; t < K; t += PAPER_THREADS) kb[(size_t)i * K + t] = (float)(th * h_ref[(size_t)u * K + t]);
+    if (theta && threadIdx.x == 0) theta[i] = (float)th;
+}
+
+// ------------------------------------------------------------ RF synthesis ----
+__global__ __launch_bounds__(256) void simulate_kernel(const Setup64 s, const double* __restrict__ scat, int32_t S,
+                                                       int32_t width, double* __restrict__ acc) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;  // over (a, n, scatterer)
+    const int64_t total = (int64_t)s.A * s.C * S;
+    if (idx >= total) return;
+    const int sc = (int)(idx % S);
+    const int n = (int)((idx / S) % s.C);
+    const int a = (int)(idx / ((int64_t)S * s.C));
+    const double x = scat[3 * (int64_t)sc], z = scat[3 * (int64_t)sc + 1], amp = scat[3 * (int64_t)sc + 2];
+    const double xn = s.x_first + (double)n * s.pitch;
+    const double tau = arrival(s, a, x, z, xn);
+    const double half = 4.0 * s.sigma;
+    const int64_t k_lo = (int64_t)ceil((tau - half - s.t0) * s.fs);
+    double* row = acc + ((int64_t)a * s.C + n) * s.T;
+    for (int w = 0; w < width; ++w) {
+        const int64_t k = k_lo + w;
+        if (k < 0 || k >= s.T) continue;
+        const double v = amp * pulse_d(s.t0 + (double)k / s.fs - tau, s.fc, s.sigma);
+        if (v != 0.0) unsafeAtomicAdd(row + k, v);
+    }
+}
+
+__global__ __launch_bounds__(256) void round_kernel(const double* __restrict__ acc, int64_t n, float* __restrict__ rf) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) rf[idx] = (float)acc[idx];
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(double* __restrict__ p, int64_t n) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) p[idx] = 0.0;
+}
+
+static int32_t fill_setup(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx, int32_t T, Setup64& s) {
+    if (tx->n_angles > BK_MAX_ANGLES) return fail(TIDAS_EUNSUPPORTED, "at most 32 plane-wave angles");
+    s.C = array->n_elem;
+    s.T = T;
+    s.A = tx->n_angles;
+    s.pitch = array->pitch;
+    s.c = array->c;
+    s.fs = tx->fs;
+    s.t0 = tx->t0;
+    s.fc = tx->fc;
+    s.sigma = (tx->cycles / tx->fc) / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    s.fnumber = rx ? rx->fnumber : 1.0;
+    s.x_first = -0.5 * (double)(s.C - 1) * s.pitch;
+    for (int a = 0; a < s.A; ++a) {
+        s.sin_a[a] = std::sin(tx->angles[a]);
+        s.cos_a[a] = std::cos(tx->angles[a]);
+    }
+    return TIDAS_OK;
+}
+
+}  // namespace tidas
+
+using namespace tidas;
+
+extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
+                                       const tidas_grid* grid, int32_t n_samples, int32_t K, int32_t mode,
+                                       const int32_t* ref_row, float* kernels, float* theta, void* stream) {
+    int32_t st;
+    if ((st = validate_array(array)) || (st = validate_tx(tx, true)) || (st = validate_rx(rx)) ||
+        (st = validate_grid(grid)))
+        return st;
+    if (!kernels) return fail(TIDAS_EINVAL, "tidas_build_kernels: null kernels pointer");
+    if (n_samples < 2) return fail(TIDAS_EINVAL, "tidas_build_kernels: n_samples must be >= 2");
+    if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_build_kernels: K must be odd and >= 1");
+    if (mode != TIDAS_MODE_EXACT && mode != TIDAS_MODE_PAPER)
+        return fail(TIDAS_EINVAL, "tidas_build_kernels: mode must be 0 (exact) or 1 (paper)");
+    if ((void*)kernels == (void*)theta) return fail(TIDAS_EINVAL, "tidas_build_kernels: theta aliases kernels");
+    const int Z = grid->nz;
+    if (ref_row)
+        for (int i = 0; i < Z; ++i)
+            if (ref_row[i] < 0 || ref_row[i] >= Z)
+                return fail(TIDAS_EINVAL, "tidas_build_kernels: ref_row entries must lie in [0, nz)");
+    Setup64 s;
+    if ((st = fill_setup(array, tx, rx, n_samples, s))) return st;
+    hipStream_t strm = (hipStream_t)stream;
+
+    if (mode == TIDAS_MODE_EXACT) {
+        const int64_t n = (int64_t)Z * K;
+        hipLaunchKernelGGL(exact_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, s, Z, K, grid->z0,
+                           grid->dz, kernels, theta);
+        return check_launch("tidas_build_kernels(exact)");
+    }
+
+    // paper mode: distinct reference rows and the row -> reference map
+    const int Qf = (int)std::ceil(8.0 * s.sigma * s.fs);
+    if (2 * Qf + 1 > FINE_MAX) return fail(TIDAS_EUNSUPPORTED, "tidas_build_kernels: pulse too long for the fine axis");
+    std::vector<int32_t> refs;
+    std::vector<int32_t> map(Z);
+    {
+        std::vector<int32_t> slot(Z, -1);
+        for (int i = 0; i < Z; ++i) {
+            const int r = ref_row ? ref_row[i] : i;
+            if (slot[r] < 0) {
+                slot[r] = (int32_t)refs.size();
+                refs.push_back(r);
+            }
+            map[i] = slot[r];
+        }
+    }
+    const size_t nref = refs.size();
+    const size_t bytes = sizeof(int32_t) * (Z + nref) + sizeof(double) * (nref * (K + 1)) + 16;
+    void* buf = nullptr;
+    if ((st = check_hip(hipMallocAsync(&buf, bytes, strm), "tidas_build_kernels: temporary buffer"))) return st;
+    double* h_ref = (double*)buf;
+    double* width = h_ref + nref * K;
+    int32_t* d_map = (int32_t*)(width + nref);
+    int32_t* d_refs = d_map + Z;
+    std::vector<int32_t> host_ints(map);
+    host_ints.insert(host_ints.end(), refs.begin(), refs.end());
+    st = check_hip(hipMemcpyAsync(d_map, host_ints.data(), sizeof(int32_t) * host_ints.size(), hipMemcpyHostToDevice, strm),
+                   "tidas_build_kernels: upload");
+    if (!st) {
+        hipLaunchKernelGGL(paper_ref_kernel, dim3((unsigned)nref), dim3(PAPER_THREADS), 0, strm, s, K, grid->z0,
+                           grid->dz, Qf, d_refs, h_ref, width);
+        st = check_launch("tidas_build_kernels(paper, reference rows)");
+    }
+    if (!st) {
+        hipLaunchKernelGGL(paper_row_kernel, dim3((unsigned)Z), dim3(PAPER_THREADS), 0, strm, s, K, grid->z0, grid->dz,
+                           d_map, d_refs, h_ref, width, kernels, theta);
+        st = check_launch("tidas_build_kernels(paper, rows)");
+    }
+    // the host staging vector must outlive the copy: order it before returning
+    hipError_t e = hipStreamSynchronize(strm);
+    hipError_t e2 = hipFreeAsync(buf, strm);
+    if (!st) st = check_hip(e, "tidas_build_kernels: synchronize");
+    if (!st) st = check_hip(e2, "tidas_build_kernels: free");
+    return st;
+}
+
+extern "C" int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* tx, const double* scat, int32_t n_scat,
+                                     int32_t n_samples, float* rf, void* stream) {
+    int32_t st;
+    if ((st = validate_array(array)) || (st = validate_tx(tx, true))) return st;
+    if (!rf || (n_scat > 0 && !scat)) return fail(TIDAS_EINVAL, "tidas_simulate_rf: null pointer");
+    if (n_samples < 1) return fail(TIDAS_EINVAL, "tidas_simulate_rf: n_samples must be >= 1");
+    if (n_scat < 0) return fail(TIDAS_EINVAL, "tidas_simulate_rf: n_scat must be >= 0");
+    Setup64 s;
+    if ((st = fill_setup(array, tx, nullptr, n_samples, s))) return st;
+    hipStream_t strm = (hipStream_t)stream;
+    const int64_t n = (int64_t)s.A * s.C * s.T;
+    void* buf = nullptr;
+    if ((st = check_hip(hipMallocAsync(&buf, sizeof(double) * n, strm), "tidas_simulate_rf: accumulator"))) return st;
+    double* acc = (double*)buf;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, acc, n);
+    st = check_launch("tidas_simulate_rf(zero)");
+    const int width = (int)std::ceil(2.0 * 4.0 * s.sigma * s.fs) + 2;
+    const int64_t work = (int64_t)s.A * s.C * n_scat;
+    if (!st && work > 0) {
+        hipLaunchKernelGGL(simulate_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, strm, s, scat, n_scat,
+                           width, acc);
+        st = check_launch("tidas_simulate_rf(accumulate)");
+    }
+    if (!st) {
+        hipLaunchKernelGGL(round_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, acc, n, rf);
+        st = check_launch("tidas_simulate_rf(round)");
+    }
+    hipError_t e = hipFreeAsync(buf, strm);
+    if (!st) st = check_hip(e, "tidas_simulate_rf: free");
+    return st;
+}

@@ -1,0 +1,79 @@
+// Shared host/device helpers of the tiDAS library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/tidas.h"
+
+namespace tidas {
+
+// ---------------------------------------------------------------- status ----
+void set_error(const std::string& msg);
+
+inline int32_t fail(int32_t code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+inline int32_t check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TIDAS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return TIDAS_OK;
+}
+
+inline int32_t check_hip(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return fail(TIDAS_ENOMEM, std::string(what) + ": out of device memory");
+    if (e != hipSuccess) return fail(TIDAS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return TIDAS_OK;
+}
+
+// Validation of the descriptors shared by several entry points.  Returns
+// TIDAS_OK or TIDAS_EINVAL with a message.
+int32_t validate_array(const tidas_array* a);
+int32_t validate_tx(const tidas_tx* t, bool need_pulse);
+int32_t validate_rx(const tidas_rx* r);
+int32_t validate_grid(const tidas_grid* g);
+
+inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// -------------------------------------------------------------- device ----
+// Hann apodization 0.5 (1 + cos(pi t)) = cos^2(pi t / 2) for |t| <= 1, from
+// the Taylor series of cos(pi t / 2) in u = t^2 through u^6 (truncation
+// error below 7e-9 on [0, 1]), evaluated by Horner's rule.
+__device__ __forceinline__ float hann_weight(float t) {
+    const float u = t * t;
+    constexpr double h = 1.5707963267948966;  // pi / 2
+    constexpr double h2 = h * h;
+    constexpr double c1 = -h2 / 2.0;
+    constexpr double c2 = h2 * h2 / 24.0;
+    constexpr double c3 = -h2 * h2 * h2 / 720.0;
+    constexpr double c4 = h2 * h2 * h2 * h2 / 40320.0;
+    constexpr double c5 = -h2 * h2 * h2 * h2 * h2 / 3628800.0;
+    constexpr double c6 = h2 * h2 * h2 * h2 * h2 * h2 / 479001600.0;
+    float q = (float)c6;
+    q = fmaf(q, u, (float)c5);
+    q = fmaf(q, u, (float)c4);
+    q = fmaf(q, u, (float)c3);
+    q = fmaf(q, u, (float)c2);
+    q = fmaf(q, u, (float)c1);
+    q = fmaf(q, u, 1.0f);
+    return q * q;
+}
+
+// Raw buffer resource over `bytes` bytes starting at `base`: loads outside
+// [0, bytes) return 0, which is exactly the zero-outside-the-record rule of
+// the channel read (negative offsets wrap to huge unsigned values and miss).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float buffer_load_f32(__amdgpu_buffer_rsrc_t r, int32_t byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
+}  // namespace tidas

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/tidas.h declares, and rejects invalid arguments before touching the
+device (these calls never reach a kernel launch)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_15464_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tidas.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libtidas.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_lists_the_entry_points():
+    names = declared_functions()
+    for n in ("das_beamform", "tidas_build_kernels", "tidas_apply", "tidas_adjoint", "tidas_simulate_rf",
+              "tidas_last_error", "tidas_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    # and the binding knows every declared entry point
+    assert set(declared_functions()) <= set(_lib.exported_symbols())
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.tidas_version()
+
+
+def _geom():
+    arr = _lib.make_array(64, 0.3e-3, 1540.0)
+    tx = _lib.make_tx([0.0], 40e6, 0.0, 5e6, 2.0)
+    rx = _lib.make_rx(1.5)
+    g = _lib.make_grid(256, 128, 7.8e-5, 1.56e-4, -9.4e-3, 1.48e-4)
+    return arr, tx, rx, g
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+NUL = ctypes.c_void_p(0)
+
+
+@pytest.mark.parametrize("args", [
+    (NUL, 65, FAKE, 1, 16, 16, FAKE),       # null kernels
+    (FAKE, 64, FAKE, 1, 16, 16, ctypes.c_void_p(0x2000)),  # even K
+    (FAKE, 0, FAKE, 1, 16, 16, ctypes.c_void_p(0x2000)),   # K = 0
+    (FAKE, 5, FAKE, 0, 16, 16, ctypes.c_void_p(0x2000)),   # B = 0
+    (FAKE, 5, FAKE, 1, 0, 16, ctypes.c_void_p(0x2000)),    # Z = 0
+    (FAKE, 5, FAKE, 1, 16, -3, ctypes.c_void_p(0x2000)),   # X < 0
+    (FAKE, 5, ctypes.c_void_p(0x2000), 1, 16, 16, ctypes.c_void_p(0x2000)),  # output aliases input
+])
+def test_conv_rejects_invalid_arguments(lib, args):
+    for fn in (lib.tidas_apply, lib.tidas_adjoint):
+        assert fn(*args, NUL) == _lib.TIDAS_EINVAL
+        assert lib.tidas_last_error()
+
+
+def test_das_rejects_invalid_arguments(lib):
+    arr, tx, rx, g = _geom()
+    ok = (ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g))
+    assert lib.das_beamform(*ok, NUL, 2048, 1, FAKE, NUL) == _lib.TIDAS_EINVAL
+    assert lib.das_beamform(*ok, FAKE, 1, 1, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EINVAL
+    assert lib.das_beamform(*ok, FAKE, 2048, 0, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EINVAL
+    assert lib.das_beamform(*ok, FAKE, 2048, 1, FAKE, NUL) == _lib.TIDAS_EINVAL  # aliasing
+    for bad in (_lib.make_array(0, 0.3e-3, 1540.0), _lib.make_array(64, -1.0, 1540.0),
+                _lib.make_array(64, 0.3e-3, 0.0)):
+        assert lib.das_beamform(ctypes.byref(bad), *ok[1:], FAKE, 2048, 1, ctypes.c_void_p(0x2000), NUL) == -1
+    for badtx in (_lib.make_tx([], 40e6, 0, 5e6, 2), _lib.make_tx([0.0], 0.0, 0, 5e6, 2),
+                  _lib.make_tx([2.0], 40e6, 0, 5e6, 2)):
+        assert lib.das_beamform(ok[0], ctypes.byref(badtx), *ok[2:], FAKE, 2048, 1, ctypes.c_void_p(0x2000),
+                                NUL) == -1
+    badrx = _lib.make_rx(0.0)
+    assert lib.das_beamform(ok[0], ok[1], ctypes.byref(badrx), ok[3], FAKE, 2048, 1, ctypes.c_void_p(0x2000),
+                            NUL) == -1
+    for badg in (_lib.make_grid(0, 4, 0, 1e-4, 0, 1e-4), _lib.make_grid(4, 4, 0, -1e-4, 0, 1e-4),
+                 _lib.make_grid(4, 4, float("nan"), 1e-4, 0, 1e-4)):
+        assert lib.das_beamform(*ok[:3], ctypes.byref(badg), FAKE, 2048, 1, ctypes.c_void_p(0x2000), NUL) == -1
+    tx33 = _lib.make_tx([0.0] * 33, 40e6, 0, 5e6, 2)
+    assert lib.das_beamform(ok[0], ctypes.byref(tx33), *ok[2:], FAKE, 2048, 1, ctypes.c_void_p(0x2000),
+                            NUL) == _lib.TIDAS_EUNSUPPORTED
+
+
+def test_build_kernels_rejects_invalid_arguments(lib):
+    arr, tx, rx, g = _geom()
+    ok = (ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g))
+    assert lib.tidas_build_kernels(*ok, 2048, 65, 0, None, NUL, NUL, NUL) == -1       # null kernels
+    assert lib.tidas_build_kernels(*ok, 2048, 64, 0, None, FAKE, NUL, NUL) == -1      # even K
+    assert lib.tidas_build_kernels(*ok, 2048, 65, 7, None, FAKE, NUL, NUL) == -1      # bad mode
+    assert lib.tidas_build_kernels(*ok, 1, 65, 0, None, FAKE, NUL, NUL) == -1         # n_samples
+    assert lib.tidas_build_kernels(*ok, 2048, 65, 0, None, FAKE, FAKE, NUL) == -1     # theta aliases
+    bad_ref = (ctypes.c_int32 * 256)(*([0] * 255 + [256]))
+    assert lib.tidas_build_kernels(*ok, 2048, 65, 1, bad_ref, FAKE, NUL, NUL) == -1   # ref out of range
+    nopulse = _lib.make_tx([0.0], 40e6, 0, 0.0, 2)
+    assert lib.tidas_build_kernels(ok[0], ctypes.byref(nopulse), *ok[2:], 2048, 65, 0, None, FAKE, NUL, NUL) == -1
+
+
+def test_simulate_rejects_invalid_arguments(lib):
+    arr, tx, _, _ = _geom()
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), NUL, 5, 2048, FAKE, NUL) == -1
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, -1, 2048, FAKE, NUL) == -1
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 0, FAKE, NUL) == -1
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 2048, NUL, NUL) == -1

@@ -1,0 +1,241 @@
+"""GPU parity: every entry point of the C ABI against the FP64 CPU oracle on
+identical seeded inputs.  Floating-point bar: relative L2 <= 1e-5 (float32
+device arithmetic vs float64 oracle), plus element-wise checks where the
+structure gives them."""
+import functools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2507_15464_amd as td  # noqa: E402
+from oracle import das as o_das, kernels as o_k, simulate as o_sim, tidas as o_t  # noqa: E402
+from workloads import config, generators  # noqa: E402
+from workloads.configs import CYSTS, N_SCATTERERS  # noqa: E402
+from tests.helpers import axes, das_kw, oracle_kw, sim_kw  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def g(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+CONV_SHAPES = [(1, 1, 1, 1), (1, 1, 7, 3), (2, 5, 3, 129), (1, 17, 65, 7), (3, 100, 70, 65), (1, 64, 64, 1),
+               (2, 129, 130, 129), (1, 300, 1, 33), (1, 63, 129, 65), (1, 1024, 256, 129)]
+
+
+@pytest.mark.parametrize("B,Z,X,K", CONV_SHAPES)
+def test_apply_matches_oracle(dev, B, Z, X, K):
+    kb = generators.normal((Z, K), seed=Z * 7 + K).astype(np.float32)
+    R = generators.normal((B, Z, X), seed=X * 3 + B).astype(np.float32)
+    y = td.apply(g(kb, dev), g(R, dev)).cpu().numpy()
+    ref = o_t.apply(kb, R)
+    assert rel(y, ref) <= RTOL
+    assert np.max(np.abs(y - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("B,Z,X,K", CONV_SHAPES)
+def test_adjoint_matches_oracle(dev, B, Z, X, K):
+    kb = generators.normal((Z, K), seed=Z * 5 + K).astype(np.float32)
+    Yb = generators.normal((B, Z, X), seed=X * 11 + B).astype(np.float32)
+    r = td.adjoint(g(kb, dev), g(Yb, dev)).cpu().numpy()
+    ref = o_t.adjoint(kb, Yb)
+    assert rel(r, ref) <= RTOL
+    assert np.max(np.abs(r - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_adjoint_dot_product_on_device(dev):
+    Z, X, K, B = 700, 190, 129, 2
+    kb = g(generators.normal((Z, K), seed=1), dev)
+    R = g(generators.normal((B, Z, X), seed=2), dev)
+    Y = g(generators.normal((B, Z, X), seed=3), dev)
+    lhs = float((td.apply(kb, R).double() * Y.double()).sum())
+    rhs = float((R.double() * td.adjoint(kb, Y).double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + 1.0) * 10
+
+
+def test_apply_impulse_reads_kernel_rows(dev):
+    Z, X, K = 200, 64, 65
+    kb = generators.normal((Z, K), seed=9).astype(np.float32)
+    R = np.zeros((1, Z, X), np.float32)
+    src = [(0, 0), (5, 10), (100, 33), (199, 63)]
+    for s, j in src:
+        R[0, s, j] = 1.0
+    y = td.apply(g(kb, dev), g(R, dev)).cpu().numpy()[0]
+    h = K // 2
+    for s, j in src:
+        for i in range(max(0, s - h), min(Z, s + h + 1)):
+            assert y[i, j] == kb[i, i - s + h]
+
+
+# ----------------------------------------------------------------- DAS ----
+@functools.lru_cache(maxsize=None)
+def rf_config(k, n_scat=None, seed=0):
+    s = config(k)
+    if k == 2:
+        n = n_scat or N_SCATTERERS[2]
+        x, z, a, _ = generators.speckle_with_cysts(n, s.field_w, s.field_d, CYSTS["n"], CYSTS["r_lo"], CYSTS["r_hi"],
+                                                   seed=seed)
+    else:
+        x, z, a = generators.point_scatterers(n_scat or N_SCATTERERS.get(k, 20), s.field_w, s.field_d, seed=seed)
+    return o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **sim_kw(s)))
+
+
+def das_case(dev, s, rf):
+    xs, zs = axes(s)
+    img = td.das_beamform(g(rf, dev), s).cpu().numpy()
+    ref = o_das.das(rf, xs, zs, **das_kw(s))
+    return img, ref
+
+
+def test_das_config1_full(dev):
+    s = config(1)
+    img, ref = das_case(dev, s, rf_config(1))
+    assert img.shape == (256, 128)
+    assert rel(img, ref) <= RTOL
+
+
+def test_das_config2_full_speckle(dev):
+    s = config(2)
+    img, ref = das_case(dev, s, rf_config(2))
+    assert img.shape == (1024, 256)
+    assert rel(img, ref) <= RTOL
+
+
+def test_das_compound_11_angles(dev):
+    s = config(3).with_grid(300, 257)
+    x, z, a = generators.point_scatterers(20, s.field_w, s.field_d, seed=4)
+    rf = o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **sim_kw(s)))
+    img, ref = das_case(dev, s, rf)
+    assert rel(img, ref) <= RTOL
+
+
+def test_das_three_angles_generic_path(dev):
+    s = config(1).replace(angles=(-0.1, 0.02, 0.15)).with_grid(130, 70)
+    x, z, a = generators.point_scatterers(20, s.field_w, s.field_d, seed=5)
+    rf = o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **sim_kw(s)))
+    img, ref = das_case(dev, s, rf)
+    assert rel(img, ref) <= RTOL
+
+
+@pytest.mark.parametrize("B", [3, 9])
+def test_das_batched_frames(dev, B):
+    s = config(1).with_grid(100, 50)
+    frames = []
+    for b in range(B):
+        x, z, a = generators.point_scatterers(20, s.field_w, s.field_d, seed=100 + b)
+        frames.append(o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **sim_kw(s))))
+    rf = np.stack(frames)
+    img = td.das_beamform(g(rf, dev), s).cpu().numpy()
+    xs, zs = axes(s)
+    for b in range(B):
+        assert rel(img[b], o_das.das(rf[b], xs, zs, **das_kw(s))) <= RTOL
+
+
+def test_das_edge_grids(dev):
+    base = config(1).replace(n_samples=1500)
+    x, z, a = generators.point_scatterers(20, base.field_w, 25e-3, seed=6)
+    rf = o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **sim_kw(base)))
+    # rows at and above the probe face (empty aperture -> 0), a single column, a single row
+    for s in (base.replace(nz=70, nx=3, z0=-2e-3, dz=0.1e-3, x0=-1e-3, dx=1e-3),
+              base.replace(nz=65, nx=1, z0=5e-3, dz=0.2e-3, x0=0.0, dx=1e-4),
+              base.replace(nz=1, nx=77, z0=11e-3, dz=1e-4, x0=-9e-3, dx=0.23e-3)):
+        img, ref = das_case(dev, s, rf)
+        assert rel(img, ref) <= RTOL
+        zs = s.z0 + np.arange(s.nz) * s.dz
+        assert np.all(img[zs <= 0] == 0)
+
+
+def test_das_single_element(dev):
+    s = config(1).replace(n_elem=1, n_samples=900).with_grid(90, 5)
+    rf = generators.normal((1, 1, 900), seed=7).astype(np.float32)
+    img, ref = das_case(dev, s, rf)
+    assert rel(img, ref) <= RTOL
+
+
+# ------------------------------------------------------------ kernels ----
+@pytest.mark.parametrize("k", [1, 2])
+def test_build_exact_kernels_full(dev, k):
+    s = config(k)
+    kb = td.build_kernels(s, mode="exact").cpu().numpy()
+    _, zs = axes(s)
+    ref = o_k.exact_kernels(zs, s.dz, s.K, **oracle_kw(s))
+    assert kb.shape == (s.nz, s.K)
+    assert rel(kb, ref) <= RTOL
+    assert np.max(np.abs(kb - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+def test_build_exact_kernels_compound(dev):
+    s = config(3).with_grid(64, 8)
+    kb = td.build_kernels(s, K=65, mode="exact").cpu().numpy()
+    _, zs = axes(s)
+    ref = o_k.exact_kernels(zs, s.dz, 65, **oracle_kw(s))
+    assert rel(kb, ref) <= RTOL
+
+
+def test_build_paper_kernels_own_rows_config1(dev):
+    s = config(1)
+    kb, th = td.build_kernels(s, mode="paper", with_theta=True)
+    _, zs = axes(s)
+    ref, th_ref, _ = o_k.paper_kernels(zs, s.dz, s.K, **oracle_kw(s))
+    assert rel(kb.cpu().numpy(), ref) <= RTOL
+    assert np.max(np.abs(th.cpu().numpy() - th_ref)) <= 1e-6 * np.max(np.abs(th_ref))
+
+
+def test_build_paper_kernels_single_reference_25mm(dev):
+    """One delay curve for the whole line (the paper's line experiments use a
+    reference depth of 25 mm)."""
+    s = config(1)
+    _, zs = axes(s)
+    r = int(np.argmin(np.abs(zs - 25e-3)))
+    kb, th = td.build_kernels(s, mode="paper", ref_row=[r] * s.nz, with_theta=True)
+    rows = np.arange(0, s.nz, 5)
+    z_rows = np.concatenate([[zs[r]], zs[rows]])
+    ref, th_ref, _ = o_k.paper_kernels(z_rows, s.dz, s.K, ref_rows=np.zeros(z_rows.size, int), **oracle_kw(s))
+    assert rel(kb.cpu().numpy()[rows], ref[1:]) <= RTOL
+    assert np.max(np.abs(th.cpu().numpy()[rows] - th_ref[1:])) <= 1e-6 * np.max(np.abs(th_ref))
+
+
+def test_build_paper_kernels_config2_sampled_rows(dev):
+    s = config(2)
+    _, zs = axes(s)
+    kb, th = td.build_kernels(s, mode="paper", with_theta=True)
+    rows = np.arange(3, s.nz, 61)
+    ref, th_ref, _ = o_k.paper_kernels(zs[rows], s.dz, s.K, **oracle_kw(s))
+    assert rel(kb.cpu().numpy()[rows], ref) <= RTOL
+    assert np.max(np.abs(th.cpu().numpy()[rows] - th_ref)) <= 1e-6 * np.max(np.abs(th_ref))
+
+
+# ----------------------------------------------------------- synthesis ----
+def test_simulate_rf_matches_oracle(dev):
+    for s, n in ((config(1), 20), (config(3).replace(n_samples=1500), 7)):
+        x, z, a = generators.point_scatterers(n, s.field_w, 28e-3, seed=12)
+        scat = torch.tensor(np.stack([x, z, a], 1), dtype=torch.float64, device=dev)
+        rf = td.simulate_rf(s, scat).cpu().numpy()
+        ref = o_sim.simulate_rf(x, z, a, **sim_kw(s))
+        assert rel(rf, ref) <= 1e-6
+        assert np.max(np.abs(rf - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+def test_simulate_rf_no_scatterers_is_zero(dev):
+    s = config(1)
+    rf = td.simulate_rf(s, torch.zeros((0, 3), dtype=torch.float64, device=dev))
+    assert float(rf.abs().max()) == 0.0
