@@ -1,0 +1,258 @@
+"""Benchmark: frames/s of tiDAS vs DAS at 256 x 1024 px with 128 channels.
+
+Workload (clinical-size plain case): 128-element linear array, 0.3 mm pitch,
+7.5 MHz 2-cycle pulse, 50 MHz sampling, 4096 float32 samples per channel,
+one 0-degree plane wave; per frame a speckle phantom of 100k scatterers in
+38 x 60 mm with 5 anechoic cysts (per-frame seed); image 256 lateral x 1024
+depth; tiDAS with 129-tap exact-mode row kernels.
+
+One step = one batch of B frames through the hot path: the tiDAS line model
+(tidas_apply) over the B reflectivity maps, and exact DAS (das_beamform) over
+the B RF records of the same phantoms.  Inputs are resident in HBM before the
+timed regions.  ``value`` is tiDAS frames/s; DAS frames/s and the speedup are
+reported beside it, each with its rel-L2 against the FP64 oracle.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks, and the derived fp32 FMA ceiling of this build's VALU code
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_TFLOPS = 157.3                                     # dense fp32 matrix peak
+FP32_VALU_NOPACK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6: 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz
+# DAS work per active (pixel, element, angle) term, counted from the definition:
+# receive distance 4 (sub, mul, add, sqrt), index 2, interpolation 3, apodization 3
+# (scale, cos, add), weighted accumulate 2
+DAS_FLOPS_PER_TERM = 14
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=64, help="frames per step")
+    ap.add_argument("--no-parity", action="store_true", help="skip the oracle parity check")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
+    ap.add_argument("--only", choices=["tidas", "das"], default=None, help="time one op only (profiling)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, run one plain device copy of the input batch (known byte count) so "
+                         "hardware byte counters can be calibrated against it")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tidas_mfma_kernel_256x1024_k129_b64_traffic.json")
+
+
+def measured_traffic(batch):
+    """HBM bytes per launch of the line-model kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a plain copy of known
+    size), or None when the kernel source changed since they were taken or the
+    batch differs from the profiled one."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if sha != rec.get("source_sha256") or batch != 64:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2507_15464_amd as td
+    from workloads import config, generators
+    from workloads.configs import CYSTS, N_SCATTERERS
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = config(2)
+    B, K = args.batch, s.K
+    Z, X = s.nz, s.nx
+
+    # ---- inputs (untimed): per-frame phantoms, RF synthesised on the GPU, snapped reflectivity maps
+    t_in = time.perf_counter()
+    rf = torch.empty((B, 1, s.n_elem, s.n_samples), device=dev, dtype=torch.float32)
+    R = torch.empty((B, Z, X), device=dev, dtype=torch.float32)
+    phantoms = []
+    for b in range(B):
+        x, z, a, _ = generators.speckle_with_cysts(N_SCATTERERS[2], s.field_w, s.field_d, CYSTS["n"], CYSTS["r_lo"],
+                                                   CYSTS["r_hi"], seed=b)
+        phantoms.append((x, z, a))
+        scat = torch.tensor(np.stack([x, z, a], 1), dtype=torch.float64, device=dev)
+        td.simulate_rf(s, scat, out=rf[b])
+        i, j, _, _ = generators.snap_to_grid(x, z, s.x0, s.dx, X, s.z0, s.dz, Z)
+        R[b] = torch.from_numpy(generators.reflectivity_map(i, j, a, Z, X).astype(np.float32))
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t_in:.1f}s")
+
+    t_b = time.perf_counter()
+    kb = td.build_kernels(s, mode="exact")
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t_b
+    Y = torch.empty_like(R)
+    img = torch.empty((B, Z, X), device=dev, dtype=torch.float32)
+
+    def run_tidas():
+        td.apply(kb, R, out=Y)
+
+    def run_das():
+        td.das_beamform(rf, s, out=img)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / args.steps, wall
+
+    res = {}
+    if args.only in (None, "tidas"):
+        res["tidas"] = timed(run_tidas)
+        log(f"tidas: {res['tidas'][0]:.4f} ms/step ({B} frames)")
+    if args.only in (None, "das"):
+        res["das"] = timed(run_das)
+        log(f"das: {res['das'][0]:.4f} ms/step ({B} frames)")
+    if args.copy_probe:
+        Y.copy_(R)  # reads and writes exactly B*Z*X*4 bytes each
+        torch.cuda.synchronize()
+        log(f"copy probe: {R.numel() * 4} bytes read, {R.numel() * 4} bytes written")
+    if args.only is not None:
+        return
+
+    tid_ms, das_ms = res["tidas"][0], res["das"][0]
+    flops = 2.0 * K * Z * X * B                       # one FMA per tap per output pixel
+    hbm_bytes = (8.0 * Z * X) * B + 4.0 * Z * K       # read R + write Y per frame, kernel bank once
+    achieved_tflops = flops / (tid_ms * 1e-3) / 1e12
+    achieved_gbs = hbm_bytes / (tid_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "frames/s tiDAS vs DAS (256x1024 px, 128 ch) at stated rel-L2 vs FP64 oracle",
+        "value": B / (tid_ms * 1e-3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tid_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded 100k-scatterer speckle phantoms with cysts, RF synthesised on the GPU)",
+        "config": {"workload": "tiDAS vs DAS, 128-ch plane wave, 256x1024 px image, 129-tap exact row kernels",
+                   "frames_per_step": B, "channels": s.n_elem, "samples": s.n_samples, "image": [Z, X], "taps": K},
+        "tidas": {"frames_per_s": B / (tid_ms * 1e-3), "mpixel_per_s": B * Z * X / (tid_ms * 1e-3) / 1e6,
+                  "ms_per_step": tid_ms, "hbm_gbs_algorithmic": achieved_gbs},
+        "das": {"frames_per_s": B / (das_ms * 1e-3), "mpixel_per_s": B * Z * X / (das_ms * 1e-3) / 1e6,
+                "ms_per_step": das_ms},
+        "tidas_speedup_vs_das": das_ms / tid_ms,
+        "kernel_build_s": build_s,
+        "roofline": {"bound": "mfma", "achieved": achieved_tflops, "peak": FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_MFMA_TFLOPS, "traffic": measured_traffic(B),
+                     "kernel": "tidas_mfma_kernel<false>", "flops_per_launch": flops,
+                     "hbm_frac_algorithmic": achieved_gbs / HBM_PEAK_GBS},
+    }
+
+    # DAS terms per frame: (pixel, element) pairs inside the Hann aperture, times angles
+    xs_h = s.x0 + np.arange(X) * s.dx
+    zs_h = s.z0 + np.arange(Z) * s.dz
+    xn_h = (np.arange(s.n_elem) - (s.n_elem - 1) / 2.0) * s.pitch
+    half_ap = zs_h[:, None] / (2.0 * s.fnumber)
+    terms = sum(int(np.count_nonzero(np.abs(xs_h[None, :] - x_n) <= half_ap)) for x_n in xn_h) * len(s.angles)
+    das_tflops = DAS_FLOPS_PER_TERM * terms * B / (das_ms * 1e-3) / 1e12
+    out["das"]["terms_per_frame"] = terms
+    out["das_roofline"] = {"bound": "alu", "achieved": das_tflops, "peak": FP32_VALU_NOPACK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": das_tflops / FP32_VALU_NOPACK_TFLOPS,
+                           "kernel": "das_kernel<4,1>", "flops_per_term": DAS_FLOPS_PER_TERM}
+
+    # ---- tiDAS-vs-DAS approximation error on frame 0 (snapped phantom, both on the GPU)
+    x, z, a = phantoms[0]
+    i, j, zs_, xs_ = generators.snap_to_grid(x, z, s.x0, s.dx, X, s.z0, s.dz, Z)
+    scat = torch.tensor(np.stack([xs_, zs_, a], 1), dtype=torch.float64, device=dev)
+    rf_snap = td.simulate_rf(s, scat)
+    d_snap = td.das_beamform(rf_snap, s)
+    y_snap = td.apply(kb, R[0])
+    out["approx_rel_l2_2d"] = float(torch.linalg.norm(y_snap - d_snap) / torch.linalg.norm(d_snap))
+
+    if not (args.no_parity and args.no_cpu_baseline):
+        # host-side inputs for the oracle, built from the seeded generators and
+        # the oracle itself (never from device results)
+        from oracle import das as o_das, kernels as o_k, simulate as o_sim, tidas as o_t
+        t_p = time.perf_counter()
+        xs = s.x0 + np.arange(X) * s.dx
+        zs = s.z0 + np.arange(Z) * s.dz
+        okw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, fc=s.fc, sigma=s.sigma,
+                   n_samples=s.n_samples, angles=list(s.angles))
+        dkw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, angles=list(s.angles), fnumber=s.fnumber)
+        kb_o = o_k.exact_kernels(zs, s.dz, K, fnumber=s.fnumber, **okw)
+        R_host = []
+        for b in range(4):
+            xb, zb, ab = phantoms[b]
+            ib, jb, _, _ = generators.snap_to_grid(xb, zb, s.x0, s.dx, X, s.z0, s.dz, Z)
+            R_host.append(generators.reflectivity_map(ib, jb, ab, Z, X).astype(np.float32))
+        R_host = np.stack(R_host)
+        rf_o = o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **okw))
+        log(f"oracle inputs ready in {time.perf_counter() - t_p:.1f}s")
+
+    if not args.no_parity:
+        t_p = time.perf_counter()
+        kb32 = kb_o.astype(np.float32)
+        y_gpu = td.apply(torch.from_numpy(kb32).to(dev), torch.from_numpy(R_host[:1]).to(dev)).cpu().numpy()
+        y_ref = o_t.apply(kb32, R_host[:1])
+        out["tidas"]["rel_l2_vs_oracle"] = float(np.linalg.norm(y_gpu - y_ref) / np.linalg.norm(y_ref))
+        out["kernel_bank_rel_l2_vs_oracle"] = float(np.linalg.norm(kb.cpu().numpy() - kb_o) / np.linalg.norm(kb_o))
+        d_gpu = td.das_beamform(torch.from_numpy(rf_o).to(dev), s).cpu().numpy()
+        d_ref = o_das.das(rf_o, xs, zs, **dkw)
+        out["das"]["rel_l2_vs_oracle"] = float(np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref))
+        log(f"parity done in {time.perf_counter() - t_p:.1f}s")
+
+    if not args.no_cpu_baseline:
+        Rc = R_host.astype(np.float64)
+        n_fr, t_c = 0, time.perf_counter()
+        while time.perf_counter() - t_c < 12.0:
+            o_t.apply(kb_o, Rc)
+            n_fr += Rc.shape[0]
+        cpu_tidas = n_fr / (time.perf_counter() - t_c)
+        out["cpu_baseline"] = {"value": cpu_tidas, "unit": "frames/s", "cores": 1, "kind": "oracle",
+                               "sample": f"FP64 oracle line model on {n_fr} frames of the workload "
+                                         f"(batches of 4), about 12 s"}
+        n_d, t_c = 0, time.perf_counter()
+        while time.perf_counter() - t_c < 8.0:
+            o_das.das(rf_o, xs, zs, **dkw)
+            n_d += 1
+        out["cpu_baseline_das"] = {"value": n_d / (time.perf_counter() - t_c), "unit": "frames/s", "cores": 1,
+                                   "kind": "oracle", "sample": f"FP64 oracle DAS on {n_d} frames, about 8 s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -41,6 +41,7 @@ __device__ __forceinline__ int xcd_remap(int L, int n) {
 struct ConvGeom {
     int32_t K, h, B, Z, X;
     int32_t n_rt, n_ct, n_blocks;
+    int32_t vec4;  // input rows may be read as float4 (X % 4 == 0 and 16-byte aligned base)
 };
 
 template <int RZ, int WAVES>
@@ -183,9 +184,183 @@ __global__ __launch_bounds__(WAVES * 64) void tidas_adj_kernel(const ConvGeom g,
     }
 }
 
+// ------------------------------------------------------------------------
+// Matrix-core path.  Over a tile of 32 output rows x 256 columns the line model
+// is a dense product Y_tile = M_tile R_tile with the banded matrix
+// M_tile[r][c] = K[i0 + r][r - c + 2h] (zero off the band) and R_tile the input
+// rows [i0 - h, i0 + 32 + h).  It runs on v_mfma_f32_16x16x4_f32 (exact float32
+// products, float32 accumulation).  Operand layouts of that instruction:
+//   A (16 x 4):  lane l holds A[l % 16][l / 16]
+//   B (4 x 16):  lane l holds B[l / 16][l % 16]
+//   D (16 x 16): register q of lane l holds D[4 (l / 16) + q][l % 16]
+// 8 waves per tile; wave w owns output rows 16 (w / 4) .. +16 and a 64-column
+// quarter of the tile, as four 16 x 16 accumulators ("chains").  Chain c of
+// lane column j covers image column 4 j + c, so one 16-byte load per lane
+// (four consecutive columns of one input row) feeds all four chains, and the
+// four results of an output row are again four consecutive columns (one
+// 16-byte store).  Each wave walks only the band: input rows
+// r0 .. r0 + 15 + K - 1, four per step, (K + 15) / 4 steps.
+// The kernel rows of the tile sit in LDS (direct-to-LDS buffer loads) with 20
+// zeros of padding before tap 0 and a row stride = 1 (mod 32) words, so the two
+// k-groups of a half-wave fall on even and odd banks: no conflicts.  The
+// reflectivity operand is streamed from L2 through a register ring, PD steps
+// ahead.  The adjoint is the same product with the transposed band
+// M^T[s][i] = K[i][i - s + h], staged as KT[s][t] = K[s + h - t][K - 1 - t].
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int MF_TZ = 32;        // output rows per tile (two 16-row M-blocks)
+constexpr int MF_TN = 256;       // columns per tile (four 64-column quarters)
+constexpr int MF_THREADS = 512;  // 8 waves
+constexpr int MF_LPAD = 20;      // zero taps before tap 0 in the LDS kernel rows
+
+__host__ __device__ constexpr int mf_nsteps(int K) { return (K + 15 + 3) / 4; }
+__host__ __device__ constexpr int mf_kstride(int K) {
+    // >= K + 15 + MF_LPAD (largest tap index read) + 1 and = 1 (mod 32)
+    return ((K + 15 + MF_LPAD + 1 + 31 - 1) / 32) * 32 + 1;
+}
+// rounded up to whole 64-entry chunks: the last direct-to-LDS wave load writes a full chunk
+__host__ __device__ constexpr size_t mf_lds_bytes(int K) {
+    return (size_t)((MF_TZ * mf_kstride(K) + 63) / 64) * 64 * sizeof(float);
+}
+
+template <bool ADJ>
+__global__ __launch_bounds__(MF_THREADS) void tidas_mfma_kernel(const ConvGeom g, const float* __restrict__ Kb,
+                                                                const float* __restrict__ In,
+                                                                float* __restrict__ Out) {
+    extern __shared__ float smem[];
+    const int K = g.K, h = g.h, Z = g.Z, X = g.X;
+    const int KS = mf_kstride(K);
+    float* kt = smem;  // [MF_TZ][KS]
+
+    const int lg = xcd_remap(blockIdx.x, g.n_blocks);
+    const int rt_i = lg % g.n_rt;
+    const int ct = (lg / g.n_rt) % g.n_ct;
+    const int b = lg / (g.n_rt * g.n_ct);
+    const int i0 = rt_i * MF_TZ, j0 = ct * MF_TN;
+    const float* Ib = In + (size_t)b * Z * X;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr uint32_t OOB = 0x80000000u;
+
+    // kernel tile, flat [MF_TZ][KS]: one dword wave load = 64 consecutive entries;
+    // entries outside the taps (or past the image) read 0 through the range check
+    {
+        const auto rs_k = make_rsrc(Kb, (uint32_t)((size_t)Z * K * sizeof(float)));
+        const int nchunks = (MF_TZ * KS + 63) / 64;
+        for (int ch = wave; ch < nchunks; ch += MF_THREADS / 64) {
+            const int e0 = ch * 64;
+            const int e = e0 + lane;
+            const int r = e / KS;
+            const int t = e - r * KS - MF_LPAD;
+            const int row = i0 + r;
+            uint32_t off = OOB;
+            if (r < MF_TZ && t >= 0 && t < K && row < Z) {
+                if (!ADJ) {
+                    off = (uint32_t)(((size_t)row * K + t) * 4);
+                } else {
+                    const int src = row + h - t;
+                    if (src >= 0 && src < Z) off = (uint32_t)(((size_t)src * K + (K - 1 - t)) * 4);
+                }
+            }
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_k, (__attribute__((address_space(3))) void*)(kt + e0), 4, off,
+                                                     0, 0, 0);
+        }
+    }
+
+    const int r0 = (wave >> 2) * 16;         // M-block rows within the tile
+    const int n0 = (wave & 3) * 64;          // column quarter
+    const int li = lane & 15, lk = lane >> 4;
+    const int nsteps = mf_nsteps(K);
+    // B: step s reads input row i0 - h + r0 + 4 s + lk, columns j0 + n0 + 4 li .. +3.
+    // int32 byte offsets from the frame base: rows above the image are negative
+    // (huge unsigned), rows below are past the end: both read 0.
+    const auto rs_in = make_rsrc(Ib, (uint32_t)((size_t)Z * X * sizeof(float)));
+    const int col = j0 + n0 + 4 * li;
+    const int step_bytes = 4 * X * 4;
+    const int off0 = ((i0 - h + r0 + lk) * X + col) * 4;
+    constexpr int PD = 8;
+    floatx4 q[PD];
+#pragma unroll
+    for (int u = 0; u < PD; ++u)
+        q[u] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs_in, off0 + u * step_bytes, 0, 0));
+    __builtin_amdgcn_s_waitcnt(0);  // drain the LDS-direct loads
+    __syncthreads();
+
+    // A: step s, lane (li, lk): M[r0 + li][r0 + 4 s + lk] -> tap t = li - lk - 4 s + 2h
+    const float* a_ptr = kt + (r0 + li) * KS + (li - lk + 2 * h + MF_LPAD);
+    floatx4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int last = nsteps - 1;
+    float a_cur = a_ptr[0];
+    int s0 = 0;
+    for (; s0 + PD <= nsteps; s0 += PD) {
+#pragma unroll
+        for (int u = 0; u < PD; ++u) {
+            const int st = s0 + u;
+            const float a_nxt = a_ptr[-4 * min(st + 1, last)];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur, q[u][c], acc[c], 0, 0, 0);
+            q[u] = __builtin_bit_cast(floatx4,
+                                      __builtin_amdgcn_raw_buffer_load_b128(rs_in, off0 + (st + PD) * step_bytes, 0, 0));
+            a_cur = a_nxt;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+        const int st = s0 + u;
+        if (st < nsteps) {
+            const float a = a_ptr[-4 * st];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, q[u][c], acc[c], 0, 0, 0);
+        }
+    }
+
+    float* Ob = Out + (size_t)b * Z * X;
+    if (col < X) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int row = i0 + r0 + 4 * lk + qq;
+            if (row < Z)
+                *reinterpret_cast<float4*>(Ob + (size_t)row * X + col) =
+                    make_float4(acc[0][qq], acc[1][qq], acc[2][qq], acc[3][qq]);
+        }
+    }
+}
+
+static bool mfma_fits(int K, int Z, int X) {
+    // LDS tile fits; rows are float4-addressable; every int32 byte offset,
+    // including rows prefetched past the band (< K + 4 PD + 64 rows beyond
+    // the image), stays below 2^31
+    return mf_lds_bytes(K) <= 160 * 1024 && (X % 4) == 0 && ((int64_t)Z + 2 * K + 256) * X * 4 < INT32_MAX;
+}
+
+static void launch_mfma(bool adj, const float* kernels, int32_t K, const float* in, int32_t B, int32_t Z, int32_t X,
+                        float* out, hipStream_t stream) {
+    ConvGeom g;
+    g.K = K;
+    g.h = (K - 1) / 2;
+    g.B = B;
+    g.Z = Z;
+    g.X = X;
+    g.n_rt = (Z + MF_TZ - 1) / MF_TZ;
+    g.n_ct = (X + MF_TN - 1) / MF_TN;
+    g.n_blocks = g.n_rt * g.n_ct * B;
+    g.vec4 = 1;
+    const size_t lds = mf_lds_bytes(K);
+    if (adj)
+        hipLaunchKernelGGL(tidas_mfma_kernel<true>, dim3(g.n_blocks), dim3(MF_THREADS), lds, stream, g, kernels, in, out);
+    else
+        hipLaunchKernelGGL(tidas_mfma_kernel<false>, dim3(g.n_blocks), dim3(MF_THREADS), lds, stream, g, kernels, in,
+                           out);
+}
+
 constexpr int CONV_RZ = 16;
 constexpr int CONV_WAVES = 4;
 constexpr size_t LDS_LIMIT = 160 * 1024;
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 static int32_t conv_common(const char* name, const float* kernels, int32_t K, const float* in, int32_t B,
                            int32_t Z, int32_t X, float* out, ConvGeom& g) {
@@ -218,6 +393,11 @@ extern "C" int32_t tidas_apply(const float* kernels, int32_t K, const float* ref
     ConvGeom g;
     int32_t st = conv_common("tidas_apply", kernels, K, refl, B, Z, X, image, g);
     if (st) return st;
+    if (mfma_fits(K, Z, X) && aligned16(refl) && aligned16(image) &&
+        (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX) {
+        launch_mfma(false, kernels, K, refl, B, Z, X, image, (hipStream_t)stream);
+        return check_launch("tidas_apply");
+    }
     const size_t lds = (size_t)(CONV_RZ + CONV_RZ * CONV_WAVES + K - 1) * 64 * sizeof(float);
     hipLaunchKernelGGL((tidas_fwd_kernel<CONV_RZ, CONV_WAVES>), dim3(g.n_blocks), dim3(CONV_WAVES * 64), lds,
                        (hipStream_t)stream, g, kernels, refl, image);
@@ -229,6 +409,11 @@ extern "C" int32_t tidas_adjoint(const float* kernels, int32_t K, const float* i
     ConvGeom g;
     int32_t st = conv_common("tidas_adjoint", kernels, K, image_bar, B, Z, X, refl_bar, g);
     if (st) return st;
+    if (mfma_fits(K, Z, X) && aligned16(image_bar) && aligned16(refl_bar) &&
+        (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX) {
+        launch_mfma(true, kernels, K, image_bar, B, Z, X, refl_bar, (hipStream_t)stream);
+        return check_launch("tidas_adjoint");
+    }
     const size_t lds = (size_t)(CONV_RZ * CONV_WAVES + K - 1) * 64 * sizeof(float);
     hipLaunchKernelGGL((tidas_adj_kernel<CONV_RZ, CONV_WAVES>), dim3(g.n_blocks), dim3(CONV_WAVES * 64), lds,
                        (hipStream_t)stream, g, kernels, image_bar, refl_bar);

@@ -39,7 +39,8 @@ def g(x, dev):
 
 
 CONV_SHAPES = [(1, 1, 1, 1), (1, 1, 7, 3), (2, 5, 3, 129), (1, 17, 65, 7), (3, 100, 70, 65), (1, 64, 64, 1),
-               (2, 129, 130, 129), (1, 300, 1, 33), (1, 63, 129, 65), (1, 1024, 256, 129)]
+               (2, 129, 130, 129), (1, 300, 1, 33), (1, 63, 129, 65), (1, 1024, 256, 129),
+               (1, 300, 70, 257), (1, 600, 40, 513), (2, 97, 131, 129), (1, 64, 128, 145)]
 
 
 @pytest.mark.parametrize("B,Z,X,K", CONV_SHAPES)
