@@ -13,6 +13,9 @@
  *   tidas_adjoint        its transpose
  *   tidas_simulate_rf    Born-approximation RF synthesis (Sec. 2, eqn:SRX),
  *                        the input generator of the path
+ *   tidas_apply_ex, tidas_adjoint_ex, tidas_deconvolve, tidas_operator_norm_sq
+ *                        fused forms and the Tikhonov deconvolution built on
+ *                        the line model (abstract; Sec. 1; Sec. 4)
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -139,7 +142,8 @@ int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_r
  * kernels DEV [nz][K]; theta DEV [nz] or NULL (exact mode writes 1).
  * ref_row HOST [nz] with 0 <= ref_row[i] < nz, or NULL.  K odd, >= 1.
  * Paper mode allocates and frees a small temporary device buffer,
- * stream-ordered, and may return TIDAS_ENOMEM.
+ * stream-ordered (TIDAS_ENOMEM possible), uploads the row -> reference map,
+ * and returns only after the stream has drained (synchronous).
  */
 int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                             const tidas_grid* grid, int32_t n_samples, int32_t K, int32_t mode,
@@ -162,6 +166,43 @@ int32_t tidas_apply(const float* kernels, int32_t K, const float* refl, int32_t 
  */
 int32_t tidas_adjoint(const float* kernels, int32_t K, const float* image_bar, int32_t B,
                       int32_t Z, int32_t X, float* refl_bar, void* stream);
+
+/*
+ * Fused forms of the line model and its adjoint (same operators as above):
+ *   image    = alpha * A(refl)       + beta * base
+ *   refl_bar = alpha * A^T(image_bar) + beta * base
+ * base is DEV [B][Z][X] or NULL (then beta is ignored).  base may alias the
+ * output (each element is read before it is written) but neither may alias
+ * the operator's input.  alpha, beta finite.  These carry the residual and
+ * the update of gradient-based reconstruction through the line model without
+ * extra passes over memory.
+ */
+int32_t tidas_apply_ex(const float* kernels, int32_t K, const float* refl, int32_t B, int32_t Z, int32_t X,
+                       float alpha, float beta, const float* base, float* image, void* stream);
+int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float* image_bar, int32_t B, int32_t Z, int32_t X,
+                         float alpha, float beta, const float* base, float* refl_bar, void* stream);
+
+/*
+ * Tikhonov-regularised deconvolution through the line model (the paper
+ * proposes the convolutional form as a foundation for deconvolution: abstract,
+ * Sec. 1, Sec. 4).  Minimises 1/2 ||A r - y||^2 + lam/2 ||r||^2 by `iters`
+ * gradient steps from r_0 = 0:
+ *   r_{t+1} = r_t - eta (A^T (A r_t - y) + lam r_t),
+ * two fused launches per step.  y, r, work DEV [B][Z][X], pairwise distinct;
+ * r receives the result, work is scratch.  lam >= 0, eta > 0 (for
+ * convergence eta < 2 / (||A||^2 + lam); see tidas_operator_norm_sq).
+ */
+int32_t tidas_deconvolve(const float* kernels, int32_t K, const float* y, int32_t B, int32_t Z, int32_t X,
+                         float lam, float eta, int32_t iters, float* r, float* work, void* stream);
+
+/*
+ * Largest eigenvalue of A^T A for the Z x Z column operator of the line model
+ * (= squared largest singular value), by `iters` steps of power iteration
+ * from the all-ones vector.  work DEV with room for 3 Z + 4 floats; *out is a
+ * HOST double, written after the call synchronises the stream.
+ */
+int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32_t Z, int32_t iters, float* work, double* out,
+                               void* stream);
 
 /*
  * Born-approximation RF synthesis, Sec. 2 eqn:SRX with linear superposition:

@@ -52,3 +52,18 @@ def closed_form(K, y, lam):
     lhs = M.T @ M + lam * np.eye(Z)
     y = np.asarray(y, np.float64)
     return np.linalg.solve(lhs, M.T @ y)
+
+
+def gradient_descent_matrix(M, y, lam, eta, iters, record_at=()):
+    """The same iteration with the operator given as its explicit column
+    matrix M (``tidas.matrix``): A r = M @ r per column.  Returns the final
+    iterate and a dict {t: r_t} for t in ``record_at``."""
+    M = np.asarray(M, np.float64)
+    y = np.asarray(y, np.float64)
+    r = np.zeros_like(y)
+    rec = {0: r.copy()} if 0 in record_at else {}
+    for t in range(1, int(iters) + 1):
+        r = r - eta * (M.T @ (M @ r - y) + lam * r)
+        if t in record_at:
+            rec[t] = r.copy()
+    return r, rec

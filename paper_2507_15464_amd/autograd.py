@@ -1,0 +1,101 @@
+"""torch.autograd integration and Tikhonov deconvolution through the line model.
+
+``TiDASFunction``: forward = tidas_apply, backward = tidas_adjoint (the exact
+transpose), so any loss built on the line model's output back-propagates to
+the reflectivity map through the library's own kernels.  The kernel bank is
+treated as a constant (no gradient).
+
+``deconvolve``: the library's native gradient loop for
+1/2 ||A r - y||^2 + lam/2 ||r||^2 (two fused launches per step).
+``operator_norm_sq``: largest eigenvalue of A^T A by power iteration on the
+device, from which a safe step size 1 / (||A||^2 + lam) follows.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from .api import _check_tensor, _ptr, _stream, adjoint, apply
+
+__all__ = ["TiDASFunction", "tidas", "apply_ex", "adjoint_ex", "deconvolve", "operator_norm_sq", "step_size"]
+
+
+class TiDASFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, refl, kernels):
+        ctx.save_for_backward(kernels)
+        return apply(kernels, refl.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (kernels,) = ctx.saved_tensors
+        return adjoint(kernels, grad_out.contiguous()), None
+
+
+def tidas(refl, kernels):
+    """Differentiable line model: image = A(refl)."""
+    return TiDASFunction.apply(refl, kernels)
+
+
+def _ex(fn, kernels, x, alpha, beta, base, out):
+    lib = _lib.load()
+    _check_tensor(kernels, "kernels")
+    _check_tensor(x, "input")
+    x3 = x.unsqueeze(0) if x.dim() == 2 else x
+    B, Z, X = x3.shape
+    if kernels.dim() != 2 or kernels.shape[0] != Z:
+        raise ValueError("kernels must be [Z][K] with the input's Z")
+    if base is not None:
+        _check_tensor(base, "base")
+        if base.numel() != x3.numel():
+            raise ValueError("base must have the input's shape")
+    if out is None:
+        out = torch.empty_like(x3)
+    _check_tensor(out, "out")
+    _lib.check(getattr(lib, fn)(_ptr(kernels), kernels.shape[1], _ptr(x3), B, Z, X, ctypes.c_float(alpha),
+                                ctypes.c_float(beta), _ptr(base), _ptr(out), _stream()))
+    return out.view(x.shape)
+
+
+def apply_ex(kernels, refl, alpha=1.0, beta=0.0, base=None, out=None):
+    """out = alpha * A(refl) + beta * base (base may be ``out`` itself)."""
+    return _ex("tidas_apply_ex", kernels, refl, alpha, beta, base, out)
+
+
+def adjoint_ex(kernels, image_bar, alpha=1.0, beta=0.0, base=None, out=None):
+    """out = alpha * A^T(image_bar) + beta * base (base may be ``out`` itself)."""
+    return _ex("tidas_adjoint_ex", kernels, image_bar, alpha, beta, base, out)
+
+
+def operator_norm_sq(kernels, iters=100):
+    """Largest eigenvalue of A^T A of the column operator (power iteration on the device)."""
+    lib = _lib.load()
+    _check_tensor(kernels, "kernels")
+    Z, K = kernels.shape
+    work = torch.empty(3 * Z + 4, device=kernels.device, dtype=torch.float32)
+    out = ctypes.c_double(0.0)
+    _lib.check(lib.tidas_operator_norm_sq(_ptr(kernels), K, Z, int(iters), _ptr(work), ctypes.byref(out), _stream()))
+    return out.value
+
+
+def step_size(kernels, lam, iters=100):
+    """eta = 1 / (||A||^2 + lam), the inverse Lipschitz constant of the gradient."""
+    return 1.0 / (operator_norm_sq(kernels, iters) + lam)
+
+
+def deconvolve(kernels, y, lam, eta=None, iters=200, out=None, work=None):
+    """Gradient-descent Tikhonov deconvolution of y [B][Z][X] (or [Z][X]) from r_0 = 0."""
+    lib = _lib.load()
+    _check_tensor(kernels, "kernels")
+    _check_tensor(y, "y")
+    y3 = y.unsqueeze(0) if y.dim() == 2 else y
+    B, Z, X = y3.shape
+    if eta is None:
+        eta = step_size(kernels, lam)
+    r = torch.empty_like(y3) if out is None else out
+    w = torch.empty_like(y3) if work is None else work
+    _check_tensor(r, "out")
+    _check_tensor(w, "work")
+    _lib.check(lib.tidas_deconvolve(_ptr(kernels), kernels.shape[1], _ptr(y3), B, Z, X, ctypes.c_float(lam),
+                                    ctypes.c_float(eta), int(iters), _ptr(r), _ptr(w), _stream()))
+    return r.view(y.shape)

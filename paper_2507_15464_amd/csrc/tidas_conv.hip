@@ -26,6 +26,9 @@
 // Blocks are remapped so that each XCD receives a contiguous range of
 // tiles (consecutive depth tiles of one column strip), which keeps the shared
 // halo rows in that XCD's L2.
+#include <algorithm>
+#include <utility>
+
 #include "common.hpp"
 
 namespace tidas {
@@ -42,12 +45,22 @@ struct ConvGeom {
     int32_t K, h, B, Z, X;
     int32_t n_rt, n_ct, n_blocks;
     int32_t vec4;  // input rows may be read as float4 (X % 4 == 0 and 16-byte aligned base)
+    // epilogue: out = alpha * (operator applied to the input) + beta * base
+    // (base may be null; it may alias out, element for element)
+    float alpha, beta;
+    const float* base;
 };
+
+__device__ __forceinline__ float epilogue(const ConvGeom& g, float acc, size_t idx) {
+    float v = g.alpha * acc;
+    if (g.base) v = fmaf(g.beta, g.base[idx], v);
+    return v;
+}
 
 template <int RZ, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void tidas_fwd_kernel(const ConvGeom g, const float* __restrict__ Kb,
                                                                const float* __restrict__ R,
-                                                               float* __restrict__ Y) {
+                                                               float* Y) {
     constexpr int TZ = RZ * WAVES;
     extern __shared__ float tile[];  // [RZ pad + TZ + K - 1][64]
     const int lg = xcd_remap(blockIdx.x, g.n_blocks);
@@ -116,17 +129,19 @@ __global__ __launch_bounds__(WAVES * 64) void tidas_fwd_kernel(const ConvGeom g,
         }
     }
     if (col_ok) {
-        float* Yb = Y + (size_t)b * Z * X;
 #pragma unroll
         for (int r = 0; r < RZ; ++r)
-            if (wi0 + r < Z) Yb[(size_t)(wi0 + r) * X + j] = acc[r];
+            if (wi0 + r < Z) {
+                const size_t idx = (size_t)b * Z * X + (size_t)(wi0 + r) * X + j;
+                Y[idx] = epilogue(g, acc[r], idx);
+            }
     }
 }
 
 template <int RZ, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void tidas_adj_kernel(const ConvGeom g, const float* __restrict__ Kb,
                                                                const float* __restrict__ Ybar,
-                                                               float* __restrict__ Rbar) {
+                                                               float* Rbar) {
     constexpr int TZ = RZ * WAVES;
     extern __shared__ float tile[];  // [TZ + K - 1][64]
     const int lg = xcd_remap(blockIdx.x, g.n_blocks);
@@ -177,10 +192,12 @@ __global__ __launch_bounds__(WAVES * 64) void tidas_adj_kernel(const ConvGeom g,
         }
     }
     if (col_ok) {
-        float* Rb = Rbar + (size_t)b * Z * X;
 #pragma unroll
         for (int r = 0; r < RZ; ++r)
-            if (wi0 + r < Z) Rb[(size_t)(wi0 + r) * X + j] = acc[r];
+            if (wi0 + r < Z) {
+                const size_t idx = (size_t)b * Z * X + (size_t)(wi0 + r) * X + j;
+                Rbar[idx] = epilogue(g, acc[r], idx);
+            }
     }
 }
 
@@ -226,7 +243,7 @@ __host__ __device__ constexpr size_t mf_lds_bytes(int K) {
 template <bool ADJ>
 __global__ __launch_bounds__(MF_THREADS) void tidas_mfma_kernel(const ConvGeom g, const float* __restrict__ Kb,
                                                                 const float* __restrict__ In,
-                                                                float* __restrict__ Out) {
+                                                                float* Out) {
     extern __shared__ float smem[];
     const int K = g.K, h = g.h, Z = g.Z, X = g.X;
     const int KS = mf_kstride(K);
@@ -317,14 +334,23 @@ __global__ __launch_bounds__(MF_THREADS) void tidas_mfma_kernel(const ConvGeom g
         }
     }
 
-    float* Ob = Out + (size_t)b * Z * X;
     if (col < X) {
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             const int row = i0 + r0 + 4 * lk + qq;
-            if (row < Z)
-                *reinterpret_cast<float4*>(Ob + (size_t)row * X + col) =
-                    make_float4(acc[0][qq], acc[1][qq], acc[2][qq], acc[3][qq]);
+            if (row < Z) {
+                const size_t idx = (size_t)b * Z * X + (size_t)row * X + col;
+                float4 v = make_float4(g.alpha * acc[0][qq], g.alpha * acc[1][qq], g.alpha * acc[2][qq],
+                                       g.alpha * acc[3][qq]);
+                if (g.base) {
+                    const float4 bv = *reinterpret_cast<const float4*>(g.base + idx);
+                    v.x = fmaf(g.beta, bv.x, v.x);
+                    v.y = fmaf(g.beta, bv.y, v.y);
+                    v.z = fmaf(g.beta, bv.z, v.z);
+                    v.w = fmaf(g.beta, bv.w, v.w);
+                }
+                *reinterpret_cast<float4*>(Out + idx) = v;
+            }
         }
     }
 }
@@ -337,7 +363,7 @@ static bool mfma_fits(int K, int Z, int X) {
 }
 
 static void launch_mfma(bool adj, const float* kernels, int32_t K, const float* in, int32_t B, int32_t Z, int32_t X,
-                        float* out, hipStream_t stream) {
+                        float alpha, float beta, const float* base, float* out, hipStream_t stream) {
     ConvGeom g;
     g.K = K;
     g.h = (K - 1) / 2;
@@ -348,6 +374,9 @@ static void launch_mfma(bool adj, const float* kernels, int32_t K, const float* 
     g.n_ct = (X + MF_TN - 1) / MF_TN;
     g.n_blocks = g.n_rt * g.n_ct * B;
     g.vec4 = 1;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.base = base;
     const size_t lds = mf_lds_bytes(K);
     if (adj)
         hipLaunchKernelGGL(tidas_mfma_kernel<true>, dim3(g.n_blocks), dim3(MF_THREADS), lds, stream, g, kernels, in, out);
@@ -362,15 +391,29 @@ constexpr size_t LDS_LIMIT = 160 * 1024;
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-static int32_t conv_common(const char* name, const float* kernels, int32_t K, const float* in, int32_t B,
-                           int32_t Z, int32_t X, float* out, ConvGeom& g) {
+// Validate, pick the matrix-core or the VALU kernel, launch.  Enqueues nothing
+// when it returns TIDAS_EINVAL / TIDAS_EUNSUPPORTED.
+static int32_t conv_launch(bool adj, const char* name, const float* kernels, int32_t K, const float* in, int32_t B,
+                           int32_t Z, int32_t X, float alpha, float beta, const float* base, float* out,
+                           hipStream_t stream) {
     if (!kernels || !in || !out) return fail(TIDAS_EINVAL, std::string(name) + ": null pointer");
     if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, std::string(name) + ": K must be odd and >= 1");
     if (B < 1 || Z < 1 || X < 1) return fail(TIDAS_EINVAL, std::string(name) + ": B, Z, X must be >= 1");
     if ((const void*)in == (const void*)out || (const void*)kernels == (const void*)out)
         return fail(TIDAS_EINVAL, std::string(name) + ": output aliases an input");
-    const size_t lds = (size_t)(CONV_RZ + CONV_RZ * CONV_WAVES + K - 1) * 64 * sizeof(float);
+    if (base && ((const void*)base == (const void*)in || (const void*)base == (const void*)kernels))
+        return fail(TIDAS_EINVAL, std::string(name) + ": base aliases an input");
+    if (!std::isfinite(alpha) || !std::isfinite(beta))
+        return fail(TIDAS_EINVAL, std::string(name) + ": alpha and beta must be finite");
+    const bool use_mfma = mfma_fits(K, Z, X) && aligned16(in) && aligned16(out) && (!base || aligned16(base)) &&
+                          (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX;
+    if (use_mfma) {
+        launch_mfma(adj, kernels, K, in, B, Z, X, alpha, beta, base, out, stream);
+        return check_launch(name);
+    }
+    const size_t lds = (size_t)((adj ? 0 : CONV_RZ) + CONV_RZ * CONV_WAVES + K - 1) * 64 * sizeof(float);
     if (lds > LDS_LIMIT) return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": K too large for the LDS tile");
+    ConvGeom g;
     g.K = K;
     g.h = (K - 1) / 2;
     g.B = B;
@@ -381,7 +424,41 @@ static int32_t conv_common(const char* name, const float* kernels, int32_t K, co
     const int64_t nb = (int64_t)g.n_rt * g.n_ct * B;
     if (nb > INT32_MAX) return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": too many tiles");
     g.n_blocks = (int32_t)nb;
-    return TIDAS_OK;
+    g.vec4 = 0;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.base = base;
+    if (adj)
+        hipLaunchKernelGGL((tidas_adj_kernel<CONV_RZ, CONV_WAVES>), dim3(g.n_blocks), dim3(CONV_WAVES * 64), lds,
+                           stream, g, kernels, in, out);
+    else
+        hipLaunchKernelGGL((tidas_fwd_kernel<CONV_RZ, CONV_WAVES>), dim3(g.n_blocks), dim3(CONV_WAVES * 64), lds,
+                           stream, g, kernels, in, out);
+    return check_launch(name);
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(float* __restrict__ p, int64_t n, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+// Single-workgroup: norm of v (length n), v /= norm, *out_norm = norm.
+__global__ __launch_bounds__(1024) void normalize_kernel(float* __restrict__ v, int32_t n, double* __restrict__ out_norm) {
+    __shared__ double red[16];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) acc += (double)v[i] * (double)v[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += red[w];
+        red[0] = sqrt(t);
+        *out_norm = red[0];
+    }
+    __syncthreads();
+    const double nrm = red[0];
+    const float inv = nrm > 0.0 ? (float)(1.0 / nrm) : 0.0f;
+    for (int i = threadIdx.x; i < n; i += 1024) v[i] *= inv;
 }
 
 }  // namespace tidas
@@ -390,32 +467,81 @@ using namespace tidas;
 
 extern "C" int32_t tidas_apply(const float* kernels, int32_t K, const float* refl, int32_t B, int32_t Z,
                                int32_t X, float* image, void* stream) {
-    ConvGeom g;
-    int32_t st = conv_common("tidas_apply", kernels, K, refl, B, Z, X, image, g);
-    if (st) return st;
-    if (mfma_fits(K, Z, X) && aligned16(refl) && aligned16(image) &&
-        (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX) {
-        launch_mfma(false, kernels, K, refl, B, Z, X, image, (hipStream_t)stream);
-        return check_launch("tidas_apply");
-    }
-    const size_t lds = (size_t)(CONV_RZ + CONV_RZ * CONV_WAVES + K - 1) * 64 * sizeof(float);
-    hipLaunchKernelGGL((tidas_fwd_kernel<CONV_RZ, CONV_WAVES>), dim3(g.n_blocks), dim3(CONV_WAVES * 64), lds,
-                       (hipStream_t)stream, g, kernels, refl, image);
-    return check_launch("tidas_apply");
+    return conv_launch(false, "tidas_apply", kernels, K, refl, B, Z, X, 1.0f, 0.0f, nullptr, image,
+                       (hipStream_t)stream);
 }
 
 extern "C" int32_t tidas_adjoint(const float* kernels, int32_t K, const float* image_bar, int32_t B, int32_t Z,
                                  int32_t X, float* refl_bar, void* stream) {
-    ConvGeom g;
-    int32_t st = conv_common("tidas_adjoint", kernels, K, image_bar, B, Z, X, refl_bar, g);
-    if (st) return st;
-    if (mfma_fits(K, Z, X) && aligned16(image_bar) && aligned16(refl_bar) &&
-        (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX) {
-        launch_mfma(true, kernels, K, image_bar, B, Z, X, refl_bar, (hipStream_t)stream);
-        return check_launch("tidas_adjoint");
+    return conv_launch(true, "tidas_adjoint", kernels, K, image_bar, B, Z, X, 1.0f, 0.0f, nullptr, refl_bar,
+                       (hipStream_t)stream);
+}
+
+extern "C" int32_t tidas_apply_ex(const float* kernels, int32_t K, const float* refl, int32_t B, int32_t Z, int32_t X,
+                                  float alpha, float beta, const float* base, float* image, void* stream) {
+    return conv_launch(false, "tidas_apply_ex", kernels, K, refl, B, Z, X, alpha, beta, base, image,
+                       (hipStream_t)stream);
+}
+
+extern "C" int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float* image_bar, int32_t B, int32_t Z,
+                                    int32_t X, float alpha, float beta, const float* base, float* refl_bar,
+                                    void* stream) {
+    return conv_launch(true, "tidas_adjoint_ex", kernels, K, image_bar, B, Z, X, alpha, beta, base, refl_bar,
+                       (hipStream_t)stream);
+}
+
+extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float* y, int32_t B, int32_t Z, int32_t X,
+                                    float lam, float eta, int32_t iters, float* r, float* work, void* stream) {
+    if (!y || !r || !work || !kernels) return fail(TIDAS_EINVAL, "tidas_deconvolve: null pointer");
+    if (iters < 0) return fail(TIDAS_EINVAL, "tidas_deconvolve: iters must be >= 0");
+    if (!(lam >= 0.0f) || !std::isfinite(lam) || !(eta > 0.0f) || !std::isfinite(eta))
+        return fail(TIDAS_EINVAL, "tidas_deconvolve: need finite lam >= 0 and eta > 0");
+    if (K < 1 || (K % 2) == 0 || B < 1 || Z < 1 || X < 1)
+        return fail(TIDAS_EINVAL, "tidas_deconvolve: K odd >= 1 and B, Z, X >= 1 required");
+    const void* ptrs[4] = {kernels, y, r, work};
+    for (int a = 0; a < 4; ++a)
+        for (int c = a + 1; c < 4; ++c)
+            if (ptrs[a] == ptrs[c]) return fail(TIDAS_EINVAL, "tidas_deconvolve: buffers must be distinct");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)B * Z * X;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s, r, n,
+                       0.0f);
+    int32_t st = check_launch("tidas_deconvolve(zero)");
+    const float decay = 1.0f - eta * lam;
+    for (int it = 0; it < iters && !st; ++it) {
+        // work = A r - y ;  r = -eta A^T work + (1 - eta lam) r
+        st = conv_launch(false, "tidas_deconvolve(residual)", kernels, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
+        if (!st)
+            st = conv_launch(true, "tidas_deconvolve(update)", kernels, K, work, B, Z, X, -eta, decay, r, r, s);
     }
-    const size_t lds = (size_t)(CONV_RZ * CONV_WAVES + K - 1) * 64 * sizeof(float);
-    hipLaunchKernelGGL((tidas_adj_kernel<CONV_RZ, CONV_WAVES>), dim3(g.n_blocks), dim3(CONV_WAVES * 64), lds,
-                       (hipStream_t)stream, g, kernels, image_bar, refl_bar);
-    return check_launch("tidas_adjoint");
+    return st;
+}
+
+extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32_t Z, int32_t iters, float* work,
+                                          double* out, void* stream) {
+    if (!kernels || !work || !out) return fail(TIDAS_EINVAL, "tidas_operator_norm_sq: null pointer");
+    if (K < 1 || (K % 2) == 0 || Z < 1 || iters < 1)
+        return fail(TIDAS_EINVAL, "tidas_operator_norm_sq: K odd >= 1, Z >= 1, iters >= 1 required");
+    hipStream_t s = (hipStream_t)stream;
+    // work layout: v [Z] | Av [Z] | w [Z] | norm (double, 8-byte aligned); v and w swap roles
+    float* v = work;
+    float* av = work + Z;
+    float* w = work + 2 * (size_t)Z;
+    double* nrm = reinterpret_cast<double*>(work + 3 * (size_t)Z + ((3 * (size_t)Z) & 1));
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((Z + 255) / 256, 65536)), dim3(256), 0, s, v,
+                       (int64_t)Z, 1.0f);
+    int32_t st = check_launch("tidas_operator_norm_sq(init)");
+    for (int it = 0; it < iters && !st; ++it) {
+        // v <- A^T A v / ||A^T A v||; the last norm is the largest eigenvalue of A^T A
+        st = conv_launch(false, "tidas_operator_norm_sq", kernels, K, v, 1, Z, 1, 1.0f, 0.0f, nullptr, av, s);
+        if (!st) st = conv_launch(true, "tidas_operator_norm_sq", kernels, K, av, 1, Z, 1, 1.0f, 0.0f, nullptr, w, s);
+        if (!st) {
+            hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w, Z, nrm);
+            st = check_launch("tidas_operator_norm_sq(normalize)");
+        }
+        std::swap(v, w);
+    }
+    if (!st) st = check_hip(hipMemcpyAsync(out, nrm, sizeof(double), hipMemcpyDeviceToHost, s), "norm download");
+    if (!st) st = check_hip(hipStreamSynchronize(s), "tidas_operator_norm_sq: synchronize");
+    return st;
 }

@@ -116,3 +116,36 @@ def test_simulate_rejects_invalid_arguments(lib):
     assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, -1, 2048, FAKE, NUL) == -1
     assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 0, FAKE, NUL) == -1
     assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 2048, NUL, NUL) == -1
+
+
+def test_python_api_refuses_host_tensors():
+    """The product path has no CPU fallback: host tensors are rejected."""
+    torch = pytest.importorskip("torch")
+    import paper_2507_15464_amd as td
+    kb = torch.zeros((8, 3))
+    x = torch.zeros((8, 4))
+    for fn in (td.apply, td.adjoint):
+        with pytest.raises(ValueError):
+            fn(kb, x)
+    with pytest.raises(ValueError):
+        td.apply_ex(kb, x)
+    with pytest.raises(ValueError):
+        td.deconvolve(kb, x, 1e-3, eta=0.1)
+
+
+def test_deconvolve_and_norm_reject_invalid_arguments(lib):
+    ok = ctypes.c_void_p(0x1000)
+    w = ctypes.c_void_p(0x2000)
+    r = ctypes.c_void_p(0x3000)
+    y = ctypes.c_void_p(0x4000)
+    f = ctypes.c_float
+    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.1), 10, r, r, NUL) == -1   # r aliases work
+    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.0), 10, r, w, NUL) == -1   # eta = 0
+    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(-1.0), f(0.1), 10, r, w, NUL) == -1   # lam < 0
+    assert lib.tidas_deconvolve(ok, 64, y, 1, 16, 16, f(1e-3), f(0.1), 10, r, w, NUL) == -1   # even K
+    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.1), -1, r, w, NUL) == -1   # iters < 0
+    out = ctypes.c_double(0)
+    assert lib.tidas_operator_norm_sq(ok, 65, 16, 0, w, ctypes.byref(out), NUL) == -1
+    assert lib.tidas_operator_norm_sq(ok, 65, 16, 10, w, None, NUL) == -1
+    assert lib.tidas_apply_ex(ok, 65, y, 1, 16, 16, f(1.0), f(1.0), y, r, NUL) == -1        # base aliases input
+    assert lib.tidas_adjoint_ex(ok, 65, y, 1, 16, 16, f(float("inf")), f(1.0), None, r, NUL) == -1

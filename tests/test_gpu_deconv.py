@@ -1,0 +1,146 @@
+"""GPU parity of the differentiation path: fused apply/adjoint forms, the
+autograd gradient (FP64 finite differences at 32 x 64 and the explicit
+transpose), and 200 iterations of Tikhonov deconvolution on the 256 x 1024
+workload (oracle iterate vs device iterate)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2507_15464_amd as td  # noqa: E402
+from oracle import deconv as o_dc, kernels as o_k, tidas as o_t  # noqa: E402
+from workloads import config, generators  # noqa: E402
+from workloads.configs import DECONV  # noqa: E402
+from tests.helpers import axes, oracle_kw  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def g(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+@pytest.mark.parametrize("B,Z,X,K", [(2, 100, 64, 65), (1, 77, 33, 17), (3, 1024, 256, 129)])
+@pytest.mark.parametrize("adj", [False, True])
+def test_fused_forms_match_oracle(dev, B, Z, X, K, adj):
+    kb = generators.normal((Z, K), seed=K).astype(np.float32)
+    x = generators.normal((B, Z, X), seed=Z).astype(np.float32)
+    base = generators.normal((B, Z, X), seed=X).astype(np.float32)
+    alpha, beta = -0.37, 0.91
+    op = o_t.adjoint if adj else o_t.apply
+    fn = td.adjoint_ex if adj else td.apply_ex
+    ref = alpha * op(kb, x) + beta * base.astype(np.float64)
+    out = fn(g(kb, dev), g(x, dev), alpha, beta, g(base, dev)).cpu().numpy()
+    assert rel(out, ref) <= RTOL
+    # in place: base is the output itself
+    buf = g(base, dev)
+    fn(g(kb, dev), g(x, dev), alpha, beta, buf, out=buf)
+    assert rel(buf.cpu().numpy(), ref) <= RTOL
+    # no base: plain scaled operator
+    out2 = fn(g(kb, dev), g(x, dev), 2.5, 7.0, None).cpu().numpy()
+    assert rel(out2, 2.5 * op(kb, x)) <= RTOL
+
+
+def grad_case():
+    """32 x 64 map with exact 65-tap kernels of the differentiation workload's
+    geometry (rows from the middle of its depth range)."""
+    s = config(4)
+    _, zs = axes(s)
+    kb = o_k.exact_kernels(zs[480:512], s.dz, 65, **oracle_kw(s)).astype(np.float32)
+    R = generators.normal((32, 64), seed=31).astype(np.float32)
+    y = generators.normal((32, 64), seed=32).astype(np.float32)
+    return kb, R, y
+
+
+def test_autograd_gradient_matches_fp64_finite_differences(dev):
+    kb, R, y = grad_case()
+    r = g(R, dev).requires_grad_(True)
+    yd = g(y, dev)
+    loss = 0.5 * ((td.tidas(r, g(kb, dev)) - yd) ** 2).sum()
+    loss.backward()
+    grad = r.grad.detach().cpu().numpy()
+
+    kb64, R64, y64 = (a.astype(np.float64) for a in (kb, R, y))
+
+    def f(rr):
+        res = o_t.apply(kb64, rr) - y64
+        return 0.5 * np.sum(res * res)
+    eps = 1e-4
+    fd = np.zeros_like(R64)
+    for i in range(32):
+        for j in range(64):
+            e = np.zeros_like(R64)
+            e[i, j] = eps
+            fd[i, j] = (f(R64 + e) - f(R64 - e)) / (2 * eps)
+    assert rel(grad, fd) <= RTOL
+    # and against the explicit transpose of the banded matrix
+    M = o_t.matrix(kb64)
+    assert rel(grad, M.T @ (M @ R64 - y64)) <= RTOL
+
+
+def test_autograd_through_a_chain(dev):
+    """Gradient of a nonlinear loss on top of the line model: only the
+    line-model part runs in the library; compare to the oracle's transpose."""
+    kb, R, y = grad_case()
+    r = g(R, dev).requires_grad_(True)
+    out = td.tidas(r, g(kb, dev))
+    loss = torch.sum(torch.tanh(out) * g(y, dev))
+    loss.backward()
+    kb64, R64, y64 = (a.astype(np.float64) for a in (kb, R, y))
+    u = o_t.apply(kb64, R64)
+    upstream = (1.0 - np.tanh(u) ** 2) * y64
+    assert rel(r.grad.cpu().numpy(), o_t.adjoint(kb64, upstream)) <= 1e-4
+
+
+def deconv_case():
+    s = config(4)
+    _, zs = axes(s)
+    kb = o_k.exact_kernels(zs, s.dz, s.K, **oracle_kw(s)).astype(np.float32)
+    rtrue = generators.spikes(s.nz, s.nx, DECONV["n_spikes"], seed=0)
+    clean = o_t.apply(kb, rtrue)
+    sigma = np.sqrt(np.mean(clean ** 2)) * 10.0 ** (-DECONV["snr_db"] / 20.0)
+    y = (clean + sigma * generators.normal(clean.shape, seed=1)).astype(np.float32)
+    return kb, rtrue, y
+
+
+def test_deconvolution_200_iterations_matches_oracle(dev):
+    kb, rtrue, y = deconv_case()
+    lam = DECONV["lam"]
+    M = o_t.matrix(kb.astype(np.float64))
+    smax = np.linalg.svd(M, compute_uv=False)[0]
+    eta = 1.0 / (smax ** 2 + lam)
+    checkpoints = (1, 10, 50, DECONV["iters"])
+    r_o, rec = o_dc.gradient_descent_matrix(M, y, lam, eta, DECONV["iters"], record_at=checkpoints)
+    kd, yd = g(kb, dev), g(y, dev)
+    for t in checkpoints:
+        r_g = td.deconvolve(kd, yd, lam, eta=eta, iters=t).cpu().numpy()
+        assert rel(r_g, rec[t]) <= RTOL, t
+    # the iterate approaches the closed-form Tikhonov solution and the truth
+    rstar = np.linalg.solve(M.T @ M + lam * np.eye(M.shape[0]), M.T @ y.astype(np.float64))
+    d0 = np.linalg.norm(rstar)
+    assert np.linalg.norm(r_o - rstar) < d0
+    assert rel(r_o, rtrue) < 1.0
+
+
+def test_operator_norm_power_iteration(dev):
+    kb, _, _ = deconv_case()
+    smax2 = np.linalg.svd(o_t.matrix(kb.astype(np.float64)), compute_uv=False)[0] ** 2
+    est = td.operator_norm_sq(g(kb, dev), iters=300)
+    assert est <= smax2 * (1 + 1e-5)
+    assert est >= 0.95 * smax2

@@ -151,3 +151,16 @@ def test_deconvolution_monotone_and_converging_to_closed_form():
     dist = [np.linalg.norm(h - rstar) for h in hist[::50]]
     assert all(b < a for a, b in zip(dist, dist[1:]))
     assert deconv.objective(kb, r, y, lam) >= deconv.objective(kb, rstar, y, lam) - 1e-12
+
+
+def test_matrix_form_gradient_descent_equals_operator_form():
+    Z, X, K = 40, 5, 9
+    kb = generators.normal((Z, K), seed=21) / 4
+    y = generators.normal((Z, X), seed=22)
+    lam = 1e-2
+    eta = deconv.step_size(kb, lam)
+    r_op, hist = deconv.gradient_descent(kb, y, lam, eta, 25, record=True)
+    r_m, rec = deconv.gradient_descent_matrix(tidas.matrix(kb), y, lam, eta, 25, record_at=(1, 7, 25))
+    assert np.max(np.abs(r_op - r_m)) < 1e-12
+    for t in (1, 7):
+        assert np.max(np.abs(hist[t] - rec[t])) < 1e-12
