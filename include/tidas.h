@@ -47,6 +47,7 @@
 #ifndef TIDAS_H
 #define TIDAS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -203,6 +204,51 @@ int32_t tidas_deconvolve(const float* kernels, int32_t K, const float* y, int32_
  */
 int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32_t Z, int32_t iters, float* work, double* out,
                                void* stream);
+
+/*
+ * Ragged batches.  Each frame has its own image grid and buffers; the array,
+ * transmit and receive set-up (and, for the line model, K) are shared.  One
+ * persistent launch covers the tiles of all frames (tiles are dealt to the
+ * 8 XCDs in contiguous chunks so a frame's data stays in one L2).
+ */
+typedef struct tidas_frame {
+    tidas_grid grid;       /* this frame's image grid */
+    const float* rf;       /* DEV [A][C][n_samples]: DAS input (ignored by the line model) */
+    const float* kernels;  /* DEV [nz][K]: line-model kernel bank (ignored by DAS) */
+    const float* in;       /* DEV [nz][nx]: line-model reflectivity (ignored by DAS) */
+    float* out;            /* DEV [nz][nx]: output image */
+} tidas_frame;
+
+/* Launch-shape variants the batch entry points accept (chosen by an autotuner):
+ *   DAS:        variant v -> 4 or 8 waves per workgroup (v & 1), and 2, 4 or 8
+ *               workgroups per compute unit (v >> 1)
+ *   line model: variant v -> prefetch depth 4, 8 or 16 steps (v % 3), and 2 or
+ *               4 workgroups per compute unit (v / 3) */
+#define TIDAS_DAS_BATCH_VARIANTS 6
+#define TIDAS_APPLY_BATCH_VARIANTS 6
+
+/* Device workspace (bytes) a batch of n_frames needs: the frame table. */
+size_t tidas_batch_workspace_bytes(int32_t n_frames);
+
+/*
+ * DAS of a ragged batch: frames[f].out = DAS(frames[f].rf) on frames[f].grid
+ * (definition of das_beamform).  frames HOST [n_frames] (validated, then
+ * copied into `workspace`, DEV, 16-byte aligned, >= tidas_batch_workspace_bytes
+ * bytes; the copy is staged before the call returns).  variant in
+ * [0, TIDAS_DAS_BATCH_VARIANTS).
+ */
+int32_t das_beamform_batch(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx, int32_t n_samples,
+                           const tidas_frame* frames, int32_t n_frames, void* workspace, size_t workspace_bytes,
+                           int32_t variant, void* stream);
+
+/*
+ * Line model of a ragged batch: frames[f].out = A_f(frames[f].in) with the
+ * frame's own [nz][K] bank (definition of tidas_apply).  Workspace as above;
+ * variant in [0, TIDAS_APPLY_BATCH_VARIANTS).  TIDAS_EUNSUPPORTED if a frame
+ * exceeds the tile path's limits (then use tidas_apply per frame).
+ */
+int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames, int32_t K, void* workspace,
+                          size_t workspace_bytes, int32_t variant, void* stream);
 
 /*
  * Born-approximation RF synthesis, Sec. 2 eqn:SRX with linear superposition:

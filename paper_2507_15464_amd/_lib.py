@@ -45,6 +45,15 @@ class Grid(ctypes.Structure):
                 ("dz", ctypes.c_double), ("x0", ctypes.c_double), ("dx", ctypes.c_double)]
 
 
+class Frame(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("rf", ctypes.c_void_p), ("kernels", ctypes.c_void_p), ("in_", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
+
+DAS_BATCH_VARIANTS = 6
+APPLY_BATCH_VARIANTS = 6
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _SIGS = {
@@ -61,6 +70,10 @@ _SIGS = {
     "tidas_adjoint_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_deconvolve": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _I, _P, _P, _P]),
     "tidas_operator_norm_sq": (_I, [_P, _I, _I, _I, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "tidas_batch_workspace_bytes": (ctypes.c_size_t, [_I]),
+    "das_beamform_batch": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), _I,
+                                ctypes.POINTER(Frame), _I, _P, ctypes.c_size_t, _I, _P]),
+    "tidas_apply_batch": (_I, [ctypes.POINTER(Frame), _I, _I, _P, ctypes.c_size_t, _I, _P]),
 }
 
 _lib = None

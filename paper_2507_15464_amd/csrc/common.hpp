@@ -41,6 +41,10 @@ int32_t validate_grid(const tidas_grid* g);
 
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Ragged-batch arguments shared by the DAS and line-model batch entry points.
+int32_t validate_batch(const char* name, const tidas_frame* frames, int32_t n_frames, void* workspace,
+                       size_t workspace_bytes, bool need_rf, bool need_conv);
+
 // -------------------------------------------------------------- device ----
 // Hann apodization 0.5 (1 + cos(pi t)) = cos^2(pi t / 2) for |t| <= 1, from
 // the Taylor series of cos(pi t / 2) in u = t^2 through u^6 (truncation

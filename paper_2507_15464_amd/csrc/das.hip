@@ -18,6 +18,9 @@
 //
 // Each thread can beamform FB frames that share the geometry: delays and
 // apodization are computed once per (pixel, element) and reused.
+#include <algorithm>
+#include <vector>
+
 #include "common.hpp"
 
 namespace tidas {
@@ -25,28 +28,35 @@ namespace tidas {
 constexpr int DAS_MAX_ANGLES = 32;
 
 struct DasArgs {
-    int32_t C, T, A, nz, nx, n_frames;
-    double pitch, fs, t0, fnumber, z0, dz, x0, dx, c;
+    int32_t C, T, A, n_frames;
+    double pitch, fs, t0, fnumber, c;
     double x_first;    // x of element 0
     float kappa;       // fs / c
     double sin_a[DAS_MAX_ANGLES];
     double cos_a[DAS_MAX_ANGLES];
 };
 
+// Grid of one frame (or of every frame of a uniform batch).
+struct DasGrid {
+    int32_t nz, nx;
+    double z0, dz, x0, dx;
+};
+
+// One wave: 64 consecutive depth rows (lanes) starting at row i_base, of image
+// column j (wave-uniform), for FB frames sharing the geometry.  rf points at
+// the first frame's [A][C][T] record, img at its [nz][nx] image; frame f of
+// the group is rf + f * frame_rf, img + f * frame_img.
 template <int FB, int NA>
-__global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const float* __restrict__ rf,
-                                                  float* __restrict__ img) {
+__device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, int i_base, int j, int nfr,
+                                         const float* __restrict__ rf, size_t frame_rf, float* img,
+                                         size_t frame_img) {
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int j = blockIdx.y * 4 + wave;
-    if (j >= p.nx) return;
-    const int i = blockIdx.x * 64 + lane;
-    const int fr0 = blockIdx.z * FB;
+    const int i = i_base + lane;
     const int A = (NA > 0) ? NA : p.A;
 
-    const double xd = p.x0 + (double)j * p.dx;
-    const double zd = p.z0 + (double)min(i, p.nz - 1) * p.dz;
-    const bool active = (i < p.nz) && (zd > 0.0);
+    const double xd = gr.x0 + (double)j * gr.dx;
+    const double zd = gr.z0 + (double)min(i, gr.nz - 1) * gr.dz;
+    const bool active = (i < gr.nz) && (zd > 0.0);
     const float zf = (float)zd;
     const float z2 = (float)(zd * zd);
     const float inv_az = active ? (float)(2.0 * p.fnumber / zd) : 0.0f;
@@ -65,8 +75,8 @@ __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const float* 
     }
 
     // element range covering the widest aperture among this wave's rows
-    const int i_last = min((int)blockIdx.x * 64 + 63, p.nz - 1);
-    const double z_last = p.z0 + (double)i_last * p.dz;
+    const int i_last = min(i_base + 63, gr.nz - 1);
+    const double z_last = gr.z0 + (double)i_last * gr.dz;
     int n_lo = 0, n_hi = -1;
     if (z_last > 0.0) {
         const double a_max = z_last / (2.0 * p.fnumber);
@@ -95,9 +105,9 @@ __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const float* 
                     const int off = (q_a[a] + (int)qf) * 4;
 #pragma unroll
                     for (int f = 0; f < FB; ++f) {
-                        if (fr0 + f < p.n_frames) {
-                            const size_t ch = ((size_t)(fr0 + f) * A + a) * p.C + n;
-                            const auto rs = make_rsrc(rf + ch * p.T, row_bytes);
+                        if (f < nfr) {
+                            const size_t ch = (size_t)a * p.C + n;
+                            const auto rs = make_rsrc(rf + f * frame_rf + ch * p.T, row_bytes);
                             const float s0 = buffer_load_f32(rs, off);
                             const float s1 = buffer_load_f32(rs, off + 4);
                             acc[f] = fmaf(w, fmaf(fr, s1 - s0, s0), acc[f]);
@@ -107,18 +117,115 @@ __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const float* 
             }
         }
     }
-    if (i < p.nz) {
+    if (i < gr.nz) {
 #pragma unroll
         for (int f = 0; f < FB; ++f)
-            if (fr0 + f < p.n_frames) img[((size_t)(fr0 + f) * p.nz + i) * p.nx + j] = acc[f];
+            if (f < nfr) img[f * frame_img + (size_t)i * gr.nx + j] = acc[f];
     }
 }
 
 template <int FB, int NA>
-static void launch_das(const DasArgs& p, const float* rf, float* img, hipStream_t s) {
-    dim3 grid((p.nz + 63) / 64, (p.nx + 3) / 4, (p.n_frames + FB - 1) / FB);
-    hipLaunchKernelGGL((das_kernel<FB, NA>), grid, dim3(256), 0, s, p, rf, img);
+__global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid gr, const float* __restrict__ rf,
+                                                  float* __restrict__ img) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = blockIdx.y * 4 + wave;
+    if (j >= gr.nx) return;
+    const int fr0 = blockIdx.z * FB;
+    const size_t frame_rf = (size_t)p.A * p.C * p.T;
+    const size_t frame_img = (size_t)gr.nz * gr.nx;
+    das_wave<FB, NA>(p, gr, blockIdx.x * 64, j, min(FB, p.n_frames - fr0), rf + fr0 * frame_rf, frame_rf,
+                     img + fr0 * frame_img, frame_img);
 }
+
+// ----------------------------------------------------------------- batches ----
+// Ragged batch: every frame has its own grid, RF record and image.  One
+// persistent launch covers the tiles (64 rows x WAVES columns) of all frames.
+// The tile list is cut into 8 contiguous chunks, chunk x served by the
+// workgroups the hardware places on XCD x (block id = x mod 8), so each frame's
+// RF stays in one XCD's L2.  Every workgroup walks its chunk with a fixed
+// stride: the loop always ends.
+struct BatchFrameDev {
+    DasGrid grid;
+    const float* rf;
+    const float* kernels;
+    const float* in;
+    float* out;
+    int64_t tile_start;  // prefix sum of tiles before this frame (op specific)
+};
+
+__device__ __forceinline__ int find_frame(const BatchFrameDev* __restrict__ fr, int n, int64_t t) {
+    int lo = 0, hi = n - 1;  // largest f with tile_start[f] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fr[mid].tile_start <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NA, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void das_batch_kernel(const DasArgs p, const BatchFrameDev* __restrict__ fr,
+                                                               int32_t n_frames, int64_t total) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int nblk = gridDim.x;
+    const int per_xcd = (nblk - x + 7) >> 3;  // workgroups on this XCD
+    const int64_t lo = total * x / 8, hi = total * (x + 1) / 8;
+    for (int64_t t = lo + slot; t < hi; t += per_xcd) {
+        const int f = find_frame(fr, n_frames, t);
+        const DasGrid gr = fr[f].grid;
+        const int64_t local = t - fr[f].tile_start;
+        const int row_tiles = (gr.nz + 63) / 64;
+        const int rt = (int)(local % row_tiles);
+        const int ct = (int)(local / row_tiles);
+        const int j = ct * WAVES + wave;
+        if (j < gr.nx) das_wave<1, NA>(p, gr, rt * 64, j, 1, fr[f].rf, 0, fr[f].out, 0);
+    }
+}
+
+template <int FB, int NA>
+static void launch_das(const DasArgs& p, const DasGrid& gr, const float* rf, float* img, hipStream_t s) {
+    dim3 grid((gr.nz + 63) / 64, (gr.nx + 3) / 4, (p.n_frames + FB - 1) / FB);
+    hipLaunchKernelGGL((das_kernel<FB, NA>), grid, dim3(256), 0, s, p, gr, rf, img);
+}
+
+// Shared validation and argument set-up of the DAS entry points.
+static int32_t das_setup(const char* name, const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
+                         int32_t n_samples, DasArgs& p) {
+    int32_t st;
+    if ((st = validate_array(array)) || (st = validate_tx(tx, false)) || (st = validate_rx(rx))) return st;
+    if (n_samples < 2) return fail(TIDAS_EINVAL, std::string(name) + ": n_samples must be >= 2");
+    if (tx->n_angles > DAS_MAX_ANGLES) return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": at most 32 angles");
+    if ((int64_t)n_samples * 4 > INT32_MAX / 2) return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": record too long");
+    p = DasArgs{};
+    p.C = array->n_elem;
+    p.T = n_samples;
+    p.A = tx->n_angles;
+    p.n_frames = 1;
+    p.pitch = array->pitch;
+    p.c = array->c;
+    p.fs = tx->fs;
+    p.t0 = tx->t0;
+    p.fnumber = rx->fnumber;
+    p.x_first = -0.5 * (double)(p.C - 1) * p.pitch;
+    p.kappa = (float)(p.fs / p.c);
+    for (int a = 0; a < p.A; ++a) {
+        p.sin_a[a] = std::sin(tx->angles[a]);
+        p.cos_a[a] = std::cos(tx->angles[a]);
+    }
+    return TIDAS_OK;
+}
+
+// Every fractional sample index of the grid must stay far inside int32 (byte offsets = 4 x index).
+static bool das_grid_in_range(const DasArgs& p, const tidas_grid* grid) {
+    const double half_w = 0.5 * (double)(p.C - 1) * p.pitch;
+    const double xmax = std::fabs(grid->x0) + std::fabs(grid->x0 + (grid->nx - 1) * grid->dx) + half_w;
+    const double zmax = std::fabs(grid->z0) + std::fabs(grid->z0 + (grid->nz - 1) * grid->dz);
+    const double bound = p.fs * (2.0 * xmax + 2.0 * zmax) / p.c + p.fs * std::fabs(p.t0) + 2.0;
+    return bound < 268435456.0;
+}
+
+static DasGrid to_grid(const tidas_grid* g) { return DasGrid{g->nz, g->nx, g->z0, g->dz, g->x0, g->dx}; }
 
 }  // namespace tidas
 
@@ -127,58 +234,119 @@ using namespace tidas;
 extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                                 const tidas_grid* grid, const float* rf, int32_t n_samples,
                                 int32_t n_frames, float* image, void* stream) {
-    int32_t st;
-    if ((st = validate_array(array)) || (st = validate_tx(tx, false)) || (st = validate_rx(rx)) ||
-        (st = validate_grid(grid)))
-        return st;
+    DasArgs p;
+    int32_t st = das_setup("das_beamform", array, tx, rx, n_samples, p);
+    if (st) return st;
+    if ((st = validate_grid(grid))) return st;
     if (!rf || !image) return fail(TIDAS_EINVAL, "das_beamform: null rf or image pointer");
-    if (n_samples < 2) return fail(TIDAS_EINVAL, "das_beamform: n_samples must be >= 2");
     if (n_frames < 1) return fail(TIDAS_EINVAL, "das_beamform: n_frames must be >= 1");
-    if (tx->n_angles > DAS_MAX_ANGLES)
-        return fail(TIDAS_EUNSUPPORTED, "das_beamform: at most 32 plane-wave angles");
     if ((const void*)rf == (const void*)image) return fail(TIDAS_EINVAL, "das_beamform: image aliases rf");
-    if ((int64_t)n_samples * 4 > INT32_MAX / 2) return fail(TIDAS_EUNSUPPORTED, "das_beamform: record too long");
-
-    {
-        // every fractional sample index must stay far inside int32 (byte offsets = 4 x index)
-        const double half_w = 0.5 * (double)(array->n_elem - 1) * array->pitch;
-        const double xmax = std::fabs(grid->x0) + std::fabs(grid->x0 + (grid->nx - 1) * grid->dx) + half_w;
-        const double zmax = std::fabs(grid->z0) + std::fabs(grid->z0 + (grid->nz - 1) * grid->dz);
-        const double bound = tx->fs * (2.0 * xmax + 2.0 * zmax) / array->c + tx->fs * std::fabs(tx->t0) + 2.0;
-        if (!(bound < 268435456.0)) return fail(TIDAS_EUNSUPPORTED, "das_beamform: sample indices exceed 2^28");
-    }
-    DasArgs p{};
-    p.C = array->n_elem;
-    p.T = n_samples;
-    p.A = tx->n_angles;
-    p.nz = grid->nz;
-    p.nx = grid->nx;
+    if (!das_grid_in_range(p, grid)) return fail(TIDAS_EUNSUPPORTED, "das_beamform: sample indices exceed 2^28");
     p.n_frames = n_frames;
-    p.pitch = array->pitch;
-    p.c = array->c;
-    p.fs = tx->fs;
-    p.t0 = tx->t0;
-    p.fnumber = rx->fnumber;
-    p.z0 = grid->z0;
-    p.dz = grid->dz;
-    p.x0 = grid->x0;
-    p.dx = grid->dx;
-    p.x_first = -0.5 * (double)(p.C - 1) * p.pitch;
-    p.kappa = (float)(p.fs / p.c);
-    for (int a = 0; a < p.A; ++a) {
-        p.sin_a[a] = std::sin(tx->angles[a]);
-        p.cos_a[a] = std::cos(tx->angles[a]);
-    }
+    const DasGrid gr = to_grid(grid);
     hipStream_t s = (hipStream_t)stream;
     // several frames per thread amortise the geometry over a batch
     const bool multi = n_frames >= 8;
     if (p.A == 1) {
-        if (multi) launch_das<4, 1>(p, rf, image, s);
-        else launch_das<1, 1>(p, rf, image, s);
+        if (multi) launch_das<4, 1>(p, gr, rf, image, s);
+        else launch_das<1, 1>(p, gr, rf, image, s);
     } else if (p.A == 11) {
-        launch_das<1, 11>(p, rf, image, s);
+        launch_das<1, 11>(p, gr, rf, image, s);
     } else {
-        launch_das<1, 0>(p, rf, image, s);
+        launch_das<1, 0>(p, gr, rf, image, s);
     }
     return check_launch("das_beamform");
+}
+
+// ------------------------------------------------------------------ batch ----
+namespace tidas {
+
+int32_t validate_batch(const char* name, const tidas_frame* frames, int32_t n_frames, void* workspace,
+                       size_t workspace_bytes, bool need_rf, bool need_conv) {
+    if (!frames || !workspace) return fail(TIDAS_EINVAL, std::string(name) + ": null frames or workspace");
+    if (n_frames < 1) return fail(TIDAS_EINVAL, std::string(name) + ": n_frames must be >= 1");
+    if (workspace_bytes < tidas_batch_workspace_bytes(n_frames))
+        return fail(TIDAS_EINVAL, std::string(name) + ": workspace too small");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 15) != 0)
+        return fail(TIDAS_EINVAL, std::string(name) + ": workspace must be 16-byte aligned");
+    for (int f = 0; f < n_frames; ++f) {
+        int32_t st = validate_grid(&frames[f].grid);
+        if (st) return st;
+        if (!frames[f].out) return fail(TIDAS_EINVAL, std::string(name) + ": null output pointer");
+        if (need_rf && !frames[f].rf) return fail(TIDAS_EINVAL, std::string(name) + ": null rf pointer");
+        if (need_conv && (!frames[f].kernels || !frames[f].in))
+            return fail(TIDAS_EINVAL, std::string(name) + ": null kernels or input pointer");
+    }
+    return TIDAS_OK;
+}
+
+// Builds the device table: host staging vector -> workspace.  hipMemcpyAsync
+// from pageable memory returns only once the source has been staged, so the
+// vector may go out of scope when this returns.
+int32_t upload_batch(const tidas_frame* frames, int32_t n_frames, int tile_rows, int tile_cols, void* workspace,
+                     hipStream_t s, int64_t& total) {
+    std::vector<BatchFrameDev> tab(n_frames);
+    total = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const tidas_grid& g = frames[f].grid;
+        tab[f].grid = to_grid(&g);
+        tab[f].rf = frames[f].rf;
+        tab[f].kernels = frames[f].kernels;
+        tab[f].in = frames[f].in;
+        tab[f].out = frames[f].out;
+        tab[f].tile_start = total;
+        total += (int64_t)((g.nz + tile_rows - 1) / tile_rows) * ((g.nx + tile_cols - 1) / tile_cols);
+    }
+    return check_hip(hipMemcpyAsync(workspace, tab.data(), sizeof(BatchFrameDev) * n_frames, hipMemcpyHostToDevice, s),
+                     "batch table upload");
+}
+
+}  // namespace tidas
+
+static_assert(sizeof(tidas::BatchFrameDev) <= 128, "batch table entry too large");
+
+extern "C" size_t tidas_batch_workspace_bytes(int32_t n_frames) {
+    return n_frames < 1 ? 0 : ((128 * (size_t)n_frames + 255) / 256) * 256;
+}
+
+extern "C" int32_t das_beamform_batch(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
+                                      int32_t n_samples, const tidas_frame* frames, int32_t n_frames,
+                                      void* workspace, size_t workspace_bytes, int32_t variant, void* stream) {
+    DasArgs p;
+    int32_t st = das_setup("das_beamform_batch", array, tx, rx, n_samples, p);
+    if (st) return st;
+    if ((st = validate_batch("das_beamform_batch", frames, n_frames, workspace, workspace_bytes, true, false)))
+        return st;
+    for (int f = 0; f < n_frames; ++f)
+        if (!das_grid_in_range(p, &frames[f].grid))
+            return fail(TIDAS_EUNSUPPORTED, "das_beamform_batch: sample indices exceed 2^28");
+    if (variant < 0 || variant >= TIDAS_DAS_BATCH_VARIANTS)
+        return fail(TIDAS_EINVAL, "das_beamform_batch: variant out of range");
+    const int waves = (variant & 1) ? 8 : 4;
+    const int per_cu = (variant >> 1) == 0 ? 2 : ((variant >> 1) == 1 ? 4 : 8);
+    hipStream_t s = (hipStream_t)stream;
+    int64_t total = 0;
+    if ((st = upload_batch(frames, n_frames, 64, waves, workspace, s, total))) return st;
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+    }
+    const int64_t want = (int64_t)n_cu * per_cu;  // workgroups of the persistent launch
+    // a multiple of 8 workgroups: the tile list is cut into 8 chunks, one per
+    // residue of the block id, and every chunk needs at least one workgroup
+    const int64_t nb = std::max<int64_t>(8, std::min<int64_t>(total, want));
+    const unsigned nblk = (unsigned)((nb + 7) / 8 * 8);
+    const BatchFrameDev* tab = (const BatchFrameDev*)workspace;
+    if (p.A == 11) {
+        if (waves == 8) hipLaunchKernelGGL((das_batch_kernel<11, 8>), dim3(nblk), dim3(512), 0, s, p, tab, n_frames, total);
+        else hipLaunchKernelGGL((das_batch_kernel<11, 4>), dim3(nblk), dim3(256), 0, s, p, tab, n_frames, total);
+    } else if (p.A == 1) {
+        if (waves == 8) hipLaunchKernelGGL((das_batch_kernel<1, 8>), dim3(nblk), dim3(512), 0, s, p, tab, n_frames, total);
+        else hipLaunchKernelGGL((das_batch_kernel<1, 4>), dim3(nblk), dim3(256), 0, s, p, tab, n_frames, total);
+    } else {
+        if (waves == 8) hipLaunchKernelGGL((das_batch_kernel<0, 8>), dim3(nblk), dim3(512), 0, s, p, tab, n_frames, total);
+        else hipLaunchKernelGGL((das_batch_kernel<0, 4>), dim3(nblk), dim3(256), 0, s, p, tab, n_frames, total);
+    }
+    return check_launch("das_beamform_batch");
 }

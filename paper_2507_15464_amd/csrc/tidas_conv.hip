@@ -28,6 +28,7 @@
 // halo rows in that XCD's L2.
 #include <algorithm>
 #include <utility>
+#include <vector>
 
 #include "common.hpp"
 
@@ -240,21 +241,17 @@ __host__ __device__ constexpr size_t mf_lds_bytes(int K) {
     return (size_t)((MF_TZ * mf_kstride(K) + 63) / 64) * 64 * sizeof(float);
 }
 
-template <bool ADJ>
-__global__ __launch_bounds__(MF_THREADS) void tidas_mfma_kernel(const ConvGeom g, const float* __restrict__ Kb,
-                                                                const float* __restrict__ In,
-                                                                float* Out) {
-    extern __shared__ float smem[];
-    const int K = g.K, h = g.h, Z = g.Z, X = g.X;
+// One 32 x 256 output tile of one frame.  Kb: the frame's [Z][K] bank; Ib, Ob,
+// base_b: the frame's [Z][X] input, output and (optional) epilogue base.  kt:
+// the workgroup's LDS kernel tile.  VEC: X % 4 == 0 and 16-byte aligned rows
+// (one 16-byte load / store per lane and step); otherwise four dword loads.
+// All threads of the workgroup call it (it contains barriers).
+template <bool ADJ, int PD, bool VEC>
+__device__ __forceinline__ void mfma_tile(const float* __restrict__ Kb, const float* __restrict__ Ib, float* Ob,
+                                          const float* base_b, float alpha, float beta, int K, int Z, int X, int i0,
+                                          int j0, float* kt) {
+    const int h = (K - 1) >> 1;
     const int KS = mf_kstride(K);
-    float* kt = smem;  // [MF_TZ][KS]
-
-    const int lg = xcd_remap(blockIdx.x, g.n_blocks);
-    const int rt_i = lg % g.n_rt;
-    const int ct = (lg / g.n_rt) % g.n_ct;
-    const int b = lg / (g.n_rt * g.n_ct);
-    const int i0 = rt_i * MF_TZ, j0 = ct * MF_TN;
-    const float* Ib = In + (size_t)b * Z * X;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -285,22 +282,29 @@ __global__ __launch_bounds__(MF_THREADS) void tidas_mfma_kernel(const ConvGeom g
         }
     }
 
-    const int r0 = (wave >> 2) * 16;         // M-block rows within the tile
-    const int n0 = (wave & 3) * 64;          // column quarter
+    const int r0 = (wave >> 2) * 16;  // M-block rows within the tile
+    const int n0 = (wave & 3) * 64;   // column quarter
     const int li = lane & 15, lk = lane >> 4;
     const int nsteps = mf_nsteps(K);
-    // B: step s reads input row i0 - h + r0 + 4 s + lk, columns j0 + n0 + 4 li .. +3.
+    // B: step s reads input row i0 - h + r0 + 4 s + lk, columns col .. col + 3.
     // int32 byte offsets from the frame base: rows above the image are negative
     // (huge unsigned), rows below are past the end: both read 0.
     const auto rs_in = make_rsrc(Ib, (uint32_t)((size_t)Z * X * sizeof(float)));
     const int col = j0 + n0 + 4 * li;
     const int step_bytes = 4 * X * 4;
     const int off0 = ((i0 - h + r0 + lk) * X + col) * 4;
-    constexpr int PD = 8;
+    auto load_b = [&](int off) -> floatx4 {
+        if (VEC) return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs_in, off, 0, 0));
+        floatx4 v;
+        v[0] = buffer_load_f32(rs_in, off);
+        v[1] = buffer_load_f32(rs_in, off + 4);
+        v[2] = buffer_load_f32(rs_in, off + 8);
+        v[3] = buffer_load_f32(rs_in, off + 12);
+        return v;
+    };
     floatx4 q[PD];
 #pragma unroll
-    for (int u = 0; u < PD; ++u)
-        q[u] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs_in, off0 + u * step_bytes, 0, 0));
+    for (int u = 0; u < PD; ++u) q[u] = load_b(off0 + u * step_bytes);
     __builtin_amdgcn_s_waitcnt(0);  // drain the LDS-direct loads
     __syncthreads();
 
@@ -319,8 +323,7 @@ __global__ __launch_bounds__(MF_THREADS) void tidas_mfma_kernel(const ConvGeom g
             const float a_nxt = a_ptr[-4 * min(st + 1, last)];
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur, q[u][c], acc[c], 0, 0, 0);
-            q[u] = __builtin_bit_cast(floatx4,
-                                      __builtin_amdgcn_raw_buffer_load_b128(rs_in, off0 + (st + PD) * step_bytes, 0, 0));
+            q[u] = load_b(off0 + (st + PD) * step_bytes);
             a_cur = a_nxt;
         }
     }
@@ -334,36 +337,101 @@ __global__ __launch_bounds__(MF_THREADS) void tidas_mfma_kernel(const ConvGeom g
         }
     }
 
-    if (col < X) {
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-            const int row = i0 + r0 + 4 * lk + qq;
-            if (row < Z) {
-                const size_t idx = (size_t)b * Z * X + (size_t)row * X + col;
-                float4 v = make_float4(g.alpha * acc[0][qq], g.alpha * acc[1][qq], g.alpha * acc[2][qq],
-                                       g.alpha * acc[3][qq]);
-                if (g.base) {
-                    const float4 bv = *reinterpret_cast<const float4*>(g.base + idx);
-                    v.x = fmaf(g.beta, bv.x, v.x);
-                    v.y = fmaf(g.beta, bv.y, v.y);
-                    v.z = fmaf(g.beta, bv.z, v.z);
-                    v.w = fmaf(g.beta, bv.w, v.w);
+    for (int qq = 0; qq < 4; ++qq) {
+        const int row = i0 + r0 + 4 * lk + qq;
+        if (row >= Z) continue;
+        const size_t idx = (size_t)row * X + col;
+        if (VEC) {
+            if (col < X) {
+                float4 v = make_float4(alpha * acc[0][qq], alpha * acc[1][qq], alpha * acc[2][qq], alpha * acc[3][qq]);
+                if (base_b) {
+                    const float4 bv = *reinterpret_cast<const float4*>(base_b + idx);
+                    v.x = fmaf(beta, bv.x, v.x);
+                    v.y = fmaf(beta, bv.y, v.y);
+                    v.z = fmaf(beta, bv.z, v.z);
+                    v.w = fmaf(beta, bv.w, v.w);
                 }
-                *reinterpret_cast<float4*>(Out + idx) = v;
+                *reinterpret_cast<float4*>(Ob + idx) = v;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (col + c < X) {
+                    float v = alpha * acc[c][qq];
+                    if (base_b) v = fmaf(beta, base_b[idx + c], v);
+                    Ob[idx + c] = v;
+                }
             }
         }
     }
 }
 
-static bool mfma_fits(int K, int Z, int X) {
-    // LDS tile fits; rows are float4-addressable; every int32 byte offset,
-    // including rows prefetched past the band (< K + 4 PD + 64 rows beyond
-    // the image), stays below 2^31
-    return mf_lds_bytes(K) <= 160 * 1024 && (X % 4) == 0 && ((int64_t)Z + 2 * K + 256) * X * 4 < INT32_MAX;
+template <bool ADJ, int PD, bool VEC>
+__global__ __launch_bounds__(MF_THREADS) void tidas_mfma_kernel(const ConvGeom g, const float* __restrict__ Kb,
+                                                                const float* __restrict__ In, float* Out) {
+    extern __shared__ float smem[];
+    const int lg = xcd_remap(blockIdx.x, g.n_blocks);
+    const int rt_i = lg % g.n_rt;
+    const int ct = (lg / g.n_rt) % g.n_ct;
+    const int b = lg / (g.n_rt * g.n_ct);
+    const size_t fo = (size_t)b * g.Z * g.X;
+    mfma_tile<ADJ, PD, VEC>(Kb, In + fo, Out + fo, g.base ? g.base + fo : nullptr, g.alpha, g.beta, g.K, g.Z, g.X,
+                            rt_i * MF_TZ, ct * MF_TN, smem);
 }
 
-static void launch_mfma(bool adj, const float* kernels, int32_t K, const float* in, int32_t B, int32_t Z, int32_t X,
-                        float alpha, float beta, const float* base, float* out, hipStream_t stream) {
+// Ragged batch of the line model: one persistent launch over the 32 x 256
+// tiles of all frames (each frame with its own grid, bank, input and output),
+// the tile list cut into 8 contiguous chunks, chunk x served by the
+// workgroups on XCD x.  Fixed strides: every workgroup's loop ends.
+struct ConvFrameDev {  // at most 128 bytes (the workspace holds 128 bytes per frame)
+    const float* kernels;
+    const float* in;
+    float* out;
+    int32_t Z, X;
+    int32_t vec;  // X % 4 == 0 and 16-byte aligned input and output
+    int32_t pad;
+    int64_t tile_start;
+};
+
+static_assert(sizeof(ConvFrameDev) <= 128, "batch table entry too large");
+
+template <int PD>
+__global__ __launch_bounds__(MF_THREADS) void tidas_batch_kernel(const ConvFrameDev* __restrict__ fr, int32_t n_frames,
+                                                                 int64_t total, int32_t K) {
+    extern __shared__ float smem[];
+    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int per_xcd = ((int)gridDim.x - x + 7) >> 3;
+    const int64_t lo = total * x / 8, hi = total * (x + 1) / 8;
+    for (int64_t t = lo + slot; t < hi; t += per_xcd) {
+        int a = 0, b = n_frames - 1;  // largest f with tile_start <= t
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (fr[mid].tile_start <= t) a = mid;
+            else b = mid - 1;
+        }
+        const ConvFrameDev f = fr[a];
+        const int64_t local = t - f.tile_start;
+        const int row_tiles = (f.Z + MF_TZ - 1) / MF_TZ;
+        const int i0 = (int)(local % row_tiles) * MF_TZ;
+        const int j0 = (int)(local / row_tiles) * MF_TN;
+        __syncthreads();  // the previous tile's readers of the LDS kernel tile are done
+        if (f.vec)
+            mfma_tile<false, PD, true>(f.kernels, f.in, f.out, nullptr, 1.0f, 0.0f, K, f.Z, f.X, i0, j0, smem);
+        else
+            mfma_tile<false, PD, false>(f.kernels, f.in, f.out, nullptr, 1.0f, 0.0f, K, f.Z, f.X, i0, j0, smem);
+    }
+}
+
+static bool mfma_fits(int K, int Z, int X) {
+    // LDS tile fits; every int32 byte offset,
+    // including rows prefetched past the band (< K + 4 PD + 64 rows beyond
+    // the image), stays below 2^31
+    return mf_lds_bytes(K) <= 160 * 1024 && ((int64_t)Z + 2 * K + 256) * X * 4 < INT32_MAX;
+}
+
+static void launch_mfma(bool adj, bool vec, const float* kernels, int32_t K, const float* in, int32_t B, int32_t Z,
+                        int32_t X, float alpha, float beta, const float* base, float* out, hipStream_t stream) {
     ConvGeom g;
     g.K = K;
     g.h = (K - 1) / 2;
@@ -373,16 +441,19 @@ static void launch_mfma(bool adj, const float* kernels, int32_t K, const float* 
     g.n_rt = (Z + MF_TZ - 1) / MF_TZ;
     g.n_ct = (X + MF_TN - 1) / MF_TN;
     g.n_blocks = g.n_rt * g.n_ct * B;
-    g.vec4 = 1;
+    g.vec4 = vec;
     g.alpha = alpha;
     g.beta = beta;
     g.base = base;
     const size_t lds = mf_lds_bytes(K);
-    if (adj)
-        hipLaunchKernelGGL(tidas_mfma_kernel<true>, dim3(g.n_blocks), dim3(MF_THREADS), lds, stream, g, kernels, in, out);
-    else
-        hipLaunchKernelGGL(tidas_mfma_kernel<false>, dim3(g.n_blocks), dim3(MF_THREADS), lds, stream, g, kernels, in,
-                           out);
+    const dim3 grid(g.n_blocks), block(MF_THREADS);
+    if (adj) {
+        if (vec) hipLaunchKernelGGL((tidas_mfma_kernel<true, 8, true>), grid, block, lds, stream, g, kernels, in, out);
+        else hipLaunchKernelGGL((tidas_mfma_kernel<true, 8, false>), grid, block, lds, stream, g, kernels, in, out);
+    } else {
+        if (vec) hipLaunchKernelGGL((tidas_mfma_kernel<false, 8, true>), grid, block, lds, stream, g, kernels, in, out);
+        else hipLaunchKernelGGL((tidas_mfma_kernel<false, 8, false>), grid, block, lds, stream, g, kernels, in, out);
+    }
 }
 
 constexpr int CONV_RZ = 16;
@@ -405,10 +476,10 @@ static int32_t conv_launch(bool adj, const char* name, const float* kernels, int
         return fail(TIDAS_EINVAL, std::string(name) + ": base aliases an input");
     if (!std::isfinite(alpha) || !std::isfinite(beta))
         return fail(TIDAS_EINVAL, std::string(name) + ": alpha and beta must be finite");
-    const bool use_mfma = mfma_fits(K, Z, X) && aligned16(in) && aligned16(out) && (!base || aligned16(base)) &&
-                          (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX;
+    const bool use_mfma = mfma_fits(K, Z, X) && (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX;
     if (use_mfma) {
-        launch_mfma(adj, kernels, K, in, B, Z, X, alpha, beta, base, out, stream);
+        const bool vec = (X % 4) == 0 && aligned16(in) && aligned16(out) && (!base || aligned16(base));
+        launch_mfma(adj, vec, kernels, K, in, B, Z, X, alpha, beta, base, out, stream);
         return check_launch(name);
     }
     const size_t lds = (size_t)((adj ? 0 : CONV_RZ) + CONV_RZ * CONV_WAVES + K - 1) * 64 * sizeof(float);
@@ -544,4 +615,52 @@ extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32
     if (!st) st = check_hip(hipMemcpyAsync(out, nrm, sizeof(double), hipMemcpyDeviceToHost, s), "norm download");
     if (!st) st = check_hip(hipStreamSynchronize(s), "tidas_operator_norm_sq: synchronize");
     return st;
+}
+
+extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames, int32_t K, void* workspace,
+                                     size_t workspace_bytes, int32_t variant, void* stream) {
+    int32_t st = validate_batch("tidas_apply_batch", frames, n_frames, workspace, workspace_bytes, false, true);
+    if (st) return st;
+    if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_apply_batch: K must be odd and >= 1");
+    if (variant < 0 || variant >= TIDAS_APPLY_BATCH_VARIANTS)
+        return fail(TIDAS_EINVAL, "tidas_apply_batch: variant out of range");
+    std::vector<ConvFrameDev> tab(n_frames);
+    int64_t total = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const tidas_frame& fr = frames[f];
+        const int Z = fr.grid.nz, X = fr.grid.nx;
+        if (!mfma_fits(K, Z, X)) return fail(TIDAS_EUNSUPPORTED, "tidas_apply_batch: frame too large for the tile path");
+        if (fr.in == fr.out || (const void*)fr.kernels == (const void*)fr.out)
+            return fail(TIDAS_EINVAL, "tidas_apply_batch: output aliases an input");
+        tab[f].kernels = fr.kernels;
+        tab[f].in = fr.in;
+        tab[f].out = fr.out;
+        tab[f].Z = Z;
+        tab[f].X = X;
+        tab[f].vec = (X % 4) == 0 && aligned16(fr.in) && aligned16(fr.out);
+        tab[f].pad = 0;
+        tab[f].tile_start = total;
+        total += (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // hipMemcpyAsync from pageable memory returns once the source is staged
+    if ((st = check_hip(hipMemcpyAsync(workspace, tab.data(), sizeof(ConvFrameDev) * n_frames, hipMemcpyHostToDevice, s),
+                        "tidas_apply_batch: table upload")))
+        return st;
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+    }
+    const int pd_sel = variant % 3, per_cu = (variant / 3) == 0 ? 2 : 4;
+    // a multiple of 8 workgroups: the tile list is cut into 8 chunks, one per
+    // residue of the block id, and every chunk needs at least one workgroup
+    const int64_t nb = std::max<int64_t>(8, std::min<int64_t>(total, (int64_t)n_cu * per_cu));
+    const unsigned nblk = (unsigned)((nb + 7) / 8 * 8);
+    const size_t lds = mf_lds_bytes(K);
+    const ConvFrameDev* d = (const ConvFrameDev*)workspace;
+    if (pd_sel == 0) hipLaunchKernelGGL(tidas_batch_kernel<4>, dim3(nblk), dim3(MF_THREADS), lds, s, d, n_frames, total, K);
+    else if (pd_sel == 1) hipLaunchKernelGGL(tidas_batch_kernel<8>, dim3(nblk), dim3(MF_THREADS), lds, s, d, n_frames, total, K);
+    else hipLaunchKernelGGL(tidas_batch_kernel<16>, dim3(nblk), dim3(MF_THREADS), lds, s, d, n_frames, total, K);
+    return check_launch("tidas_apply_batch");
 }

@@ -149,3 +149,25 @@ def test_deconvolve_and_norm_reject_invalid_arguments(lib):
     assert lib.tidas_operator_norm_sq(ok, 65, 16, 10, w, None, NUL) == -1
     assert lib.tidas_apply_ex(ok, 65, y, 1, 16, 16, f(1.0), f(1.0), y, r, NUL) == -1        # base aliases input
     assert lib.tidas_adjoint_ex(ok, 65, y, 1, 16, 16, f(float("inf")), f(1.0), None, r, NUL) == -1
+
+
+def test_batch_entry_points_reject_invalid_arguments(lib):
+    arr, tx, rx, g = _geom()
+    frames = (_lib.Frame * 2)()
+    for f in range(2):
+        frames[f] = _lib.Frame(g, 0x1000, 0x2000, 0x3000, 0x4000 + 0x100 * f)
+    need = lib.tidas_batch_workspace_bytes(2)
+    assert need >= 2 * 72 and lib.tidas_batch_workspace_bytes(0) == 0
+    ws = ctypes.c_void_p(0x10000)
+    geo = (ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx))
+    assert lib.das_beamform_batch(*geo, 2048, frames, 2, ws, need - 1, 0, NUL) == -1       # small workspace
+    assert lib.das_beamform_batch(*geo, 2048, frames, 2, ws, need, 6, NUL) == -1           # variant
+    assert lib.das_beamform_batch(*geo, 2048, frames, 0, ws, need, 0, NUL) == -1           # no frames
+    assert lib.das_beamform_batch(*geo, 2048, frames, 2, ctypes.c_void_p(0x10004), need, 0, NUL) == -1  # alignment
+    assert lib.tidas_apply_batch(frames, 2, 64, ws, need, 0, NUL) == -1                     # even K
+    assert lib.tidas_apply_batch(frames, 2, 65, ws, need, -1, NUL) == -1                    # variant
+    bad = (_lib.Frame * 1)()
+    bad[0] = _lib.Frame(_lib.make_grid(0, 4, 0, 1e-4, 0, 1e-4), 0x1000, 0x2000, 0x3000, 0x4000)
+    assert lib.tidas_apply_batch(bad, 1, 65, ws, need, 0, NUL) == -1                        # empty grid
+    bad[0] = _lib.Frame(g, 0x1000, 0x2000, 0x3000, 0)
+    assert lib.das_beamform_batch(*geo, 2048, bad, 1, ws, need, 0, NUL) == -1              # null output
