@@ -251,6 +251,63 @@ int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames, int32_t K
                           size_t workspace_bytes, int32_t variant, void* stream);
 
 /*
+ * Exact-mode row kernels for independent draws (the surrogate's training data
+ * and error judge).  Row i uses params[i] = (depth z, F-number, plane-wave
+ * angle [rad], centre frequency [Hz]) (DEV float64 [N][4]), one transmit
+ * angle, the pulse of `cycles` periods at that frequency and n_samples
+ * samples at fs from t0:
+ *   out[i][m+h] = DAS, at (0, z + m dz), of a unit scatterer at (0, z)
+ * (the exact mode of tidas_build_kernels for that single row).  scale DEV [N]
+ * or NULL receives s_i = max(sum_n w(-x_n, z), 1), the row's aperture weight
+ * sum, against which the surrogate learns normalised kernels; with
+ * normalise != 0, out[i] is divided by s_i.
+ */
+int32_t tidas_kernels_at(const tidas_array* array, double fs, double t0, double cycles, int32_t n_samples, double dz,
+                         const double* params, int32_t N, int32_t K, int32_t normalise, float* out, float* scale,
+                         void* stream);
+
+/*
+ * Kernel-surrogate MLP (an extension; the paper treats the weights Theta as
+ * learned, Sec. 4): widths[5] = {4, 256, 256, 256, K}, GELU after the first
+ * three linear layers.  Parameters are one flat float32 buffer (DEV [P],
+ * P = tidas_mlp_param_count): for each layer W [out][in] then b [out]; a
+ * bfloat16 copy (DEV uint16 [P], round to nearest even) feeds the matrix
+ * cores.  Inputs x DEV float32 [rows][4] are normalised features in [-1, 1]
+ * (tidas_mlp_features).  Every GEMM takes bfloat16 operands and accumulates
+ * in float32; activations and back-propagated gradients are rounded to
+ * bfloat16 before each GEMM.  `work` is DEV, 256-byte aligned, of
+ * tidas_mlp_workspace_bytes(widths, N) bytes.
+ */
+int64_t tidas_mlp_param_count(const int32_t* widths /* HOST [5] */);
+size_t tidas_mlp_workspace_bytes(const int32_t* widths /* HOST [5] */, int32_t N);
+
+/* x [N][4] = 2 (params - lo) / (hi - lo) - 1 per column; params DEV float64
+ * [N][4]; lo, hi HOST [4] with lo < hi. */
+int32_t tidas_mlp_features(const double* params, int32_t N, const double* lo, const double* hi, float* x,
+                           void* stream);
+
+/* params16 = bfloat16(params), n values. */
+int32_t tidas_mlp_to_bf16(const float* params, int64_t n, uint16_t* params16, void* stream);
+
+/* y [N][K] = MLP(x), each row times scale[row] (scale DEV [N] or NULL). */
+int32_t tidas_mlp_forward(const int32_t* widths, const uint16_t* params16, const float* params, const float* x,
+                          int32_t N, const float* scale, float* y, void* work, size_t work_bytes, void* stream);
+
+/* One training step on N rows gathered from the dataset (x DEV [n_rows][4],
+ * target DEV [n_rows][K]) through idx (DEV int32 [N], values clamped to
+ * [0, n_rows); NULL = rows 0..N-1): forward, loss = mean (y - target)^2
+ * written to *loss (DEV float), and the gradient of the loss with respect to
+ * every parameter written to grad (DEV float32 [P]). */
+int32_t tidas_mlp_train_step(const int32_t* widths, const uint16_t* params16, const float* params, const float* x,
+                             const float* target, int32_t n_rows, const int32_t* idx, int32_t N, float* grad,
+                             float* loss, void* work, size_t work_bytes, void* stream);
+
+/* Adam (bias-corrected, step >= 1) on the float32 master parameters with
+ * moments m, v (DEV [P]); refreshes the bfloat16 copy. */
+int32_t tidas_mlp_adam(const int32_t* widths, float* params, const float* grad, float* m, float* v,
+                       uint16_t* params16, float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/*
  * Born-approximation RF synthesis, Sec. 2 eqn:SRX with linear superposition:
  *   rf[a][n][k] = sum_s amp[s] * p(t0 + k/fs - tau_n(x_s, z_s; a))
  * accumulated in float64 and rounded once to float32.  scat is DEV

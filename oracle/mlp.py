@@ -25,6 +25,23 @@ SQRT2 = np.sqrt(2.0)
 INV_SQRT_2PI = 1.0 / np.sqrt(2.0 * np.pi)
 
 
+def kernel_scale(z, fnumber, n_elem, pitch):
+    """Normaliser of a row kernel: max(sum_n w(-x_n, z), 1), the aperture's
+    Hann weight sum (the centre tap of an unsteered exact kernel is this sum
+    times the pulse peak, up to interpolation), floored at 1."""
+    from . import geometry
+    w = geometry.hann_apod(-geometry.element_x(n_elem, pitch), z, fnumber)
+    return max(float(np.sum(w)), 1.0)
+
+
+def features(params, lo, hi):
+    """Affine map of each parameter column onto [-1, 1]."""
+    params = np.asarray(params, np.float64)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    return 2.0 * (params - lo) / (hi - lo) - 1.0
+
+
 def bf16(v):
     """Round to bfloat16 (8 significant bits, round to nearest even), returned
     as float64.  The value is first rounded to float32 (the device rounds

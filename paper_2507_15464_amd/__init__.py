@@ -5,3 +5,4 @@ from .api import adjoint, apply, build_kernels, das_beamform, simulate_rf, versi
 from .autograd import TiDASFunction, adjoint_ex, apply_ex, deconvolve, operator_norm_sq, step_size, tidas  # noqa: F401,E402
 from .batch import apply_batch, das_beamform_batch  # noqa: F401,E402
 from . import autotune  # noqa: F401,E402
+from . import surrogate  # noqa: F401,E402

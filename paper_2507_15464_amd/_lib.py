@@ -74,6 +74,17 @@ _SIGS = {
     "das_beamform_batch": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), _I,
                                 ctypes.POINTER(Frame), _I, _P, ctypes.c_size_t, _I, _P]),
     "tidas_apply_batch": (_I, [ctypes.POINTER(Frame), _I, _I, _P, ctypes.c_size_t, _I, _P]),
+    "tidas_kernels_at": (_I, [ctypes.POINTER(Array), ctypes.c_double, ctypes.c_double, ctypes.c_double, _I,
+                              ctypes.c_double, _P, _I, _I, _I, _P, _P, _P]),
+    "tidas_mlp_param_count": (ctypes.c_int64, [ctypes.POINTER(ctypes.c_int32)]),
+    "tidas_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int32), _I]),
+    "tidas_mlp_features": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P, _P]),
+    "tidas_mlp_to_bf16": (_I, [_P, ctypes.c_int64, _P, _P]),
+    "tidas_mlp_forward": (_I, [ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _I, _P, _P, _P, ctypes.c_size_t, _P]),
+    "tidas_mlp_train_step": (_I, [ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P, _I, _P, _I, _P, _P, _P,
+                                  ctypes.c_size_t, _P]),
+    "tidas_mlp_adam": (_I, [ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, ctypes.c_float, _I, _P]),
 }
 
 _lib = None

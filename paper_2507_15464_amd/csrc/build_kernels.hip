@@ -257,6 +257,58 @@ __global__ __launch_bounds__(256) void zero_kernel(double* __restrict__ p, int64
     if (idx < n) p[idx] = 0.0;
 }
 
+// ------------------------------------------------------- per-row draws ----
+// Exact-mode kernels for independent rows, each with its own depth, F-number,
+// plane-wave angle and centre frequency (single angle per row); the training
+// data and error judge of the kernel surrogate.
+struct RowDrawArgs {
+    int32_t C, T, K;
+    double pitch, c, fs, t0, cycles, dz, x_first;
+};
+
+__device__ double unit_das_row(const RowDrawArgs& e, double z, double zs, double fnumber, double sa, double ca,
+                               double fc, double sigma) {
+    double acc = 0.0;
+    for (int n = 0; n < e.C; ++n) {
+        const double xn = e.x_first + (double)n * e.pitch;
+        const double w = hann_d(-xn, z, fnumber);
+        if (w == 0.0) continue;
+        const double u = ((z * ca) / e.c + sqrt(xn * xn + z * z) / e.c - e.t0) * e.fs;
+        const double tau = (zs * ca) / e.c + sqrt(xn * xn + zs * zs) / e.c;
+        const double q = floor(u);
+        const double f = u - q;
+        double s0 = 0.0, s1 = 0.0;
+        if (q >= 0.0 && q < (double)e.T) s0 = pulse_d(e.t0 + q / e.fs - tau, fc, sigma);
+        if (q + 1.0 >= 0.0 && q + 1.0 < (double)e.T) s1 = pulse_d(e.t0 + (q + 1.0) / e.fs - tau, fc, sigma);
+        acc += w * ((1.0 - f) * s0 + f * s1);
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void kernels_at_kernel(const RowDrawArgs e, const double* __restrict__ params,
+                                                         int32_t N, int32_t normalise, float* __restrict__ out,
+                                                         float* __restrict__ scale) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)N * e.K) return;
+    const int i = (int)(idx / e.K);
+    const int t = (int)(idx % e.K);
+    const int h = (e.K - 1) / 2;
+    const double z = params[4 * (int64_t)i], F = params[4 * (int64_t)i + 1];
+    const double alpha = params[4 * (int64_t)i + 2], fc = params[4 * (int64_t)i + 3];
+    const double sigma = (e.cycles / fc) / (2.0 * sqrt(2.0 * log(2.0)));
+    double sa, ca;
+    sincos(alpha, &sa, &ca);
+    double sw = 1.0;
+    if (normalise || (scale && t == 0)) {
+        sw = 0.0;
+        for (int n = 0; n < e.C; ++n) sw += hann_d(-(e.x_first + (double)n * e.pitch), z, F);
+        sw = fmax(sw, 1.0);
+    }
+    const double v = unit_das_row(e, z + (double)(t - h) * e.dz, z, F, sa, ca, fc, sigma);
+    out[idx] = (float)(normalise ? v / sw : v);
+    if (scale && t == 0) scale[i] = (float)sw;
+}
+
 static int32_t fill_setup(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx, int32_t T, Setup64& s) {
     if (tx->n_angles > BK_MAX_ANGLES) return fail(TIDAS_EUNSUPPORTED, "at most 32 plane-wave angles");
     s.C = array->n_elem;
@@ -386,4 +438,31 @@ extern "C" int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* t
     hipError_t e = hipFreeAsync(buf, strm);
     if (!st) st = check_hip(e, "tidas_simulate_rf: free");
     return st;
+}
+
+extern "C" int32_t tidas_kernels_at(const tidas_array* array, double fs, double t0, double cycles, int32_t n_samples,
+                                    double dz, const double* params, int32_t N, int32_t K, int32_t normalise,
+                                    float* out, float* scale, void* stream) {
+    int32_t st;
+    if ((st = validate_array(array))) return st;
+    if (!params || !out || N < 1) return fail(TIDAS_EINVAL, "tidas_kernels_at: null pointer or N < 1");
+    if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_kernels_at: K must be odd and >= 1");
+    if (!finite_pos(fs) || !std::isfinite(t0) || !finite_pos(cycles) || !finite_pos(dz) || n_samples < 2)
+        return fail(TIDAS_EINVAL, "tidas_kernels_at: need fs, cycles, dz > 0, finite t0, n_samples >= 2");
+    if ((void*)out == (void*)scale) return fail(TIDAS_EINVAL, "tidas_kernels_at: scale aliases out");
+    RowDrawArgs e;
+    e.C = array->n_elem;
+    e.T = n_samples;
+    e.K = K;
+    e.pitch = array->pitch;
+    e.c = array->c;
+    e.fs = fs;
+    e.t0 = t0;
+    e.cycles = cycles;
+    e.dz = dz;
+    e.x_first = -0.5 * (double)(e.C - 1) * e.pitch;
+    const int64_t n = (int64_t)N * K;
+    hipLaunchKernelGGL(kernels_at_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, e,
+                       params, N, normalise, out, scale);
+    return check_launch("tidas_kernels_at");
 }
