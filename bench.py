@@ -21,6 +21,10 @@ Other workloads (one JSON line each, not the headline):
                         and the line model
     --workload deconv   200 Tikhonov gradient iterations on a 256 x 1024 map
                         (500 spikes, 40 dB noise, lambda 1e-3, 65 taps)
+    --workload surrogate  train the BF16-MFMA kernel surrogate on 200k exact
+                        kernels (depth, F# 1-3, angle +-15 deg, fc 3-10 MHz), then
+                        surrogate-kernel vs exact-kernel line model on 512 x 2048
+                        speckle (129 taps): rel-L2, bank generation and frames/s
 """
 import argparse
 import json
@@ -45,7 +49,9 @@ DAS_FLOPS_PER_TERM = 14
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["main", "batch", "deconv"], default="main")
+    ap.add_argument("--workload", choices=["main", "batch", "deconv", "surrogate"], default="main")
+    ap.add_argument("--train-steps", type=int, default=20000, help="surrogate workload: Adam steps")
+    ap.add_argument("--train-rows", type=int, default=200_000, help="surrogate workload: training kernels")
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=64, help="frames per step")
@@ -88,7 +94,7 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
-    {"main": run_main, "batch": run_batch, "deconv": run_deconv}[args.workload](args)
+    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "surrogate": run_surrogate}[args.workload](args)
 
 
 def run_main(args):
@@ -375,6 +381,109 @@ def run_deconv(args):
                    "iterations": iters, "eta": eta},
         "us_per_iteration": ms * 1e3 / iters, "achieved_tflops": flops / (ms * 1e-3) / 1e12,
         "rel_error_to_truth": err,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_surrogate(args):
+    """Train the kernel surrogate and compare surrogate-kernel tiDAS with exact-kernel tiDAS and DAS."""
+    import numpy as np
+    import torch
+
+    import paper_2507_15464_amd as td
+    from paper_2507_15464_amd import surrogate as sg
+    from workloads import config, generators
+    from workloads.configs import CYSTS, N_SCATTERERS, SURROGATE
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s5 = config(5)
+    K, Z, X = s5.K, s5.nz, s5.nx
+    lo = (s5.z0, SURROGATE["fnumber"][0], np.radians(SURROGATE["angle_deg"][0]), SURROGATE["fc"][0])
+    hi = (s5.z0 + (Z - 1) * s5.dz, SURROGATE["fnumber"][1], np.radians(SURROGATE["angle_deg"][1]),
+          SURROGATE["fc"][1])
+
+    def draws(n, seed):
+        return torch.from_numpy(generators.kernel_params(n, lo[0], hi[0], SURROGATE["fnumber"], SURROGATE["angle_deg"],
+                                                         SURROGATE["fc"], seed)).to(dev)
+
+    # ---- data: exact normalised kernels generated on the GPU
+    t0 = time.perf_counter()
+    P_tr = draws(args.train_rows, 0)
+    x_tr = sg.features(P_tr, lo, hi)
+    t_tr, _ = sg.kernels_at(s5, s5.fs, s5.t0, s5.cycles, s5.n_samples, s5.dz, P_tr, K, normalise=True)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    log(f"{args.train_rows} training kernels in {gen_s:.2f}s")
+
+    # ---- training
+    model = sg.Surrogate()
+    model.load_layers([(W, np.zeros_like(b)) for W, b in generators.mlp_init(SURROGATE["widths"], 0)])
+    B = SURROGATE["batch"]
+    idx_all = torch.from_numpy(generators.batch_indices(args.train_rows, B, args.train_steps, seed=2).astype(np.int32))
+    idx_all = idx_all.to(dev)
+    batches = [idx_all[i] for i in range(args.train_steps)]
+    first = float(model.train_step(x_tr, t_tr, idx=batches[0]))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    final = model.fit(x_tr, t_tr, batches, total_steps=args.train_steps, log_every=max(1, args.train_steps // 10),
+                      log=lambda st, l: log(f"step {st} loss {l:.3e}"))
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    macs = sum(a * b for a, b in zip(SURROGATE["widths"][:-1], SURROGATE["widths"][1:]))
+    train_flops = args.train_steps * B * 2.0 * macs * 3.0
+
+    # ---- held-out kernels
+    P_te = draws(4096, 1)
+    ex_te, s_te = sg.kernels_at(s5, s5.fs, s5.t0, s5.cycles, s5.n_samples, s5.dz, P_te, K)
+    pr_te = model.forward(sg.features(P_te, lo, hi), scale=s_te)
+    heldout = sg.rel_l2(pr_te, ex_te)
+
+    # ---- the 512 x 2048 image: rows at F# 1.5, 0 deg, 7.5 MHz
+    zs = s5.z0 + np.arange(Z) * s5.dz
+    P_img = torch.from_numpy(np.stack([zs, np.full(Z, 1.5), np.zeros(Z), np.full(Z, 7.5e6)], 1)).to(dev)
+    bank_s, info = model.kernel_bank(s5, P_img, lo, hi, judge_rows=32, tol=1.0)
+    bank_e, _ = sg.kernels_at(s5, s5.fs, s5.t0, s5.cycles, s5.n_samples, s5.dz, P_img, K)
+    bank_err = sg.rel_l2(bank_s, bank_e)
+    t_sur = _events_ms(lambda: model.forward(sg.features(P_img, lo, hi), scale=sg.aperture_scale(s5, P_img)), 20, 3)
+    t_ex = _events_ms(lambda: sg.kernels_at(s5, s5.fs, s5.t0, s5.cycles, s5.n_samples, s5.dz, P_img, K), 20, 3)
+
+    x, z, a, _ = generators.speckle_with_cysts(N_SCATTERERS[2], s5.field_w, s5.field_d, CYSTS["n"], CYSTS["r_lo"],
+                                               CYSTS["r_hi"], seed=0)
+    i, j, zsn, xsn = generators.snap_to_grid(x, z, s5.x0, s5.dx, X, s5.z0, s5.dz, Z)
+    R = torch.from_numpy(generators.reflectivity_map(i, j, a, Z, X).astype(np.float32)).to(dev)
+    y_s = td.apply(bank_s, R)
+    y_e = td.apply(bank_e, R)
+    tidas_err = sg.rel_l2(y_s, y_e)
+    img_setup = s5.replace(fnumber=1.5, fc=7.5e6, angles=(0.0,))
+    rf = td.simulate_rf(img_setup, torch.tensor(np.stack([xsn, zsn, a], 1), dtype=torch.float64, device=dev))
+    d = td.das_beamform(rf, img_setup)
+    approx_e, approx_s = sg.rel_l2(y_e, d), sg.rel_l2(y_s, d)
+
+    # ---- throughput: 16 frames per launch
+    nb = 16
+    Rb = R.unsqueeze(0).repeat(nb, 1, 1).contiguous()
+    Yb = torch.empty_like(Rb)
+    app_ms = _events_ms(lambda: td.apply(bank_s, Rb, out=Yb), args.steps, args.warmup)
+    hbm = (8.0 * Z * X * nb + 4.0 * Z * K) / (app_ms * 1e-3) / 1e9
+    tflops = 2.0 * K * Z * X * nb / (app_ms * 1e-3) / 1e12
+    out = {
+        "metric": "surrogate-kernel tiDAS vs exact-kernel tiDAS (512x2048 px, 129 taps): rel-L2 and frames/s",
+        "value": nb / (app_ms * 1e-3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": app_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MLP / f32 line model", "data": "synthetic (exact DAS kernels of random draws; speckle)",
+        "config": {"workload": "MLP 4-256-256-256-129 GELU, 200k kernels, batch 1024; 512x2048 image",
+                   "train_rows": args.train_rows, "train_steps": args.train_steps},
+        "training": {"data_gen_s": gen_s, "ms": train_ms, "steps_per_s": args.train_steps / (train_ms * 1e-3),
+                     "achieved_tflops_bf16": train_flops / (train_ms * 1e-3) / 1e12, "loss_first": first,
+                     "loss_final": final},
+        "heldout_kernel_rel_l2": heldout,
+        "image": {"bank_rel_l2": bank_err, "judge": info, "surrogate_vs_exact_tidas_rel_l2": tidas_err,
+                  "exact_tidas_vs_das_rel_l2": approx_e, "surrogate_tidas_vs_das_rel_l2": approx_s},
+        "bank_generation_ms": {"surrogate": t_sur, "exact": t_ex, "speedup": t_ex / t_sur},
+        "per_frame_with_bank_ms": {"surrogate": t_sur + app_ms / nb, "exact": t_ex + app_ms / nb},
+        "line_model": {"tflops": tflops, "hbm_gbs_algorithmic": hbm, "hbm_frac": hbm / HBM_PEAK_GBS},
     }
     print(json.dumps(out), flush=True)
 

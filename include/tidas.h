@@ -308,6 +308,14 @@ int32_t tidas_mlp_adam(const int32_t* widths, float* params, const float* grad, 
                        uint16_t* params16, float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
 
 /*
+ * Error measure for reports and for the surrogate's error judge:
+ * out[0] = sum (a - b)^2, out[1] = sum b^2 over n float32 values (DEV a, b),
+ * accumulated in float64; work DEV double [2]; out HOST double [2], written
+ * after the call synchronises the stream.
+ */
+int32_t tidas_sq_norms(const float* a, const float* b, int64_t n, double* work, double* out, void* stream);
+
+/*
  * Born-approximation RF synthesis, Sec. 2 eqn:SRX with linear superposition:
  *   rf[a][n][k] = sum_s amp[s] * p(t0 + k/fs - tau_n(x_s, z_s; a))
  * accumulated in float64 and rounded once to float32.  scat is DEV

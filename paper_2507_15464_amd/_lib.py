@@ -83,6 +83,7 @@ _SIGS = {
     "tidas_mlp_forward": (_I, [ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _I, _P, _P, _P, ctypes.c_size_t, _P]),
     "tidas_mlp_train_step": (_I, [ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P, _I, _P, _I, _P, _P, _P,
                                   ctypes.c_size_t, _P]),
+    "tidas_sq_norms": (_I, [_P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "tidas_mlp_adam": (_I, [ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float,
                             ctypes.c_float, ctypes.c_float, _I, _P]),
 }

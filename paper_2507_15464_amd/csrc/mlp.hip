@@ -19,6 +19,7 @@
 //   A operand (16 x 32): lane l holds A[l % 16][8 (l / 16) .. +7]
 //   B operand (32 x 16): lane l holds B[8 (l / 16) .. +7][l % 16]
 //   D (16 x 16): register r of lane l holds D[4 (l / 16) + r][l % 16]
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -223,6 +224,35 @@ __global__ __launch_bounds__(256) void features_kernel(const double* __restrict_
     if (e >= (int64_t)N * 4) return;
     const int j = (int)(e & 3);
     x[e] = (float)(2.0 * (params[e] - r.lo[j]) / (r.hi[j] - r.lo[j]) - 1.0);
+}
+
+// sums of (a - b)^2 and b^2 in float64 (atomics: order-free, used for error reports only)
+__global__ __launch_bounds__(256) void sq_norms_kernel(const float* __restrict__ a, const float* __restrict__ b,
+                                                       int64_t n, double* __restrict__ out) {
+    __shared__ double red[2][4];
+    double d2 = 0.0, b2 = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const double d = (double)a[e] - (double)b[e];
+        d2 += d * d;
+        b2 += (double)b[e] * (double)b[e];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        d2 += __shfl_down(d2, off, 64);
+        b2 += __shfl_down(b2, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = d2;
+        red[1][threadIdx.x >> 6] = b2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsafeAtomicAdd(out, red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        unsafeAtomicAdd(out + 1, red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    }
+}
+
+__global__ void zero2_kernel(double* p) {
+    if (threadIdx.x < 2) p[threadIdx.x] = 0.0;
 }
 
 // ---------------------------------------------------------------- layout ----
@@ -465,4 +495,19 @@ extern "C" int32_t tidas_mlp_features(const double* params, int32_t N, const dou
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, params, N,
                        r, x);
     return check_launch("tidas_mlp_features");
+}
+
+extern "C" int32_t tidas_sq_norms(const float* a, const float* b, int64_t n, double* work, double* out,
+                                  void* stream) {
+    if (!a || !b || !work || !out || n < 0) return fail(TIDAS_EINVAL, "tidas_sq_norms: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(64), 0, s, work);
+    if (n > 0) {
+        const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+        hipLaunchKernelGGL(sq_norms_kernel, dim3(nb), dim3(256), 0, s, a, b, n, work);
+    }
+    int32_t st = check_launch("tidas_sq_norms");
+    if (!st) st = check_hip(hipMemcpyAsync(out, work, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "tidas_sq_norms");
+    if (!st) st = check_hip(hipStreamSynchronize(s), "tidas_sq_norms: synchronize");
+    return st;
 }

@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from .api import _check_tensor, _stream
 
-__all__ = ["Surrogate", "kernels_at", "features", "aperture_scale"]
+__all__ = ["Surrogate", "kernels_at", "features", "aperture_scale", "rel_l2"]
 
 WIDTHS = (4, 256, 256, 256, 129)
 
@@ -46,6 +46,19 @@ def kernels_at(array, fs, t0, cycles, n_samples, dz, params, K, normalise=False)
     _lib.check(lib.tidas_kernels_at(ctypes.byref(arr), float(fs), float(t0), float(cycles), int(n_samples), float(dz),
                                     _ptr(params), N, int(K), int(bool(normalise)), _ptr(out), _ptr(scale), _stream()))
     return out, scale
+
+
+def rel_l2(a, b):
+    """||a - b|| / ||b|| over two float32 device tensors of equal size."""
+    lib = _lib.load()
+    _check_tensor(a, "a")
+    _check_tensor(b, "b")
+    if a.numel() != b.numel():
+        raise ValueError("sizes differ")
+    work = torch.empty(2, device=a.device, dtype=torch.float64)
+    out = (ctypes.c_double * 2)()
+    _lib.check(lib.tidas_sq_norms(_ptr(a), _ptr(b), a.numel(), _ptr(work), out, _stream()))
+    return math.sqrt(out[0] / out[1]) if out[1] > 0 else math.sqrt(out[0])
 
 
 def aperture_scale(array, params):
@@ -170,6 +183,28 @@ class Surrogate:
             if log_every and log is not None and self.step % log_every == 0:
                 log(self.step, float(self.loss))
         return float(self.loss)
+
+    def kernel_bank(self, rig, params, lo, hi, judge_rows=16, tol=1e-2):
+        """Kernel bank [N][K] for row draws ``params`` (float64 device [N][4]).
+
+        The surrogate predicts every row; the exact kernels of ``judge_rows``
+        evenly spaced rows judge it.  If their relative L2 error exceeds
+        ``tol`` the bank falls back to exact kernels for all rows.  ``rig``
+        needs ``n_elem, pitch, c, fs, t0, cycles, n_samples, dz``.
+        Returns (bank, info)."""
+        N = params.shape[0]
+        K = self.widths[-1]
+        x = features(params, lo, hi)
+        s = aperture_scale(rig, params)
+        bank = self.forward(x, scale=s)
+        rows = torch.linspace(0, N - 1, min(judge_rows, N), device=params.device).round().long()
+        exact_rows, _ = kernels_at(rig, rig.fs, rig.t0, rig.cycles, rig.n_samples, rig.dz, params[rows].contiguous(), K)
+        err = rel_l2(bank[rows].contiguous(), exact_rows)
+        info = {"judge_rel_l2": err, "fallback": False}
+        if err > tol:
+            bank, _ = kernels_at(rig, rig.fs, rig.t0, rig.cycles, rig.n_samples, rig.dz, params, K)
+            info["fallback"] = True
+        return bank, info
 
     # -- checkpoint / resume --
     def state_dict(self):

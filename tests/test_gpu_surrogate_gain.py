@@ -1,0 +1,105 @@
+"""What the trained surrogate gains over the method without it.
+
+Without the network, a kernel bank for a new (depth, F-number, angle, fc)
+configuration either comes from the exact derivation (DAS of a unit echo per
+row and tap) or from a precomputed table of exact kernels looked up at the
+nearest parameter point.  The test trains a surrogate briefly on the device
+and shows, on held-out draws, that it is (1) faster than exact derivation and
+(2) more accurate than a nearest-neighbour table holding as many numbers as
+the network has parameters; it also exercises the exact-kernel fallback
+driven by the error judge.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2507_15464_amd import surrogate as sg  # noqa: E402
+from workloads import config, generators  # noqa: E402
+from workloads.configs import SURROGATE  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+S5 = config(5)
+LO = (S5.z0, SURROGATE["fnumber"][0], np.radians(SURROGATE["angle_deg"][0]), SURROGATE["fc"][0])
+HI = (S5.z0 + (S5.nz - 1) * S5.dz, SURROGATE["fnumber"][1], np.radians(SURROGATE["angle_deg"][1]), SURROGATE["fc"][1])
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def draws(n, seed, dev):
+    P = generators.kernel_params(n, LO[0], HI[0], SURROGATE["fnumber"], SURROGATE["angle_deg"], SURROGATE["fc"], seed)
+    return torch.from_numpy(P).to(dev)
+
+
+@pytest.fixture(scope="module")
+def trained(dev):
+    n, steps = 65536, 3000
+    P = draws(n, 0, dev)
+    x = sg.features(P, LO, HI)
+    t, _ = sg.kernels_at(S5, S5.fs, S5.t0, S5.cycles, S5.n_samples, S5.dz, P, S5.K, normalise=True)
+    m = sg.Surrogate()
+    m.load_layers([(W, np.zeros_like(b)) for W, b in generators.mlp_init(SURROGATE["widths"], 0)])
+    idx = torch.from_numpy(generators.batch_indices(n, 1024, steps, seed=2).astype(np.int32)).to(dev)
+    m.fit(x, t, [idx[i] for i in range(steps)], total_steps=steps)
+    return m
+
+
+def ms(fn, reps=10):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def test_surrogate_beats_equal_memory_table_on_heldout_draws(dev, trained):
+    K = S5.K
+    P_te = draws(2048, 1, dev)
+    ex, s = sg.kernels_at(S5, S5.fs, S5.t0, S5.cycles, S5.n_samples, S5.dz, P_te, K)
+    pred = trained.forward(sg.features(P_te, LO, HI), scale=s)
+    err_net = sg.rel_l2(pred, ex)
+    # table of exact normalised kernels with as many numbers as the network has parameters
+    n_tab = trained.P // K
+    P_tab = draws(n_tab, 4, dev)
+    tab, _ = sg.kernels_at(S5, S5.fs, S5.t0, S5.cycles, S5.n_samples, S5.dz, P_tab, K, normalise=True)
+    xt = sg.features(P_tab, LO, HI).cpu().numpy().astype(np.float64)
+    xq = sg.features(P_te, LO, HI).cpu().numpy().astype(np.float64)
+    nn = np.argmin(((xq[:, None, :] - xt[None, :, :]) ** 2).sum(-1), axis=1)
+    table_pred = tab.cpu().numpy()[nn] * s.cpu().numpy()[:, None]
+    exn = ex.cpu().numpy().astype(np.float64)
+    err_tab = np.linalg.norm(table_pred - exn) / np.linalg.norm(exn)
+    print(f"held-out rel-L2: surrogate {err_net:.3e}, nearest-of-{n_tab} table {err_tab:.3e}")
+    assert err_net < err_tab
+
+
+def test_surrogate_bank_is_faster_than_exact_derivation(dev, trained):
+    K, Z = S5.K, S5.nz
+    zs = S5.z0 + np.arange(Z) * S5.dz
+    P = torch.from_numpy(np.stack([zs, np.full(Z, 1.5), np.zeros(Z), np.full(Z, 7.5e6)], 1)).to(dev)
+    t_net = ms(lambda: trained.forward(sg.features(P, LO, HI), scale=sg.aperture_scale(S5, P)))
+    t_ex = ms(lambda: sg.kernels_at(S5, S5.fs, S5.t0, S5.cycles, S5.n_samples, S5.dz, P, K))
+    print(f"2048-row bank: surrogate {t_net:.3f} ms, exact {t_ex:.3f} ms")
+    assert t_net < t_ex
+
+
+def test_error_judge_falls_back_to_exact_kernels(dev, trained):
+    K, Z = S5.K, 256
+    zs = S5.z0 + (np.arange(Z) * 8) * S5.dz
+    P = torch.from_numpy(np.stack([zs, np.full(Z, 2.0), np.full(Z, 0.1), np.full(Z, 5e6)], 1)).to(dev)
+    exact, _ = sg.kernels_at(S5, S5.fs, S5.t0, S5.cycles, S5.n_samples, S5.dz, P, K)
+    bank, info = trained.kernel_bank(S5, P, LO, HI, judge_rows=16, tol=1e-9)
+    assert info["fallback"] and torch.equal(bank, exact)
+    bank2, info2 = trained.kernel_bank(S5, P, LO, HI, judge_rows=16, tol=10.0)
+    assert not info2["fallback"] and info2["judge_rel_l2"] > 0
+    assert sg.rel_l2(bank2, exact) < 1.0
