@@ -21,6 +21,10 @@ Other workloads (one JSON line each, not the headline):
                         and the line model
     --workload deconv   200 Tikhonov gradient iterations on a 256 x 1024 map
                         (500 spikes, 40 dB noise, lambda 1e-3, 65 taps)
+    --workload approx   the paper-style 1-D approximation error (on-axis line,
+                        plane wave): single scatterers at every row and 5 / 5 rising /
+                        100 scatterer lines, exact kernels and one reference curve
+                        at 25 and 35 mm, local and global squared errors
     --workload surrogate  train the BF16-MFMA kernel surrogate on 200k exact
                         kernels (depth, F# 1-3, angle +-15 deg, fc 3-10 MHz), then
                         surrogate-kernel vs exact-kernel line model on 512 x 2048
@@ -49,7 +53,7 @@ DAS_FLOPS_PER_TERM = 14
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["main", "batch", "deconv", "surrogate"], default="main")
+    ap.add_argument("--workload", choices=["main", "batch", "deconv", "surrogate", "approx"], default="main")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate workload: Adam steps")
     ap.add_argument("--train-rows", type=int, default=200_000, help="surrogate workload: training kernels")
     ap.add_argument("--steps", type=int, default=100)
@@ -94,7 +98,8 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
-    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "surrogate": run_surrogate}[args.workload](args)
+    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "surrogate": run_surrogate,
+     "approx": run_approx}[args.workload](args)
 
 
 def run_main(args):
@@ -221,6 +226,13 @@ def run_main(args):
     d_snap = td.das_beamform(rf_snap, s)
     y_snap = td.apply(kb, R[0])
     out["approx_rel_l2_2d"] = float(torch.linalg.norm(y_snap - d_snap) / torch.linalg.norm(d_snap))
+    # the paper-style 1-D error on the centre line (single scatterers at every row, exact kernels)
+    e1d = line_errors(s, K, dev)["exact"]
+    out["approx_1d"] = {"single_local_sq_median": e1d["single_local_sq_median"],
+                        "single_local_below_5pct": e1d["single_local_below_5pct"],
+                        "single_global_sq_median": e1d["single_global_sq_median"],
+                        "lines_global_sq": {p: e1d[p]["global_sq"] for p in ("5_uniform", "5_rising", "100_uniform")},
+                        "paper_threshold": 0.05}
 
     if not (args.no_parity and args.no_cpu_baseline):
         # host-side inputs for the oracle, built from the seeded generators and
@@ -485,6 +497,95 @@ def run_surrogate(args):
         "per_frame_with_bank_ms": {"surrogate": t_sur + app_ms / nb, "exact": t_ex + app_ms / nb},
         "line_model": {"tflops": tflops, "hbm_gbs_algorithmic": hbm, "hbm_frac": hbm / HBM_PEAK_GBS},
     }
+    print(json.dumps(out), flush=True)
+
+
+def line_errors(setup, K, dev):
+    """Paper-style 1-D error of the line model against DAS on the centre line.
+
+    Single scatterers: the DAS response of a unit scatterer at row s along the
+    whole line is the exact-mode kernel of row s with 2 Z - 1 taps; the line
+    model's response is column s of its banded matrix.  Local error: squared
+    relative l2 error inside the pulse's two-way envelope FWHM around the
+    scatterer; global: over the whole line.  Line phantoms: on-grid on-axis
+    scatterers, RF synthesised and beamformed by DAS on the x = 0 column."""
+    import numpy as np
+    import torch
+
+    import paper_2507_15464_amd as td
+    Z = setup.nz
+    line = setup.replace(nx=1, x0=0.0)
+    zs = setup.z0 + np.arange(Z) * setup.dz
+    big = td.build_kernels(line, K=2 * Z - 1, mode="exact").cpu().numpy().astype(np.float64)
+    H = Z - 1
+    das_cols = np.stack([big[s, H - s:H - s + Z] for s in range(Z)], 1)  # [i][s]: DAS at row i of scatterer s
+    w_fwhm = setup.cycles / setup.fc * setup.c / 2.0
+    local_mask = np.abs(zs[:, None] - zs[None, :]) <= 0.5 * w_fwhm
+    r25, r35 = int(np.argmin(np.abs(zs - 25e-3))), int(np.argmin(np.abs(zs - 35e-3)))
+    banks = {"exact": td.build_kernels(line, K=K, mode="exact"),
+             "paper_ref25mm": td.build_kernels(line, K=K, mode="paper", ref_row=[r25] * Z),
+             "paper_ref35mm": td.build_kernels(line, K=K, mode="paper", ref_row=[r35] * Z)}
+    # line phantoms (on-grid, on-axis), DAS from synthesised RF
+    rows5 = np.linspace(0.15 * Z, 0.85 * Z, 5).round().astype(int)
+    rng = np.random.default_rng(0)
+    rows100 = np.sort(rng.choice(np.arange(int(0.05 * Z), int(0.95 * Z)), 100, replace=False))
+    phantoms = {"5_uniform": (rows5, np.ones(5)), "5_rising": (rows5, np.linspace(0.5, 2.0, 5)),
+                "100_uniform": (rows100, np.ones(100))}
+    out = {}
+    for name, kb in banks.items():
+        M = np.zeros((Z, Z))
+        kbn = kb.cpu().numpy().astype(np.float64)
+        h = (K - 1) // 2
+        for s in range(Z):
+            lo_i, hi_i = max(0, s - h), min(Z, s + h + 1)
+            for i in range(lo_i, hi_i):
+                M[i, s] = kbn[i, i - s + h]
+        d2 = das_cols ** 2
+        e2 = (M - das_cols) ** 2
+        valid = d2.sum(0) > 0
+        glob = e2.sum(0)[valid] / d2.sum(0)[valid]
+        loc_num = (e2 * local_mask).sum(0)
+        loc_den = (d2 * local_mask).sum(0)
+        okl = loc_den > 0
+        loc = loc_num[okl] / loc_den[okl]
+        rec = {"single_local_sq_median": float(np.median(loc)), "single_local_sq_mean": float(np.mean(loc)),
+               "single_local_below_5pct": float(np.mean(loc < 0.05)),
+               "single_global_sq_median": float(np.median(glob)), "single_global_below_5pct": float(np.mean(glob < 0.05))}
+        for pname, (rows, amp) in phantoms.items():
+            scat = torch.tensor(np.stack([np.zeros(rows.size), zs[rows], amp], 1), dtype=torch.float64, device=dev)
+            rf = td.simulate_rf(line, scat)
+            d = td.das_beamform(rf, line).cpu().numpy()[:, 0].astype(np.float64)
+            Rm = np.zeros((Z, 1), np.float32)
+            Rm[rows, 0] = amp
+            y = td.apply(kb, torch.from_numpy(Rm).to(dev)).cpu().numpy()[:, 0].astype(np.float64)
+            near = np.zeros(Z, bool)
+            for r in rows:
+                near |= np.abs(zs - zs[r]) <= 0.5 * w_fwhm
+            rec[pname] = {"global_sq": float(np.sum((y - d) ** 2) / np.sum(d ** 2)),
+                          "local_sq": float(np.sum(((y - d) ** 2)[near]) / np.sum((d ** 2)[near])),
+                          "rel_l2": float(np.linalg.norm(y - d) / np.linalg.norm(d))}
+        out[name] = rec
+    return out
+
+
+def run_approx(args):
+    import torch
+
+    from workloads import config
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    res = {}
+    for k in (1, 2):
+        s = config(k)
+        t0 = time.perf_counter()
+        res[f"config{k}"] = line_errors(s, s.K, dev)
+        log(f"config {k}: {time.perf_counter() - t0:.1f}s")
+    out = {"metric": "paper-style 1-D tiDAS-vs-DAS squared error (on-axis line, plane wave)",
+           "value": res["config2"]["exact"]["single_local_sq_median"], "unit": "squared rel. error (median, local)",
+           "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic on-axis scatterers", "config": {"workload": "configs 1 and 2 geometry, x = 0 column"},
+           "errors": res, "paper_threshold": 0.05}
     print(json.dumps(out), flush=True)
 
 

@@ -61,6 +61,7 @@ struct GemmArgs {
 };
 
 constexpr int GM = 64, GN = 64, GK = 32, GPAD = 8;  // LDS rows of GK + GPAD bfloat16
+static_assert(GM == GN, "operand staging assumes square tiles");
 
 template <int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
@@ -71,23 +72,59 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
     const int m0 = blockIdx.x * GM, n0 = blockIdx.y * GN;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lq = lane >> 4;
+    // split-K: slice blockIdx.z of gridDim.z covers [kbeg, kend), a whole number of GK chunks
+    const int kper = ((g.K + (int)gridDim.z - 1) / (int)gridDim.z + GK - 1) / GK * GK;
+    const int kbeg = blockIdx.z * kper;
+    const int kend = min(g.K, kbeg + kper);
     floatx4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += GK) {
+    // each thread stages 8 elements of each operand per chunk; the next
+    // chunk's loads are issued before the current chunk's MFMAs
+    constexpr int PER = (GM * GK) / 256;
+    uint16_t ra[PER], rb[PER];
+    // element e of a chunk maps to (row, k) k-fastest when the operand is
+    // k-contiguous in memory and row-fastest otherwise, so neighbouring
+    // threads read neighbouring addresses in both layouts
+    const bool a_kfast = g.sak == 1, b_kfast = g.sbk == 1;
+    auto rk = [](int e, bool kfast, int& r, int& k) {
+        if (kfast) {
+            r = e / GK;
+            k = e % GK;
+        } else {
+            r = e % GM;
+            k = e / GM;
+        }
+    };
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int j = 0; j < (GM * GK) / 256; ++j) {
+        for (int j = 0; j < PER; ++j) {
             const int e = tid + 256 * j;
-            const int r = e / GK, k = e % GK;
+            int r, k;
+            rk(e, a_kfast, r, k);
             const int m = m0 + r, kk = k0 + k;
-            As[r][k] = (m < g.M && kk < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)kk * g.sak] : (uint16_t)0;
-            const int n = n0 + r;
-            Bs[r][k] = (n < g.N && kk < g.K) ? g.B[(int64_t)kk * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
+            ra[j] = (m < g.M && kk < kend) ? g.A[(int64_t)m * g.sam + (int64_t)kk * g.sak] : (uint16_t)0;
+            rk(e, b_kfast, r, k);
+            const int n = n0 + r, kn = k0 + k;
+            rb[j] = (n < g.N && kn < kend) ? g.B[(int64_t)kn * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
+        }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = tid + 256 * j;
+            int r, k;
+            rk(e, a_kfast, r, k);
+            As[r][k] = ra[j];
+            rk(e, b_kfast, r, k);
+            Bs[r][k] = rb[j];
         }
         __syncthreads();
+        if (k0 + GK < kend) load(k0 + GK);
         bf16x8 af[2], bfr[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) af[a] = *reinterpret_cast<const bf16x8*>(&As[wr + 16 * a + li][8 * lq]);
@@ -100,6 +137,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
         __syncthreads();
     }
 
+    // split-K partials go to slice blockIdx.z of c32 (reduced afterwards)
+    float* c32 = g.c32 + (int64_t)blockIdx.z * g.M * g.ldc;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -111,7 +150,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
                 if (m >= g.M || n >= g.N) continue;
                 const float v = acc[a][b][r];
                 if (EPI == EPI_STORE) {
-                    g.c32[(int64_t)m * g.ldc + n] = v;
+                    c32[(int64_t)m * g.ldc + n] = v;
                 } else if (EPI == EPI_BIAS_GELU) {
                     const float z = v + g.bias[n];
                     g.c32[(int64_t)m * g.ldc + n] = z;
@@ -128,8 +167,18 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
             }
 }
 
-static void gemm(int epi, const GemmArgs& g, hipStream_t s) {
-    const dim3 grid((g.M + GM - 1) / GM, (g.N + GN - 1) / GN), block(256);
+// out[m][n] = sum_s part[s][m][n] in slice order (deterministic split-K reduction)
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int32_t S, int64_t mn,
+                                                            float* __restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mn; e += (int64_t)gridDim.x * 256) {
+        float s = 0.0f;
+        for (int i = 0; i < S; ++i) s += part[(int64_t)i * mn + e];
+        out[e] = s;
+    }
+}
+
+static void gemm(int epi, const GemmArgs& g, hipStream_t s, int splits = 1) {
+    const dim3 grid((g.M + GM - 1) / GM, (g.N + GN - 1) / GN, splits), block(256);
     switch (epi) {
         case EPI_STORE: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_STORE>, grid, block, 0, s, g); break;
         case EPI_BIAS_GELU: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_BIAS_GELU>, grid, block, 0, s, g); break;
@@ -175,23 +224,37 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict_
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// one workgroup adds the per-block partial sums (tree order fixed: deterministic)
 __global__ __launch_bounds__(256) void loss_finish_kernel(const double* __restrict__ partial, int32_t nblk, double inv_n,
                                                           float* __restrict__ loss) {
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < nblk; ++i) s += partial[i];
-        *loss = (float)(s * inv_n);
-    }
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) s += partial[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *loss = (float)((red[0] + red[1] + red[2] + red[3]) * inv_n);
 }
 
-// db[o] = sum_b g[b][o] (fixed order: deterministic)
-__global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ g, int32_t N, int32_t O,
-                                                     float* __restrict__ db) {
-    const int o = blockIdx.x * 256 + threadIdx.x;
-    if (o >= O) return;
+// db[o] = sum_b g[b][o]: 64 columns per workgroup, 16 row lanes each summing a
+// strided subset, then the 16 partial sums added in lane order (deterministic)
+__global__ __launch_bounds__(1024) void colsum_kernel(const float* __restrict__ g, int32_t N, int32_t O,
+                                                      float* __restrict__ db) {
+    __shared__ float part[16][65];
+    const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + c;
     float s = 0.0f;
-    for (int b = 0; b < N; ++b) s += g[(int64_t)b * O + o];
-    db[o] = s;
+    if (o < O) {
+#pragma unroll 8
+        for (int b = rl; b < N; b += 16) s += g[(int64_t)b * O + o];
+    }
+    part[rl][c] = s;
+    __syncthreads();
+    if (rl == 0 && o < O) {
+        float t = 0.0f;
+        for (int i = 0; i < 16; ++i) t += part[i][c];
+        db[o] = t;
+    }
 }
 
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const float* __restrict__ gr,
@@ -289,12 +352,16 @@ struct MlpWork {
     float* g32[4];
     uint16_t* g16[4];
     double* partial;
+    float* splitk;  // split-K partial products of the weight gradients
     size_t bytes;
 };
 
 constexpr int LOSS_BLOCKS = 256;
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// weight-gradient products run over the batch: one k-slice per 256 rows (at most 8)
+static int wgrad_splits(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(8, N / 256)); }
 
 static MlpWork carve(const MlpLayout& L, int64_t N, void* base) {
     MlpWork w{};
@@ -317,6 +384,9 @@ static MlpWork carve(const MlpLayout& L, int64_t N, void* base) {
         w.g16[l] = (uint16_t*)take(2 * N * L.w[l + 1]);
     }
     w.partial = (double*)take(8 * LOSS_BLOCKS);
+    int64_t mn = 0;
+    for (int l = 0; l < 4; ++l) mn = std::max<int64_t>(mn, (int64_t)L.w[l] * L.w[l + 1]);
+    w.splitk = (float*)take(4 * (size_t)wgrad_splits(N) * mn);
     w.bytes = off;
     return w;
 }
@@ -413,7 +483,7 @@ extern "C" int32_t tidas_mlp_train_step(const int32_t* widths, const uint16_t* p
     const int64_t ny = (int64_t)N * L.w[4];
     hipLaunchKernelGGL(loss_grad_kernel, dim3(LOSS_BLOCKS), dim3(256), 0, s, w.y, w.t, ny, (float)(1.0 / (double)ny),
                        w.g32[3], w.g16[3], w.partial);
-    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(64), 0, s, w.partial, LOSS_BLOCKS, 1.0 / (double)ny, loss);
+    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(256), 0, s, w.partial, LOSS_BLOCKS, 1.0 / (double)ny, loss);
     for (int l = 3; l >= 0; --l) {
         const uint16_t* h_in = (l == 0) ? w.x16 : w.h16[l - 1];
         const int in = L.w[l], out = L.w[l + 1];
@@ -428,10 +498,19 @@ extern "C" int32_t tidas_mlp_train_step(const int32_t* widths, const uint16_t* p
         gw.M = out;
         gw.N = in;
         gw.K = N;
-        gw.c32 = grad + L.off_w[l];
         gw.ldc = in;
-        gemm(EPI_STORE, gw, s);
-        hipLaunchKernelGGL(colsum_kernel, dim3((out + 255) / 256), dim3(256), 0, s, w.g32[l], N, out, grad + L.off_b[l]);
+        const int S = wgrad_splits(N);
+        if (S > 1) {
+            gw.c32 = w.splitk;
+            gemm(EPI_STORE, gw, s, S);
+            const int64_t mn = (int64_t)out * in;
+            hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)std::min<int64_t>((mn + 255) / 256, 1024)), dim3(256),
+                               0, s, w.splitk, S, mn, grad + L.off_w[l]);
+        } else {
+            gw.c32 = grad + L.off_w[l];
+            gemm(EPI_STORE, gw, s);
+        }
+        hipLaunchKernelGGL(colsum_kernel, dim3((out + 63) / 64), dim3(1024), 0, s, w.g32[l], N, out, grad + L.off_b[l]);
         if (l > 0) {
             // g_{l-1}[b][i] = (sum_o g_l[b][o] W_l[o][i]) * GELU'(z_{l-1}[b][i])
             GemmArgs gd{};
