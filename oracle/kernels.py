@@ -25,6 +25,13 @@ scatterer of amplitude 1 before its FP32 rounding.
   squares solution of the first line of eqn:theta,
   theta_i = sum_B a_i b_i / sum_B a_i^2 (its time-domain form, Plancherel);
   finally K[i] = theta_i * h_{r(i)}.
+
+* line mode (Sec. 2.4, eqn:line_conv taken literally): the line model is
+  Theta times the fixed-delay beamformer of the RF.  By Born linearity its
+  exact form on a reflectivity map has, for output row i and source row
+  i - m, the kernel K[i][m+h] = theta_i * F_r[RF1 at z_{i-m}](z_i): the
+  fixed-delay response of the source scatterer read at the output depth,
+  scaled by the output row's weight.  theta_i and r(i) as in paper mode.
 """
 import numpy as np
 
@@ -144,12 +151,31 @@ def fine_half_length(fs, sigma):
     return int(np.ceil(2.0 * pulse_mod.TRUNC_SIGMAS * sigma * fs))
 
 
-def paper_kernels(z_rows, dz, K, ref_rows=None, **setup):
+def fixed_delay_beamform(rf, z_eval, z_ref, *, n_elem, pitch, c, fs, t0, angles, fnumber):
+    """The fixed-delay line of Sec. 2.3 / 2.4 applied to sampled RF [A][C][T]
+    on the centre line: sum_a sum_n w(-x_n, z_ref) L(RF[a][n], (t(z; a) - D_n(z_ref) - t0) fs)."""
+    rf = np.asarray(rf, np.float64)
+    z_eval = np.asarray(z_eval, np.float64)
+    out = np.zeros(z_eval.shape, np.float64)
+    from .das import lerp_read
+    for ai, alpha in enumerate(angles):
+        t_centre = geometry.tau_tx(0.0, z_eval, alpha, c) + z_eval / c
+        for n, xn in enumerate(geometry.element_x(n_elem, pitch)):
+            w = geometry.hann_apod(-xn, z_ref, fnumber)
+            u = (t_centre - geometry.receive_delay(xn, z_ref, c) - t0) * fs
+            out += w * lerp_read(rf[ai, n], u)
+    return out
+
+
+def paper_kernels(z_rows, dz, K, ref_rows=None, line=False, **setup):
     """Paper-mode kernel bank [Z][K] and weights theta [Z].
 
     ref_rows[i] is the row whose depth supplies the frozen receive law for
-    row i (default: the row itself).  Returns (kernels, theta, widths) with
-    widths[i] = W_{r(i)} the FWHM window width in metres.
+    row i (default: the row itself).  line=True gives the line-mode bank
+    (theta_i times the fixed-delay response of each source row at row i)
+    instead of theta_i times the reference response h_r.  Returns
+    (kernels, theta, widths) with widths[i] = W_{r(i)} the FWHM window width
+    in metres.
     """
     z_rows = np.asarray(z_rows, np.float64)
     Z = z_rows.size
@@ -179,6 +205,9 @@ def paper_kernels(z_rows, dz, K, ref_rows=None, **setup):
         a = fixed_delay_line(zq, z_rows[r], z_rows[i], **setup)
         b = unit_das(0.0, zq, 0.0, z_rows[i], **setup)
         theta[i] = theta_ls(a, b)
-        kernels[i] = theta[i] * h_ref[r]
+        if line:
+            kernels[i] = theta[i] * fixed_delay_line(z_rows[i], z_rows[r], z_rows[i] - m_axis * dz, **setup)
+        else:
+            kernels[i] = theta[i] * h_ref[r]
         widths[i] = W
     return kernels, theta, widths

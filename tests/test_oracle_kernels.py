@@ -166,3 +166,40 @@ def test_paper_theta_drops_away_from_reference():
     kb, th, W = kernels.paper_kernels(zr[rows], s.dz, 65, ref_rows=np.searchsorted(rows, ref[rows]), **oracle_kw(s))
     assert abs(th[2] - 1.0) < 0.05
     assert abs(th[0] - 1.0) > abs(th[2] - 1.0)
+
+
+def test_line_mode_reproduces_the_rf_domain_line_model():
+    """eqn:line_conv taken literally: Theta times the fixed-delay beamformer of
+    the RF.  For an on-axis line phantom the line-mode kernels applied to the
+    reflectivity map equal Theta times the fixed-delay beamformer run on the
+    synthesised RF (Born linearity), up to rounding."""
+    from oracle import tidas
+    from workloads import generators
+    s = C1.replace(n_samples=2000)
+    zs = s.z0 + np.arange(s.nz) * s.dz
+    rows = np.arange(40, 200)
+    zr = zs[rows]
+    ref = np.searchsorted(rows, 120)
+    kb, th, _ = kernels.paper_kernels(zr, s.dz, 33, ref_rows=np.full(rows.size, ref), line=True, **oracle_kw(s))
+    src = np.array([20, 21, 55, 90, 91, 140])
+    amp = generators.normal(src.size, seed=4)
+    R = np.zeros((rows.size, 1))
+    R[src, 0] = amp
+    y = tidas.apply(kb, R)[:, 0]
+    rf = simulate.simulate_rf(np.zeros(src.size), zr[src], amp, **sim_kw(s))
+    kw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, angles=list(s.angles), fnumber=s.fnumber)
+    f = kernels.fixed_delay_beamform(rf, zr, zr[ref], **kw)
+    assert np.max(np.abs(y - th * f)) <= 1e-12 * np.max(np.abs(th * f))
+
+
+def test_line_mode_single_element_equals_exact():
+    """One element at the probe centre: the fixed delay law is the DAS law, so
+    theta = 1 and, on a depth grid of one two-way sample (linear interpolation
+    then reads the echo at the same fractional position for source and output
+    shifts), the line-mode kernel equals the exact one."""
+    s = C1.replace(n_elem=1, n_samples=3000, dz=C1.c / (2 * C1.fs))
+    zr = s.z0 + np.arange(40, 60) * s.dz
+    kb, th, _ = kernels.paper_kernels(zr, s.dz, 33, line=True, **oracle_kw(s))
+    ref = kernels.exact_kernels(zr, s.dz, 33, **oracle_kw(s))
+    assert np.allclose(th, 1.0, rtol=0, atol=1e-12)
+    assert np.max(np.abs(kb - ref)) < 1e-12 * np.max(np.abs(ref))
