@@ -524,7 +524,9 @@ def line_errors(setup, K, dev):
     r25, r35 = int(np.argmin(np.abs(zs - 25e-3))), int(np.argmin(np.abs(zs - 35e-3)))
     banks = {"exact": td.build_kernels(line, K=K, mode="exact"),
              "paper_ref25mm": td.build_kernels(line, K=K, mode="paper", ref_row=[r25] * Z),
-             "paper_ref35mm": td.build_kernels(line, K=K, mode="paper", ref_row=[r35] * Z)}
+             "paper_ref35mm": td.build_kernels(line, K=K, mode="paper", ref_row=[r35] * Z),
+             "line_ref25mm": td.build_kernels(line, K=K, mode="line", ref_row=[r25] * Z),
+             "line_own_rows": td.build_kernels(line, K=K, mode="line")}
     # line phantoms (on-grid, on-axis), DAS from synthesised RF
     rows5 = np.linspace(0.15 * Z, 0.85 * Z, 5).round().astype(int)
     rng = np.random.default_rng(0)

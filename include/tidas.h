@@ -62,6 +62,7 @@ extern "C" {
 
 #define TIDAS_MODE_EXACT 0 /* kernel = DAS PSF of a unit scatterer (Sec. 2.2 eq:PSF)        */
 #define TIDAS_MODE_PAPER 1 /* kernel = theta x fixed-delay response (Sec. 2.3, eqn:theta)  */
+#define TIDAS_MODE_LINE 2  /* kernel = theta x fixed-delay line on the RF (Sec. 2.4)       */
 
 /* Linear array: element count C >= 1, pitch > 0, speed of sound c > 0 (Sec. 2.1). */
 typedef struct tidas_array {
@@ -140,9 +141,13 @@ int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_r
  *                z_i] and b = DAS of the unit echo at z_i (first line of
  *                eqn:theta, time domain), 0 when sum a^2 = 0,
  *     kernels[i][m+h] = theta_i * h_r[m].
+ * mode TIDAS_MODE_LINE (Sec. 2.4, eqn:line_conv: Theta times the fixed-delay
+ *   beamformer of the RF, expressed on the reflectivity by Born linearity):
+ *   theta_i, r and W_r as in paper mode, and
+ *     kernels[i][m+h] = theta_i * F_r[unit echo at z_i - m dz](z_i).
  * kernels DEV [nz][K]; theta DEV [nz] or NULL (exact mode writes 1).
  * ref_row HOST [nz] with 0 <= ref_row[i] < nz, or NULL.  K odd, >= 1.
- * Paper mode allocates and frees a small temporary device buffer,
+ * Paper and line modes allocate and free a small temporary device buffer,
  * stream-ordered (TIDAS_ENOMEM possible), uploads the row -> reference map,
  * and returns only after the stream has drained (synchronous).
  */

@@ -18,6 +18,7 @@ TIDAS_ENOMEM = -3
 TIDAS_EUNSUPPORTED = -4
 MODE_EXACT = 0
 MODE_PAPER = 1
+MODE_LINE = 2
 
 
 class TidasError(RuntimeError):

@@ -70,7 +70,7 @@ def build_kernels(setup, grid=None, K=None, mode="exact", ref_row=None, n_sample
     lib = _lib.load()
     K = int(K if K is not None else setup.K)
     T = int(n_samples if n_samples is not None else setup.n_samples)
-    m = {"exact": _lib.MODE_EXACT, "paper": _lib.MODE_PAPER}[mode]
+    m = {"exact": _lib.MODE_EXACT, "paper": _lib.MODE_PAPER, "line": _lib.MODE_LINE}[mode]
     dev = torch.device("cuda", torch.cuda.current_device())
     kb = torch.empty((grid.nz, K), device=dev, dtype=torch.float32)
     th = torch.empty(grid.nz, device=dev, dtype=torch.float32) if with_theta else None

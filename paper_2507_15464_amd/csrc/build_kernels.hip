@@ -16,6 +16,12 @@
 //                     signal), and the FWHM;
 //   paper_row_kernel  one workgroup per row: a_i and b_i on the window, the
 //                     two dot products, theta_i, and the scaled kernel row.
+//
+// Line mode (Sec. 2.4, eqn:line_conv read literally: Theta times the
+// fixed-delay beamformer of the RF): same theta_i and reference rows as paper
+// mode, but tap m of row i is theta_i times the fixed-delay response, read at
+// z_i, of a unit scatterer at the source row's depth z_i - m dz (Born
+// linearity turns the RF-domain model into this gather on the reflectivity).
 #include <algorithm>
 #include <vector>
 
@@ -198,7 +204,7 @@ __global__ __launch_bounds__(PAPER_THREADS) void paper_row_kernel(const Setup64 
                                                                   const int32_t* __restrict__ ref_of_row,
                                                                   const int32_t* __restrict__ refs,
                                                                   const double* __restrict__ h_ref,
-                                                                  const double* __restrict__ width,
+                                                                  const double* __restrict__ width, int32_t line,
                                                                   float* __restrict__ kb, float* __restrict__ theta) {
     __shared__ double red[PAPER_THREADS / 64];
     const int i = blockIdx.x;
@@ -220,7 +226,11 @@ __global__ __launch_bounds__(PAPER_THREADS) void paper_row_kernel(const Setup64 
     ab = block_sum(ab, red);
     aa = block_sum(aa, red);
     const double th = (aa > 0.0) ? ab / aa : 0.0;
-    for (int t = threadIdx.x; t < K; t += PAPER_THREADS) kb[(size_t)i * K + t] = (float)(th * h_ref[(size_t)u * K + t]);
+    const int h = (K - 1) / 2;
+    for (int t = threadIdx.x; t < K; t += PAPER_THREADS) {
+        const double k = line ? fixed_delay(s, zi, zr, zi - (double)(t - h) * dz) : h_ref[(size_t)u * K + t];
+        kb[(size_t)i * K + t] = (float)(th * k);
+    }
     if (theta && threadIdx.x == 0) theta[i] = (float)th;
 }
 
@@ -343,8 +353,8 @@ extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx*
     if (!kernels) return fail(TIDAS_EINVAL, "tidas_build_kernels: null kernels pointer");
     if (n_samples < 2) return fail(TIDAS_EINVAL, "tidas_build_kernels: n_samples must be >= 2");
     if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_build_kernels: K must be odd and >= 1");
-    if (mode != TIDAS_MODE_EXACT && mode != TIDAS_MODE_PAPER)
-        return fail(TIDAS_EINVAL, "tidas_build_kernels: mode must be 0 (exact) or 1 (paper)");
+    if (mode != TIDAS_MODE_EXACT && mode != TIDAS_MODE_PAPER && mode != TIDAS_MODE_LINE)
+        return fail(TIDAS_EINVAL, "tidas_build_kernels: mode must be 0 (exact), 1 (paper) or 2 (line)");
     if ((void*)kernels == (void*)theta) return fail(TIDAS_EINVAL, "tidas_build_kernels: theta aliases kernels");
     const int Z = grid->nz;
     if (ref_row)
@@ -362,7 +372,7 @@ extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx*
         return check_launch("tidas_build_kernels(exact)");
     }
 
-    // paper mode: distinct reference rows and the row -> reference map
+    // paper and line modes: distinct reference rows and the row -> reference map
     const int Qf = (int)std::ceil(8.0 * s.sigma * s.fs);
     if (2 * Qf + 1 > FINE_MAX) return fail(TIDAS_EUNSUPPORTED, "tidas_build_kernels: pulse too long for the fine axis");
     std::vector<int32_t> refs;
@@ -397,7 +407,7 @@ extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx*
     }
     if (!st) {
         hipLaunchKernelGGL(paper_row_kernel, dim3((unsigned)Z), dim3(PAPER_THREADS), 0, strm, s, K, grid->z0, grid->dz,
-                           d_map, d_refs, h_ref, width, kernels, theta);
+                           d_map, d_refs, h_ref, width, (int32_t)(mode == TIDAS_MODE_LINE), kernels, theta);
         st = check_launch("tidas_build_kernels(paper, rows)");
     }
     // the host staging vector must outlive the copy: order it before returning

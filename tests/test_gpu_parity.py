@@ -225,6 +225,30 @@ def test_build_paper_kernels_config2_sampled_rows(dev):
     assert np.max(np.abs(th.cpu().numpy()[rows] - th_ref)) <= 1e-6 * np.max(np.abs(th_ref))
 
 
+def test_build_line_kernels_single_reference_25mm(dev):
+    """Line mode: theta times the fixed-delay response of each source row, one
+    delay curve at 25 mm for the whole line."""
+    s = config(1)
+    _, zs = axes(s)
+    r = int(np.argmin(np.abs(zs - 25e-3)))
+    kb, th = td.build_kernels(s, mode="line", ref_row=[r] * s.nz, with_theta=True)
+    rows = np.arange(0, s.nz, 7)
+    z_rows = np.concatenate([[zs[r]], zs[rows]])
+    ref, th_ref, _ = o_k.paper_kernels(z_rows, s.dz, s.K, ref_rows=np.zeros(z_rows.size, int), line=True,
+                                       **oracle_kw(s))
+    assert rel(kb.cpu().numpy()[rows], ref[1:]) <= RTOL
+    assert np.max(np.abs(th.cpu().numpy()[rows] - th_ref[1:])) <= 1e-6 * np.max(np.abs(th_ref))
+
+
+def test_build_line_kernels_config2_sampled_rows(dev):
+    s = config(2)
+    _, zs = axes(s)
+    kb = td.build_kernels(s, mode="line")
+    rows = np.arange(5, s.nz, 97)
+    ref, _, _ = o_k.paper_kernels(zs[rows], s.dz, s.K, line=True, **oracle_kw(s))
+    assert rel(kb.cpu().numpy()[rows], ref) <= RTOL
+
+
 # ----------------------------------------------------------- synthesis ----
 def test_simulate_rf_matches_oracle(dev):
     for s, n in ((config(1), 20), (config(3).replace(n_samples=1500), 7)):
