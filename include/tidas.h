@@ -16,6 +16,9 @@
  *   tidas_apply_ex, tidas_adjoint_ex, tidas_deconvolve, tidas_operator_norm_sq
  *                        fused forms and the Tikhonov deconvolution built on
  *                        the line model (abstract; Sec. 1; Sec. 4)
+ *   tidas_prepare, tidas_apply_prepared, tidas_adjoint_prepared
+ *                        the line model with its kernel bank converted once
+ *                        into the form its matrix-core kernels read
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -187,6 +190,34 @@ int32_t tidas_apply_ex(const float* kernels, int32_t K, const float* refl, int32
                        float alpha, float beta, const float* base, float* image, void* stream);
 int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float* image_bar, int32_t B, int32_t Z, int32_t X,
                          float alpha, float beta, const float* base, float* refl_bar, void* stream);
+
+/*
+ * Prepared kernel bank.  The line model's kernels (Sec. 2.4, eqn:line_conv)
+ * depend on the geometry only, so a caller that applies one bank to many
+ * frames can convert it once: tidas_prepare writes, for the forward operator
+ * and its adjoint, the banded matrix of every 64-row tile of the bank with
+ * each float32 tap cut exactly into three bfloat16 parts (the form the
+ * split-bfloat16 matrix-core kernels of tidas_apply read; tidas_apply builds
+ * it in a temporary buffer on every call).  tidas_apply_prepared and
+ * tidas_adjoint_prepared then give the same results as tidas_apply_ex and
+ * tidas_adjoint_ex on that bank, bit for bit.
+ *
+ * tidas_prepared_bytes: size of the prepared form for K taps and Z rows; 0
+ * when K is even, < 1, or too large for the matrix-core tiles (K > 321).
+ * tidas_prepare: kernels DEV [Z][K] -> prepared DEV, >= tidas_prepared_bytes
+ * bytes, 16-byte aligned, owned by the caller, valid until the bank changes.
+ * TIDAS_EUNSUPPORTED when tidas_prepared_bytes is 0 for a valid odd K.
+ * tidas_apply_prepared / tidas_adjoint_prepared: the fused forms above with
+ * the prepared bank of the same K and Z in place of the kernels;
+ * TIDAS_EUNSUPPORTED when the frame is too large for the matrix-core tiles
+ * (then use tidas_apply_ex / tidas_adjoint_ex).
+ */
+size_t tidas_prepared_bytes(int32_t K, int32_t Z);
+int32_t tidas_prepare(const float* kernels, int32_t K, int32_t Z, void* prepared, size_t bytes, void* stream);
+int32_t tidas_apply_prepared(const void* prepared, int32_t K, const float* refl, int32_t B, int32_t Z, int32_t X,
+                             float alpha, float beta, const float* base, float* image, void* stream);
+int32_t tidas_adjoint_prepared(const void* prepared, int32_t K, const float* image_bar, int32_t B, int32_t Z,
+                               int32_t X, float alpha, float beta, const float* base, float* refl_bar, void* stream);
 
 /*
  * Tikhonov-regularised deconvolution through the line model (the paper

@@ -69,6 +69,10 @@ _SIGS = {
     "tidas_simulate_rf": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), _P, _I, _I, _P, _P]),
     "tidas_apply_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_adjoint_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
+    "tidas_prepared_bytes": (ctypes.c_size_t, [_I, _I]),
+    "tidas_prepare": (_I, [_P, _I, _I, _P, ctypes.c_size_t, _P]),
+    "tidas_apply_prepared": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
+    "tidas_adjoint_prepared": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_deconvolve": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _I, _P, _P, _P]),
     "tidas_operator_norm_sq": (_I, [_P, _I, _I, _I, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "tidas_batch_workspace_bytes": (ctypes.c_size_t, [_I]),

@@ -86,7 +86,66 @@ def build_kernels(setup, grid=None, K=None, mode="exact", ref_row=None, n_sample
     return (kb, th) if with_theta else kb
 
 
+class Prepared:
+    """A kernel bank converted once by ``tidas_prepare`` (forward and adjoint
+    band tiles in split-bfloat16 form).  Pass it wherever a kernel bank is
+    taken; results equal those of the bank itself, bit for bit.  Valid while
+    the bank it was made from is unchanged."""
+
+    def __init__(self, kernels):
+        lib = _lib.load()
+        _check_tensor(kernels, "kernels")
+        if kernels.dim() != 2:
+            raise ValueError("kernels must be [Z][K]")
+        self.Z, self.K = int(kernels.shape[0]), int(kernels.shape[1])
+        nbytes = lib.tidas_prepared_bytes(self.K, self.Z)
+        if nbytes == 0:
+            raise _lib.TidasError(_lib.TIDAS_EUNSUPPORTED, f"no prepared form for K={self.K}")
+        self.buffer = torch.empty(nbytes, device=kernels.device, dtype=torch.uint8)
+        _lib.check(lib.tidas_prepare(_ptr(kernels), self.K, self.Z, _ptr(self.buffer), nbytes, _stream()))
+        self.device = kernels.device
+        self.shape = (self.Z, self.K)
+
+
+def prepare(kernels):
+    """Convert a kernel bank [Z][K] once for repeated ``apply`` / ``adjoint``."""
+    return Prepared(kernels)
+
+
+def conv_ex(adj, kernels, x, alpha=1.0, beta=0.0, base=None, out=None):
+    """alpha * A(x) + beta * base (adj: A^T); kernels a bank [Z][K] or a Prepared."""
+    lib = _lib.load()
+    _check_tensor(x, "input")
+    x3 = x.unsqueeze(0) if x.dim() == 2 else x
+    if x3.dim() != 3:
+        raise ValueError("the input must be [B][Z][X] or [Z][X]")
+    B, Z, X = x3.shape
+    if base is not None:
+        _check_tensor(base, "base")
+        if base.numel() != x3.numel():
+            raise ValueError("base must have the input's shape")
+    if out is None:
+        out = torch.empty_like(x3)
+    _check_tensor(out, "out")
+    if isinstance(kernels, Prepared):
+        if kernels.Z != Z:
+            raise ValueError("the prepared bank's Z differs from the input's")
+        fn = "tidas_adjoint_prepared" if adj else "tidas_apply_prepared"
+        ptr, K = _ptr(kernels.buffer), kernels.K
+    else:
+        _check_tensor(kernels, "kernels")
+        if kernels.dim() != 2 or kernels.shape[0] != Z:
+            raise ValueError("kernels must be [Z][K] with the input's Z")
+        fn = "tidas_adjoint_ex" if adj else "tidas_apply_ex"
+        ptr, K = _ptr(kernels), kernels.shape[1]
+    _lib.check(getattr(lib, fn)(ptr, K, _ptr(x3), B, Z, X, ctypes.c_float(alpha), ctypes.c_float(beta), _ptr(base),
+                                _ptr(out), _stream()))
+    return out.view(x.shape)
+
+
 def _conv(fn, kernels, x, out):
+    if isinstance(kernels, Prepared):
+        return conv_ex(fn == "tidas_adjoint", kernels, x, out=out)
     lib = _lib.load()
     _check_tensor(kernels, "kernels")
     _check_tensor(x, "input")

@@ -15,7 +15,7 @@ import ctypes
 import torch
 
 from . import _lib
-from .api import _check_tensor, _ptr, _stream, adjoint, apply
+from .api import Prepared, _check_tensor, _ptr, _stream, adjoint, apply, conv_ex
 
 __all__ = ["TiDASFunction", "tidas", "apply_ex", "adjoint_ex", "deconvolve", "operator_norm_sq", "step_size"]
 
@@ -23,12 +23,16 @@ __all__ = ["TiDASFunction", "tidas", "apply_ex", "adjoint_ex", "deconvolve", "op
 class TiDASFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, refl, kernels):
-        ctx.save_for_backward(kernels)
+        if isinstance(kernels, Prepared):
+            ctx.prepared = kernels
+        else:
+            ctx.prepared = None
+            ctx.save_for_backward(kernels)
         return apply(kernels, refl.contiguous())
 
     @staticmethod
     def backward(ctx, grad_out):
-        (kernels,) = ctx.saved_tensors
+        kernels = ctx.prepared if ctx.prepared is not None else ctx.saved_tensors[0]
         return adjoint(kernels, grad_out.contiguous()), None
 
 
@@ -37,34 +41,14 @@ def tidas(refl, kernels):
     return TiDASFunction.apply(refl, kernels)
 
 
-def _ex(fn, kernels, x, alpha, beta, base, out):
-    lib = _lib.load()
-    _check_tensor(kernels, "kernels")
-    _check_tensor(x, "input")
-    x3 = x.unsqueeze(0) if x.dim() == 2 else x
-    B, Z, X = x3.shape
-    if kernels.dim() != 2 or kernels.shape[0] != Z:
-        raise ValueError("kernels must be [Z][K] with the input's Z")
-    if base is not None:
-        _check_tensor(base, "base")
-        if base.numel() != x3.numel():
-            raise ValueError("base must have the input's shape")
-    if out is None:
-        out = torch.empty_like(x3)
-    _check_tensor(out, "out")
-    _lib.check(getattr(lib, fn)(_ptr(kernels), kernels.shape[1], _ptr(x3), B, Z, X, ctypes.c_float(alpha),
-                                ctypes.c_float(beta), _ptr(base), _ptr(out), _stream()))
-    return out.view(x.shape)
-
-
 def apply_ex(kernels, refl, alpha=1.0, beta=0.0, base=None, out=None):
-    """out = alpha * A(refl) + beta * base (base may be ``out`` itself)."""
-    return _ex("tidas_apply_ex", kernels, refl, alpha, beta, base, out)
+    """out = alpha * A(refl) + beta * base (base may be ``out`` itself); kernels a bank or a Prepared."""
+    return conv_ex(False, kernels, refl, alpha, beta, base, out)
 
 
 def adjoint_ex(kernels, image_bar, alpha=1.0, beta=0.0, base=None, out=None):
-    """out = alpha * A^T(image_bar) + beta * base (base may be ``out`` itself)."""
-    return _ex("tidas_adjoint_ex", kernels, image_bar, alpha, beta, base, out)
+    """out = alpha * A^T(image_bar) + beta * base (base may be ``out`` itself); kernels a bank or a Prepared."""
+    return conv_ex(True, kernels, image_bar, alpha, beta, base, out)
 
 
 def operator_norm_sq(kernels, iters=100):

@@ -27,6 +27,8 @@
 // tiles (consecutive depth tiles of one column strip), which keeps the shared
 // halo rows in that XCD's L2.
 #include <algorithm>
+#include <climits>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -423,6 +425,455 @@ __global__ __launch_bounds__(MF_THREADS) void tidas_batch_kernel(const ConvFrame
     }
 }
 
+// ------------------------------------------------------------------------
+// Split-bfloat16 matrix-core path (preferred whenever its LDS tile fits).
+// The same banded product on v_mfma_f32_32x32x16_bf16.  Every float32 operand
+// v is cut exactly, by truncation, into three bfloat16 parts v = v0 + v1 + v2:
+// v0 = the top 16 bits of v, v1 = the top 16 bits of r1 = v - v0 (exact: r1
+// has at most 16 significant bits), v2 = r1 - v1 (at most 8 significant bits,
+// so exactly a bfloat16).  A product a b is taken as the six terms
+//   a0 b0 + a0 b1 + a1 b0 + a0 b2 + a1 b1 + a2 b0,
+// each exact in float32, accumulated in float32; the dropped a1 b2 + a2 b1 +
+// a2 b2 is below 2^-20 |a b| (|a1| < 2^-7 |a|, |a2| < 2^-14 |a|), so the sum
+// carries float32-level error (the split-bfloat16 scheme of Henry, Tang and
+// Heinecke, ARITH 2019).  Six products at the dense bf16 matrix rate are
+// 2.6x the float32 matrix rate: the line model becomes bound by memory
+// instead of the matrix cores.  Non-finite inputs give NaN.
+//
+// Tile: 64 output rows x 256 columns, 4 waves.  Wave w owns columns 64 w ..
+// +63 as two chains (chain c of lane column j is image column 2 j + c, so an
+// 8-byte load of two consecutive columns feeds both) and all 64 rows as two
+// 32-row M-blocks: 4 accumulators of 32 x 32.  Operand layouts of the
+// instruction: A lane l holds A[l % 32][8 (l / 32) .. +7], B lane l holds
+// B[8 (l / 32) .. +7][l % 32], register i of D lane l holds
+// D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].  The k dimension walks the
+// tile's source window [i0 - h, i0 - h + 16 NS) in steps of 16 rows: per
+// step lane (j, g) loads window rows 16 s + 8 g .. +7 at its two columns
+// (eight coalesced 8-byte loads), splits them in registers, and M-block b
+// runs the six products for the steps its band [32 b, 32 b + 31 + 2h] meets.
+// The loads run BX_PD - 1 steps ahead through a register ring.  The tile's
+// band matrix, M[r][c] = K[i0 + r][r - c + 2h] (adjoint: K[i0 - h + c][c - r];
+// zero off the band and outside the bank), is split once into three bfloat16
+// planes in LDS with a row stride of 8 (mod 16) bf16, so the 16-byte A reads
+// of eight consecutive rows hit distinct banks, and it serves nf consecutive
+// frames (same rows and columns); the ring runs on across frame boundaries.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int BX_TZ = 64;        // output rows per tile (two 32-row M-blocks)
+constexpr int BX_TN = 256;       // columns per tile
+constexpr int BX_THREADS = 256;  // 4 waves
+constexpr int BX_PD = 4;         // register ring: the current step and three in flight
+
+// k-steps per tile, rounded up to whole groups of BX_PD (the extra steps meet a
+// zero band and cost matrix work only)
+__host__ __device__ constexpr int bx_nsteps(int K) { return ((BX_TZ + K - 1 + 15) / 16 + 3) / 4 * 4; }
+__host__ __device__ constexpr int bx_lstride(int K) { return 16 * bx_nsteps(K) + 8; }
+__host__ __device__ constexpr size_t bx_lds_bytes(int K) { return (size_t)3 * BX_TZ * bx_lstride(K) * 2; }
+
+// A wave-uniform pointer moved into scalar registers (a buffer descriptor
+// built from a pointer the compiler cannot prove uniform costs a loop per load).
+__device__ __forceinline__ const float* uniform_ptr(const float* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const float*>(((uint64_t)hi << 32) | lo);
+}
+
+// bfloat16 parts of the exact split, each as the top half of a 32-bit word
+__device__ __forceinline__ void split3(float v, uint32_t& w0, uint32_t& w1, uint32_t& w2) {
+    const uint32_t u = __float_as_uint(v);
+    const float r1 = v - __uint_as_float(u & 0xffff0000u);
+    const uint32_t u1 = __float_as_uint(r1);
+    const float r2 = r1 - __uint_as_float(u1 & 0xffff0000u);
+    w0 = u;
+    w1 = u1;
+    w2 = __float_as_uint(r2);
+}
+
+// eight words -> eight bfloat16 (top halves), element e in half (e & 1) of word e / 2
+__device__ __forceinline__ bf16x8 pack8(const uint32_t (&w)[8]) {
+    u32x4 p;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) p[d] = (w[2 * d] >> 16) | (w[2 * d + 1] & 0xffff0000u);
+    return __builtin_bit_cast(bf16x8, p);
+}
+
+// The tile's band matrix in split form ("band image"): three planes of
+// [64][LS] bfloat16, entry (r, c) = M[r][c] of the 64-row tile at i0, zero off
+// the band, outside the bank and in the padding columns c >= 16 NS.
+__host__ __device__ constexpr size_t bx_band_bytes(int K) { return bx_lds_bytes(K); }
+
+template <bool ADJ>
+__device__ __forceinline__ float bx_band_value(const float* __restrict__ Kb, int K, int Z, int i0, int r, int c) {
+    const int h = (K - 1) >> 1;
+    const int t = ADJ ? c - r : r - c + 2 * h;
+    const int row = ADJ ? i0 - h + c : i0 + r;
+    const bool ok = c < 16 * bx_nsteps(K) && t >= 0 && t < K && row >= 0 && row < Z;
+    return ok ? Kb[(size_t)row * K + t] : 0.0f;
+}
+
+template <bool ADJ>
+__device__ __forceinline__ void bx_band_put(uint16_t* img, int plane, int o, float v) {
+    uint32_t w0, w1, w2;
+    split3(v, w0, w1, w2);
+    img[o] = (uint16_t)(w0 >> 16);
+    img[plane + o] = (uint16_t)(w1 >> 16);
+    img[2 * plane + o] = (uint16_t)(w2 >> 16);
+}
+
+// Band images of every 64-row tile of a bank, mode mode0 + blockIdx.z (0
+// forward, 1 adjoint), tile rt at prepared + (blockIdx.z n_rt + rt) bx_band_bytes(K).
+__global__ __launch_bounds__(256) void bx_prepare_kernel(const float* __restrict__ Kb, int32_t K, int32_t Z,
+                                                         int32_t n_rt, uint16_t* __restrict__ prepared, int32_t mode0) {
+    const int LS = bx_lstride(K);
+    const int rt = blockIdx.y, adj = mode0 + (int)blockIdx.z;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= BX_TZ * LS) return;
+    const int r = e / LS, c = e - (e / LS) * LS;
+    uint16_t* img = prepared + (size_t)(blockIdx.z * n_rt + rt) * (bx_band_bytes(K) / 2);
+    const float v = adj ? bx_band_value<true>(Kb, K, Z, rt * BX_TZ, r, c) : bx_band_value<false>(Kb, K, Z, rt * BX_TZ, r, c);
+    bx_band_put<false>(img, BX_TZ * LS, e, v);
+}
+
+// Band image into LDS.  From a prepared image: a straight copy by
+// direct-to-LDS 16-byte loads (every wave load moves 1 KB; the image is a
+// whole number of them since LS = 0 (mod 8)).  From the bank: a rolled loop
+// over the entries (the ragged batch path, whose frames each bring a bank).
+template <bool ADJ>
+__device__ __forceinline__ void bx_band_to_lds(const uint16_t* __restrict__ img, const float* __restrict__ Kb, int K,
+                                               int Z, int i0, uint16_t* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (img) {
+        const int n_loads = (int)(bx_band_bytes(K) / 1024);
+        const auto rs = make_rsrc(img, (uint32_t)bx_band_bytes(K));
+        for (int q = wave; q < n_loads; q += BX_THREADS / 64)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(lds + q * 512), 16,
+                                                     q * 1024 + lane * 16, 0, 0, 0);
+        __builtin_amdgcn_s_waitcnt(0);  // the copy is in LDS (also drains the input prefetch)
+    } else {
+        const int LS = bx_lstride(K);
+        const int n = BX_TZ * LS;
+#pragma unroll 4
+        for (int e = threadIdx.x; e < n; e += BX_THREADS) {
+            const int r = e / LS, c = e - r * LS;
+            bx_band_put<ADJ>(lds, n, e, bx_band_value<ADJ>(Kb, K, Z, i0, r, c));
+        }
+    }
+}
+
+// nf consecutive frames (stride Z X floats) of one 64 x 256 tile.  All threads
+// of the workgroup call it (it contains barriers).  VEC: X % 4 == 0 and
+// 16-byte aligned rows (one 8-byte load / store per lane and row); otherwise
+// dword accesses.
+template <bool ADJ, bool VEC>
+__device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const float* __restrict__ Kb,
+                                        const float* __restrict__ In, float* Out, const float* Base, int nf,
+                                        float alpha, float beta, int K, int Z, int X, int i0, int j0, uint16_t* lds) {
+    const int h = (K - 1) >> 1;
+    const int NS = bx_nsteps(K);
+    const int LS = bx_lstride(K);
+    const int plane = BX_TZ * LS;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = lane & 31, g = lane >> 5;
+    const int col = j0 + 64 * wave + 2 * j;
+    const size_t fstride = (size_t)Z * X;
+    const uint32_t frame_bytes = (uint32_t)(fstride * sizeof(float));
+    const int row_bytes = X * 4;
+    // byte offset of window row 8 g at this lane's columns; rows above the image
+    // are negative (huge unsigned), rows below are past the end: both read 0
+    const int off0 = ((i0 - h + 8 * g) * X + col) * 4;
+
+    // rows of step s of frame f; !valid (past the last step) reads nothing:
+    // the offsets are pushed out of range, so the loads return 0 without traffic
+    auto load8 = [&](int f, int s, bool valid, floatx2(&x)[8]) {
+        // the frame index is wave-uniform; say so, or the descriptor is built per lane
+        const int fu = __builtin_amdgcn_readfirstlane(valid ? f : 0);
+        const int so = __builtin_amdgcn_readfirstlane(valid ? s * 16 * row_bytes : INT32_MIN - off0);
+        const auto rs = make_rsrc(uniform_ptr(In + (size_t)fu * fstride), frame_bytes);
+        const int o = off0 + so;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (VEC) {
+                x[e] = __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, o + e * row_bytes, 0, 0));
+            } else {
+                x[e][0] = buffer_load_f32(rs, o + e * row_bytes);
+                x[e][1] = buffer_load_f32(rs, o + e * row_bytes + 4);
+            }
+        }
+    };
+
+    floatx2 ring[BX_PD][8];
+    // step s' of frame f' for the prefetch BX_PD - 1 steps ahead of step s of frame f
+    auto ahead = [&](int f, int s, int& fn, int& sn) {
+        sn = s + BX_PD - 1;
+        fn = f;
+        if (sn >= NS) {  // NS >= BX_PD: at most one wrap
+            sn -= NS;
+            ++fn;
+        }
+    };
+    // first steps' input loads in flight while the band image is brought in
+#pragma unroll
+    for (int u = 0; u < BX_PD - 1; ++u) load8(0, u, true, ring[u]);
+    bx_band_to_lds<ADJ>(img, Kb, K, Z, i0, lds);
+    __syncthreads();
+
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[b][c][i] = 0.0f;
+
+    const uint16_t* a_base = lds + j * LS + 8 * g;
+    constexpr int TA[6] = {0, 0, 1, 0, 1, 2};
+    constexpr int TB[6] = {0, 1, 0, 2, 1, 0};
+
+    // Results of frame f.  Every store and base load is issued (rows past Z and
+    // columns past X get an out-of-range offset, which the buffer unit drops or
+    // reads as 0): conditional memory operations would make the wait counts
+    // after the epilogue drain the whole prefetch ring.
+    const int vbase = ((i0 + 4 * g) * X + col) * 4;
+    constexpr int OOB = INT32_MIN;
+    auto store_frame = [&](int f) {
+        const auto rs_o = make_rsrc(uniform_ptr(Out + (size_t)f * fstride), frame_bytes);
+        const bool has_base = Base != nullptr;
+        const auto rs_b = make_rsrc(uniform_ptr((has_base ? Base : Out) + (size_t)f * fstride), frame_bytes);
+        // lane offset of row rr of the tile, chain c (OOB when outside the image);
+        // VEC accesses both chains at the chain-0 offset (X % 4 == 0 and col is
+        // even, so col < X implies col + 1 < X)
+        auto voff = [&](int rr, int c) {
+            const bool ok = i0 + 4 * g + rr < Z && col + c < X;
+            return ok ? vbase + rr * row_bytes + 4 * c : OOB;
+        };
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            floatx2 v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = floatx2{alpha * acc[b][0][i], alpha * acc[b][1][i]};
+            if (has_base) {  // all base loads of the M-block first, then the updates
+                floatx2 bv[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int rr = 32 * b + 8 * (i >> 2) + (i & 3);
+                    if (VEC) {
+                        bv[i] = __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs_b, voff(rr, 0), 0, 0));
+                    } else {
+                        bv[i][0] = buffer_load_f32(rs_b, voff(rr, 0));
+                        bv[i][1] = buffer_load_f32(rs_b, voff(rr, 1));
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    v[i][0] = fmaf(beta, bv[i][0], v[i][0]);
+                    v[i][1] = fmaf(beta, bv[i][1], v[i][1]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int rr = 32 * b + 8 * (i >> 2) + (i & 3);
+                if (VEC) {
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[i]), rs_o, voff(rr, 0), 0, 0);
+                } else {
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[i][0]), rs_o, voff(rr, 0), 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[i][1]), rs_o, voff(rr, 1), 0, 0);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[b][c][i] = 0.0f;
+        }
+    };
+
+    // step s of frame f on ring slot U = s % BX_PD; first refill slot
+    // (U + BX_PD - 1) % BX_PD (consumed by the previous step) BX_PD - 1 steps ahead
+    auto step = [&](auto U_, int f, int s) {
+        constexpr int U = decltype(U_)::value;
+        {
+            int fn, sn;
+            ahead(f, s, fn, sn);
+            load8(fn, sn, fn < nf, ring[(U + BX_PD - 1) % BX_PD]);
+        }
+        // keep the prefetch at the top of the step: the scheduler would sink the
+        // loads below the matrix instructions to shorten their live ranges
+        __builtin_amdgcn_sched_barrier(0);
+        // both M-blocks on every step: outside a block's band its A is zero, and
+        // straight-line code keeps the accumulators in place (no joins)
+        bf16x8 A[2][3];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                A[b][p] = *reinterpret_cast<const bf16x8*>(a_base + p * plane + 32 * b * LS + 16 * s);
+        bf16x8 Bp[2][3];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            uint32_t w0[8], w1[8], w2[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) split3(ring[U][e][c], w0[e], w1[e], w2[e]);
+            Bp[c][0] = pack8(w0);
+            Bp[c][1] = pack8(w1);
+            Bp[c][2] = pack8(w2);
+        }
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][TA[t]], Bp[c][TB[t]], acc[b][c], 0, 0, 0);
+    };
+
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    static_assert(BX_PD == 4, "the unrolled ring below has four slots");
+    // NS is a multiple of four: each frame is whole groups of four straight-line
+    // steps (fixed ring slots), and the epilogue sits outside the group loop, so
+    // the wait counts before each step leave the younger steps' loads in flight
+    for (int f = 0; f < nf; ++f) {
+        for (int s = 0; s < NS; s += BX_PD) {
+            step(I0{}, f, s);
+            step(I1{}, f, s + 1);
+            step(I2{}, f, s + 2);
+            step(I3{}, f, s + 3);
+        }
+        store_frame(f);
+    }
+}
+
+struct BxGeom {
+    int32_t K, B, Z, X, nf;
+    int32_t n_rt, n_ct, n_blocks;
+    float alpha, beta;
+    const float* base;
+};
+
+template <bool ADJ, bool VEC>
+__global__ __launch_bounds__(BX_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void tidas_bx6_kernel(
+    const BxGeom g, const uint16_t* __restrict__ images, const float* __restrict__ In, float* Out) {
+    extern __shared__ uint16_t bx_smem[];
+    const int lg = xcd_remap(blockIdx.x, g.n_blocks);
+    const int rt = lg % g.n_rt;
+    const int ct = (lg / g.n_rt) % g.n_ct;
+    const int fg = lg / (g.n_rt * g.n_ct);
+    const int f0 = fg * g.nf;
+    const int nf = min(g.nf, g.B - f0);
+    const size_t fo = (size_t)f0 * g.Z * g.X;
+    const uint16_t* img = images + (size_t)rt * (bx_band_bytes(g.K) / 2);
+    bx_tile<ADJ, VEC>(img, nullptr, In + fo, Out + fo, g.base ? g.base + fo : nullptr, nf, g.alpha, g.beta, g.K, g.Z,
+                      g.X, rt * BX_TZ, ct * BX_TN, bx_smem);
+}
+
+// Ragged batch on the split-bfloat16 tile: as tidas_batch_kernel, over the
+// 64 x 256 tiles of all frames (one frame per tile visit).
+// One tile of the persistent batch kernel, kept out of line: inlined into the
+// tile loop, the loop-invariant parts of the band fill are hoisted out of it
+// and hold registers through the whole tile.
+template <bool VEC>
+__device__ __attribute__((noinline)) void bx_batch_tile(const float* Kb, const float* In, float* Out, int K, int Z,
+                                                        int X, int i0, int j0) {
+    extern __shared__ uint16_t bx_smem[];
+    bx_tile<false, VEC>(nullptr, Kb, In, Out, nullptr, 1, 1.0f, 0.0f, K, Z, X, i0, j0, bx_smem);
+}
+
+// VEC: every frame of the table is a VEC frame (the host launches the VEC and
+// the other frames as two tables, so one kernel inlines one tile variant).
+template <bool VEC>
+__global__ __launch_bounds__(BX_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void tidas_bx6_batch_kernel(
+    const ConvFrameDev* __restrict__ fr, int32_t n_frames, int64_t total, int32_t K) {
+    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int per_xcd = ((int)gridDim.x - x + 7) >> 3;
+    const int64_t lo = total * x / 8, hi = total * (x + 1) / 8;
+    for (int64_t t = lo + slot; t < hi; t += per_xcd) {
+        int a = 0, b = n_frames - 1;  // largest f with tile_start <= t
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (fr[mid].tile_start <= t) a = mid;
+            else b = mid - 1;
+        }
+        // the table entry is wave-uniform: move it to scalar registers, or every
+        // buffer descriptor built from it becomes a per-lane loop
+        const ConvFrameDev f = fr[__builtin_amdgcn_readfirstlane(a)];
+        const int Zf = __builtin_amdgcn_readfirstlane(f.Z), Xf = __builtin_amdgcn_readfirstlane(f.X);
+        const int64_t local = t - f.tile_start;
+        const int row_tiles = (Zf + BX_TZ - 1) / BX_TZ;
+        const int i0 = __builtin_amdgcn_readfirstlane((int)(local % row_tiles) * BX_TZ);
+        const int j0 = __builtin_amdgcn_readfirstlane((int)(local / row_tiles) * BX_TN);
+        __syncthreads();  // the previous tile's readers of the LDS band are done
+        bx_batch_tile<VEC>(uniform_ptr(f.kernels), uniform_ptr(f.in), const_cast<float*>(uniform_ptr(f.out)), K, Zf,
+                           Xf, i0, j0);
+    }
+}
+
+// The split-bfloat16 tile fits: its LDS band, and every int32 byte offset of
+// the source window (at most K + 160 rows beyond the image) below 2^31.
+static bool bx_fits(int K, int Z, int X) {
+    return bx_lds_bytes(K) <= 160 * 1024 && ((int64_t)Z + 2 * K + 256) * X * 4 < INT32_MAX;
+}
+
+static int device_cu_count() {
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+    }
+    return n_cu;
+}
+
+// Band images of the bank's tiles for modes mode0 .. mode0 + n_modes - 1 (0
+// forward, 1 adjoint): out holds [n_modes][tile][band image].
+static void launch_prepare(const float* kernels, int32_t K, int32_t Z, int mode0, int n_modes, uint16_t* out,
+                           hipStream_t stream) {
+    const int n_rt = (Z + BX_TZ - 1) / BX_TZ;
+    const int per_tile = BX_TZ * bx_lstride(K);
+    const dim3 grid((unsigned)((per_tile + 255) / 256), (unsigned)n_rt, (unsigned)n_modes);
+    hipLaunchKernelGGL(bx_prepare_kernel, grid, dim3(256), 0, stream, kernels, K, Z, n_rt, out, mode0);
+}
+
+static size_t prepared_bytes(int32_t K, int32_t Z, int n_modes) {
+    return (size_t)n_modes * ((Z + BX_TZ - 1) / BX_TZ) * bx_band_bytes(K);
+}
+
+// images: the band images of the operator's mode (forward or adjoint), tile
+// rt at images + rt bx_band_bytes(K) / 2
+static void launch_bx6(bool adj, bool vec, const uint16_t* images, int32_t K, const float* in, int32_t B, int32_t Z,
+                       int32_t X, float alpha, float beta, const float* base, float* out, hipStream_t stream) {
+    BxGeom g;
+    g.K = K;
+    g.B = B;
+    g.Z = Z;
+    g.X = X;
+    g.n_rt = (Z + BX_TZ - 1) / BX_TZ;
+    g.n_ct = (X + BX_TN - 1) / BX_TN;
+    // frames per workgroup: about two workgroups per compute unit in one
+    // round; each reuses its band for its frames
+    const int64_t tiles = (int64_t)g.n_rt * g.n_ct;
+    const int64_t per_round = 2 * (int64_t)device_cu_count();
+    g.nf = (int32_t)std::max<int64_t>(1, std::min<int64_t>(B, tiles * B / per_round));
+    g.n_blocks = (int32_t)(tiles * ((B + g.nf - 1) / g.nf));
+    g.alpha = alpha;
+    g.beta = beta;
+    g.base = base;
+    const size_t lds = bx_lds_bytes(K);
+    const dim3 grid(g.n_blocks), block(BX_THREADS);
+    if (adj) {
+        if (vec) hipLaunchKernelGGL((tidas_bx6_kernel<true, true>), grid, block, lds, stream, g, images, in, out);
+        else hipLaunchKernelGGL((tidas_bx6_kernel<true, false>), grid, block, lds, stream, g, images, in, out);
+    } else {
+        if (vec) hipLaunchKernelGGL((tidas_bx6_kernel<false, true>), grid, block, lds, stream, g, images, in, out);
+        else hipLaunchKernelGGL((tidas_bx6_kernel<false, false>), grid, block, lds, stream, g, images, in, out);
+    }
+}
+
 static bool mfma_fits(int K, int Z, int X) {
     // LDS tile fits; every int32 byte offset,
     // including rows prefetched past the band (< K + 4 PD + 64 rows beyond
@@ -462,23 +913,53 @@ constexpr size_t LDS_LIMIT = 160 * 1024;
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-// Validate, pick the matrix-core or the VALU kernel, launch.  Enqueues nothing
-// when it returns TIDAS_EINVAL / TIDAS_EUNSUPPORTED.
-static int32_t conv_launch(bool adj, const char* name, const float* kernels, int32_t K, const float* in, int32_t B,
-                           int32_t Z, int32_t X, float alpha, float beta, const float* base, float* out,
-                           hipStream_t stream) {
+static int32_t conv_validate(const char* name, const void* kernels, int32_t K, const float* in, int32_t B, int32_t Z,
+                             int32_t X, float alpha, float beta, const float* base, const float* out) {
     if (!kernels || !in || !out) return fail(TIDAS_EINVAL, std::string(name) + ": null pointer");
     if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, std::string(name) + ": K must be odd and >= 1");
     if (B < 1 || Z < 1 || X < 1) return fail(TIDAS_EINVAL, std::string(name) + ": B, Z, X must be >= 1");
-    if ((const void*)in == (const void*)out || (const void*)kernels == (const void*)out)
+    if ((const void*)in == (const void*)out || kernels == (const void*)out)
         return fail(TIDAS_EINVAL, std::string(name) + ": output aliases an input");
-    if (base && ((const void*)base == (const void*)in || (const void*)base == (const void*)kernels))
+    if (base && ((const void*)base == (const void*)in || (const void*)base == kernels))
         return fail(TIDAS_EINVAL, std::string(name) + ": base aliases an input");
     if (!std::isfinite(alpha) || !std::isfinite(beta))
         return fail(TIDAS_EINVAL, std::string(name) + ": alpha and beta must be finite");
+    return TIDAS_OK;
+}
+
+static bool bx_path(int32_t K, int32_t B, int32_t Z, int32_t X) {
+    return bx_fits(K, Z, X) && (int64_t)((Z + BX_TZ - 1) / BX_TZ) * ((X + BX_TN - 1) / BX_TN) * B <= INT32_MAX;
+}
+
+static bool vec_ok(int32_t X, const float* in, const float* out, const float* base) {
+    return (X % 4) == 0 && aligned16(in) && aligned16(out) && (!base || aligned16(base));
+}
+
+// Validate, pick the matrix-core or the VALU kernel, launch.  Enqueues nothing
+// when it returns TIDAS_EINVAL / TIDAS_EUNSUPPORTED.  The split-bfloat16 path
+// prepares the band images it needs in a stream-ordered temporary buffer.
+static int32_t conv_launch(bool adj, const char* name, const float* kernels, int32_t K, const float* in, int32_t B,
+                           int32_t Z, int32_t X, float alpha, float beta, const float* base, float* out,
+                           hipStream_t stream) {
+    int32_t st = conv_validate(name, kernels, K, in, B, Z, X, alpha, beta, base, out);
+    if (st) return st;
+    const bool vec = vec_ok(X, in, out, base);
+    if (bx_path(K, B, Z, X)) {
+        // the images of this one mode
+        void* buf = nullptr;
+        if ((st = check_hip(hipMallocAsync(&buf, prepared_bytes(K, Z, 1), stream), "band buffer")))
+            return st;
+        launch_prepare(kernels, K, Z, adj ? 1 : 0, 1, (uint16_t*)buf, stream);
+        st = check_launch(name);
+        if (!st) {
+            launch_bx6(adj, vec, (const uint16_t*)buf, K, in, B, Z, X, alpha, beta, base, out, stream);
+            st = check_launch(name);
+        }
+        const int32_t st2 = check_hip(hipFreeAsync(buf, stream), "band buffer");
+        return st ? st : st2;
+    }
     const bool use_mfma = mfma_fits(K, Z, X) && (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX;
     if (use_mfma) {
-        const bool vec = (X % 4) == 0 && aligned16(in) && aligned16(out) && (!base || aligned16(base));
         launch_mfma(adj, vec, kernels, K, in, B, Z, X, alpha, beta, base, out, stream);
         return check_launch(name);
     }
@@ -505,6 +986,18 @@ static int32_t conv_launch(bool adj, const char* name, const float* kernels, int
     else
         hipLaunchKernelGGL((tidas_fwd_kernel<CONV_RZ, CONV_WAVES>), dim3(g.n_blocks), dim3(CONV_WAVES * 64), lds,
                            stream, g, kernels, in, out);
+    return check_launch(name);
+}
+
+// The split-bfloat16 operator on prepared band images of one mode.
+static int32_t conv_launch_images(bool adj, const char* name, const uint16_t* images, int32_t K, const float* in,
+                                  int32_t B, int32_t Z, int32_t X, float alpha, float beta, const float* base,
+                                  float* out, hipStream_t stream) {
+    int32_t st = conv_validate(name, images, K, in, B, Z, X, alpha, beta, base, out);
+    if (st) return st;
+    if (!bx_path(K, B, Z, X))
+        return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": K or the frame size is outside the prepared path");
+    launch_bx6(adj, vec_ok(X, in, out, base), images, K, in, B, Z, X, alpha, beta, base, out, stream);
     return check_launch(name);
 }
 
@@ -561,6 +1054,39 @@ extern "C" int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float
                        (hipStream_t)stream);
 }
 
+extern "C" size_t tidas_prepared_bytes(int32_t K, int32_t Z) {
+    if (K < 1 || (K % 2) == 0 || Z < 1 || bx_lds_bytes(K) > 160 * 1024) return 0;
+    return prepared_bytes(K, Z, 2);
+}
+
+extern "C" int32_t tidas_prepare(const float* kernels, int32_t K, int32_t Z, void* prepared, size_t bytes,
+                                 void* stream) {
+    if (!kernels || !prepared) return fail(TIDAS_EINVAL, "tidas_prepare: null pointer");
+    if (K < 1 || (K % 2) == 0 || Z < 1) return fail(TIDAS_EINVAL, "tidas_prepare: K odd >= 1 and Z >= 1 required");
+    if (bx_lds_bytes(K) > 160 * 1024) return fail(TIDAS_EUNSUPPORTED, "tidas_prepare: K too large for the prepared path");
+    if (bytes < prepared_bytes(K, Z, 2)) return fail(TIDAS_EINVAL, "tidas_prepare: buffer smaller than tidas_prepared_bytes");
+    if ((reinterpret_cast<uintptr_t>(prepared) & 15) != 0) return fail(TIDAS_EINVAL, "tidas_prepare: buffer not 16-byte aligned");
+    if ((const void*)kernels == prepared) return fail(TIDAS_EINVAL, "tidas_prepare: output aliases the bank");
+    launch_prepare(kernels, K, Z, 0, 2, (uint16_t*)prepared, (hipStream_t)stream);
+    return check_launch("tidas_prepare");
+}
+
+extern "C" int32_t tidas_apply_prepared(const void* prepared, int32_t K, const float* refl, int32_t B, int32_t Z,
+                                        int32_t X, float alpha, float beta, const float* base, float* image,
+                                        void* stream) {
+    return conv_launch_images(false, "tidas_apply_prepared", (const uint16_t*)prepared, K, refl, B, Z, X, alpha, beta,
+                              base, image, (hipStream_t)stream);
+}
+
+extern "C" int32_t tidas_adjoint_prepared(const void* prepared, int32_t K, const float* image_bar, int32_t B,
+                                          int32_t Z, int32_t X, float alpha, float beta, const float* base,
+                                          float* refl_bar, void* stream) {
+    const uint16_t* adj = prepared ? (const uint16_t*)prepared + prepared_bytes(K, Z, 1) / 2 : nullptr;
+    if (K < 1 || (K % 2) == 0 || Z < 1) adj = (const uint16_t*)prepared;  // validation reports the sizes
+    return conv_launch_images(true, "tidas_adjoint_prepared", adj, K, image_bar, B, Z, X, alpha, beta, base, refl_bar,
+                              (hipStream_t)stream);
+}
+
 extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float* y, int32_t B, int32_t Z, int32_t X,
                                     float lam, float eta, int32_t iters, float* r, float* work, void* stream) {
     if (!y || !r || !work || !kernels) return fail(TIDAS_EINVAL, "tidas_deconvolve: null pointer");
@@ -579,11 +1105,30 @@ extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float
                        0.0f);
     int32_t st = check_launch("tidas_deconvolve(zero)");
     const float decay = 1.0f - eta * lam;
+    // the band images of both modes once for all iterations
+    void* imgs = nullptr;
+    const bool bx = bx_path(K, B, Z, X);
+    if (!st && bx && !(st = check_hip(hipMallocAsync(&imgs, prepared_bytes(K, Z, 2), s), "tidas_deconvolve: bands"))) {
+        launch_prepare(kernels, K, Z, 0, 2, (uint16_t*)imgs, s);
+        st = check_launch("tidas_deconvolve(prepare)");
+    }
+    const uint16_t* fwd = (const uint16_t*)imgs;
+    const uint16_t* adj = fwd ? fwd + prepared_bytes(K, Z, 1) / 2 : nullptr;
     for (int it = 0; it < iters && !st; ++it) {
         // work = A r - y ;  r = -eta A^T work + (1 - eta lam) r
-        st = conv_launch(false, "tidas_deconvolve(residual)", kernels, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
-        if (!st)
-            st = conv_launch(true, "tidas_deconvolve(update)", kernels, K, work, B, Z, X, -eta, decay, r, r, s);
+        if (bx) {
+            st = conv_launch_images(false, "tidas_deconvolve(residual)", fwd, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
+            if (!st)
+                st = conv_launch_images(true, "tidas_deconvolve(update)", adj, K, work, B, Z, X, -eta, decay, r, r, s);
+        } else {
+            st = conv_launch(false, "tidas_deconvolve(residual)", kernels, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
+            if (!st)
+                st = conv_launch(true, "tidas_deconvolve(update)", kernels, K, work, B, Z, X, -eta, decay, r, r, s);
+        }
+    }
+    if (imgs) {
+        const int32_t st2 = check_hip(hipFreeAsync(imgs, s), "tidas_deconvolve: bands");
+        if (!st) st = st2;
     }
     return st;
 }
@@ -602,15 +1147,32 @@ extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((Z + 255) / 256, 65536)), dim3(256), 0, s, v,
                        (int64_t)Z, 1.0f);
     int32_t st = check_launch("tidas_operator_norm_sq(init)");
+    void* imgs = nullptr;
+    const bool bx = bx_path(K, 1, Z, 1);
+    if (!st && bx && !(st = check_hip(hipMallocAsync(&imgs, prepared_bytes(K, Z, 2), s), "tidas_operator_norm_sq: bands"))) {
+        launch_prepare(kernels, K, Z, 0, 2, (uint16_t*)imgs, s);
+        st = check_launch("tidas_operator_norm_sq(prepare)");
+    }
+    const uint16_t* fwd = (const uint16_t*)imgs;
+    const uint16_t* adj = fwd ? fwd + prepared_bytes(K, Z, 1) / 2 : nullptr;
     for (int it = 0; it < iters && !st; ++it) {
         // v <- A^T A v / ||A^T A v||; the last norm is the largest eigenvalue of A^T A
-        st = conv_launch(false, "tidas_operator_norm_sq", kernels, K, v, 1, Z, 1, 1.0f, 0.0f, nullptr, av, s);
-        if (!st) st = conv_launch(true, "tidas_operator_norm_sq", kernels, K, av, 1, Z, 1, 1.0f, 0.0f, nullptr, w, s);
+        if (bx) {
+            st = conv_launch_images(false, "tidas_operator_norm_sq", fwd, K, v, 1, Z, 1, 1.0f, 0.0f, nullptr, av, s);
+            if (!st) st = conv_launch_images(true, "tidas_operator_norm_sq", adj, K, av, 1, Z, 1, 1.0f, 0.0f, nullptr, w, s);
+        } else {
+            st = conv_launch(false, "tidas_operator_norm_sq", kernels, K, v, 1, Z, 1, 1.0f, 0.0f, nullptr, av, s);
+            if (!st) st = conv_launch(true, "tidas_operator_norm_sq", kernels, K, av, 1, Z, 1, 1.0f, 0.0f, nullptr, w, s);
+        }
         if (!st) {
             hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, w, Z, nrm);
             st = check_launch("tidas_operator_norm_sq(normalize)");
         }
         std::swap(v, w);
+    }
+    if (imgs) {
+        const int32_t st2 = check_hip(hipFreeAsync(imgs, s), "tidas_operator_norm_sq: bands");
+        if (!st) st = st2;
     }
     if (!st) st = check_hip(hipMemcpyAsync(out, nrm, sizeof(double), hipMemcpyDeviceToHost, s), "norm download");
     if (!st) st = check_hip(hipStreamSynchronize(s), "tidas_operator_norm_sq: synchronize");
@@ -624,12 +1186,17 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
     if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_apply_batch: K must be odd and >= 1");
     if (variant < 0 || variant >= TIDAS_APPLY_BATCH_VARIANTS)
         return fail(TIDAS_EINVAL, "tidas_apply_batch: variant out of range");
+    // the same arithmetic as tidas_apply on each frame: the split-bfloat16
+    // tiles when the band fits, else the float32 matrix-core tiles
+    const bool bx = bx_lds_bytes(K) <= 160 * 1024;
+    const int TZ = bx ? BX_TZ : MF_TZ, TN = bx ? BX_TN : MF_TN;
     std::vector<ConvFrameDev> tab(n_frames);
     int64_t total = 0;
     for (int f = 0; f < n_frames; ++f) {
         const tidas_frame& fr = frames[f];
         const int Z = fr.grid.nz, X = fr.grid.nx;
-        if (!mfma_fits(K, Z, X)) return fail(TIDAS_EUNSUPPORTED, "tidas_apply_batch: frame too large for the tile path");
+        if (!(bx ? bx_fits(K, Z, X) : mfma_fits(K, Z, X)))
+            return fail(TIDAS_EUNSUPPORTED, "tidas_apply_batch: frame too large for the tile path");
         if (fr.in == fr.out || (const void*)fr.kernels == (const void*)fr.out)
             return fail(TIDAS_EINVAL, "tidas_apply_batch: output aliases an input");
         tab[f].kernels = fr.kernels;
@@ -640,17 +1207,47 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
         tab[f].vec = (X % 4) == 0 && aligned16(fr.in) && aligned16(fr.out);
         tab[f].pad = 0;
         tab[f].tile_start = total;
-        total += (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN);
+        total += (int64_t)((Z + TZ - 1) / TZ) * ((X + TN - 1) / TN);
+    }
+    // split-bfloat16 tiles: VEC frames first, then the others, each group with
+    // its own tile numbering (one launch per group)
+    int n_vec = 0;
+    int64_t total_vec = 0, total_other = 0;
+    if (bx) {
+        std::stable_partition(tab.begin(), tab.end(), [](const ConvFrameDev& e) { return e.vec != 0; });
+        for (auto& e : tab) {
+            const int64_t tiles = (int64_t)((e.Z + TZ - 1) / TZ) * ((e.X + TN - 1) / TN);
+            if (e.vec) {
+                e.tile_start = total_vec;
+                total_vec += tiles;
+                ++n_vec;
+            } else {
+                e.tile_start = total_other;
+                total_other += tiles;
+            }
+        }
     }
     hipStream_t s = (hipStream_t)stream;
     // hipMemcpyAsync from pageable memory returns once the source is staged
     if ((st = check_hip(hipMemcpyAsync(workspace, tab.data(), sizeof(ConvFrameDev) * n_frames, hipMemcpyHostToDevice, s),
                         "tidas_apply_batch: table upload")))
         return st;
-    int dev = 0, n_cu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+    const int n_cu = device_cu_count();
+    const ConvFrameDev* d = (const ConvFrameDev*)workspace;
+    if (bx) {
+        // variants: workgroups per compute unit
+        static const int bx_per_cu[TIDAS_APPLY_BATCH_VARIANTS] = {1, 2, 3, 4, 6, 8};
+        auto grid_for = [&](int64_t t) {
+            const int64_t nb = std::max<int64_t>(8, std::min<int64_t>(t, (int64_t)n_cu * bx_per_cu[variant]));
+            return (unsigned)((nb + 7) / 8 * 8);
+        };
+        if (n_vec > 0)
+            hipLaunchKernelGGL(tidas_bx6_batch_kernel<true>, dim3(grid_for(total_vec)), dim3(BX_THREADS),
+                               bx_lds_bytes(K), s, d, n_vec, total_vec, K);
+        if (n_vec < n_frames)
+            hipLaunchKernelGGL(tidas_bx6_batch_kernel<false>, dim3(grid_for(total_other)), dim3(BX_THREADS),
+                               bx_lds_bytes(K), s, d + n_vec, n_frames - n_vec, total_other, K);
+        return check_launch("tidas_apply_batch");
     }
     const int pd_sel = variant % 3, per_cu = (variant / 3) == 0 ? 2 : 4;
     // a multiple of 8 workgroups: the tile list is cut into 8 chunks, one per
@@ -658,7 +1255,6 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
     const int64_t nb = std::max<int64_t>(8, std::min<int64_t>(total, (int64_t)n_cu * per_cu));
     const unsigned nblk = (unsigned)((nb + 7) / 8 * 8);
     const size_t lds = mf_lds_bytes(K);
-    const ConvFrameDev* d = (const ConvFrameDev*)workspace;
     if (pd_sel == 0) hipLaunchKernelGGL(tidas_batch_kernel<4>, dim3(nblk), dim3(MF_THREADS), lds, s, d, n_frames, total, K);
     else if (pd_sel == 1) hipLaunchKernelGGL(tidas_batch_kernel<8>, dim3(nblk), dim3(MF_THREADS), lds, s, d, n_frames, total, K);
     else hipLaunchKernelGGL(tidas_batch_kernel<16>, dim3(nblk), dim3(MF_THREADS), lds, s, d, n_frames, total, K);

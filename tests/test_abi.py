@@ -171,3 +171,26 @@ def test_batch_entry_points_reject_invalid_arguments(lib):
     assert lib.tidas_apply_batch(bad, 1, 65, ws, need, 0, NUL) == -1                        # empty grid
     bad[0] = _lib.Frame(g, 0x1000, 0x2000, 0x3000, 0)
     assert lib.das_beamform_batch(*geo, 2048, bad, 1, ws, need, 0, NUL) == -1              # null output
+
+
+def test_prepared_bank_size_and_invalid_arguments(lib):
+    # 16 tiles of 64 rows, two modes, three bf16 planes of 64 x 200 (K = 129)
+    assert lib.tidas_prepared_bytes(129, 1024) == 2 * 16 * 3 * 64 * 200 * 2
+    assert lib.tidas_prepared_bytes(129, 1000) == lib.tidas_prepared_bytes(129, 1024)
+    assert lib.tidas_prepared_bytes(64, 1024) == 0      # even K
+    assert lib.tidas_prepared_bytes(0, 1024) == 0
+    assert lib.tidas_prepared_bytes(129, 0) == 0
+    assert lib.tidas_prepared_bytes(401, 1024) == 0     # band tile larger than LDS
+    big = 1 << 30
+    assert lib.tidas_prepare(NUL, 129, 1024, FAKE, big, NUL) == _lib.TIDAS_EINVAL
+    assert lib.tidas_prepare(FAKE, 129, 1024, NUL, big, NUL) == _lib.TIDAS_EINVAL
+    assert lib.tidas_prepare(FAKE, 128, 1024, ctypes.c_void_p(0x2000), big, NUL) == _lib.TIDAS_EINVAL
+    assert lib.tidas_prepare(FAKE, 129, 1024, ctypes.c_void_p(0x2000), 1000, NUL) == _lib.TIDAS_EINVAL  # too small
+    assert lib.tidas_prepare(FAKE, 129, 1024, ctypes.c_void_p(0x2008), big, NUL) == _lib.TIDAS_EINVAL  # misaligned
+    assert lib.tidas_prepare(FAKE, 401, 1024, ctypes.c_void_p(0x2000), big, NUL) == _lib.TIDAS_EUNSUPPORTED
+    f1, f0 = ctypes.c_float(1.0), ctypes.c_float(0.0)
+    for fn in (lib.tidas_apply_prepared, lib.tidas_adjoint_prepared):
+        assert fn(NUL, 129, FAKE, 1, 64, 64, f1, f0, NUL, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EINVAL
+        assert fn(FAKE, 128, FAKE, 1, 64, 64, f1, f0, NUL, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EINVAL
+        assert fn(FAKE, 129, FAKE, 1, 64, 64, f1, f0, NUL, FAKE, NUL) == _lib.TIDAS_EINVAL  # out aliases input
+        assert fn(FAKE, 401, FAKE, 1, 64, 64, f1, f0, NUL, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EUNSUPPORTED

@@ -63,6 +63,31 @@ def test_adjoint_matches_oracle(dev, B, Z, X, K):
     assert np.max(np.abs(r - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("B,Z,X,K", [(2, 129, 130, 129), (3, 100, 70, 65), (1, 1024, 256, 129), (2, 97, 131, 9),
+                                     (1, 300, 1, 33), (1, 64, 64, 1)])
+def test_prepared_bank_matches_the_bank_bit_for_bit(dev, B, Z, X, K):
+    kb = g(generators.normal((Z, K), seed=Z + 3 * K), dev)
+    R = g(generators.normal((B, Z, X), seed=X + B), dev)
+    base = g(generators.normal((B, Z, X), seed=X + B + 1), dev)
+    prep = td.prepare(kb)
+    assert torch.equal(td.apply(prep, R), td.apply(kb, R))
+    assert torch.equal(td.adjoint(prep, R), td.adjoint(kb, R))
+    assert torch.equal(td.apply_ex(prep, R, 0.5, -2.0, base), td.apply_ex(kb, R, 0.5, -2.0, base))
+    assert torch.equal(td.adjoint_ex(prep, R, -1.5, 0.25, base), td.adjoint_ex(kb, R, -1.5, 0.25, base))
+    ref = o_t.apply(kb.cpu().numpy(), R.cpu().numpy())
+    assert rel(td.apply(prep, R).cpu().numpy(), ref) <= RTOL
+
+
+def test_prepared_bank_through_autograd(dev):
+    Z, X, K = 256, 64, 65
+    kb = g(generators.normal((Z, K), seed=21), dev)
+    prep = td.prepare(kb)
+    R = g(generators.normal((Z, X), seed=22), dev).requires_grad_(True)
+    W = g(generators.normal((Z, X), seed=23), dev)
+    (td.tidas(R, prep) * W).sum().backward()
+    assert torch.equal(R.grad, td.adjoint(kb, W))
+
+
 def test_adjoint_dot_product_on_device(dev):
     Z, X, K, B = 700, 190, 129, 2
     kb = g(generators.normal((Z, K), seed=1), dev)
