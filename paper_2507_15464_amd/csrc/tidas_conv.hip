@@ -588,13 +588,17 @@ __device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const 
     // are negative (huge unsigned), rows below are past the end: both read 0
     const int off0 = ((i0 - h + 8 * g) * X + col) * 4;
 
-    // rows of step s of frame f; !valid (past the last step) reads nothing:
-    // the offsets are pushed out of range, so the loads return 0 without traffic
-    auto load8 = [&](int f, int s, bool valid, floatx2(&x)[8]) {
-        // the frame index is wave-uniform; say so, or the descriptor is built per lane
-        const int fu = __builtin_amdgcn_readfirstlane(valid ? f : 0);
+    // buffer descriptor of frame f (frame 0 stands in past the last frame: its
+    // loads are then pushed out of range)
+    auto frame_rsrc = [&](int f) {
+        const int fu = __builtin_amdgcn_readfirstlane(f < nf ? f : 0);  // wave-uniform: keep it scalar
+        return make_rsrc(uniform_ptr(In + (size_t)fu * fstride), frame_bytes);
+    };
+    // rows of local step s through descriptor rs; !valid (past the last frame)
+    // reads nothing: the offsets are pushed out of range, so the loads return 0
+    // without traffic
+    auto load8 = [&](__amdgpu_buffer_rsrc_t rs, int s, bool valid, floatx2(&x)[8]) {
         const int so = __builtin_amdgcn_readfirstlane(valid ? s * 16 * row_bytes : INT32_MIN - off0);
-        const auto rs = make_rsrc(uniform_ptr(In + (size_t)fu * fstride), frame_bytes);
         const int o = off0 + so;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -608,18 +612,25 @@ __device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const 
     };
 
     floatx2 ring[BX_PD][8];
-    // step s' of frame f' for the prefetch BX_PD - 1 steps ahead of step s of frame f
-    auto ahead = [&](int f, int s, int& fn, int& sn) {
-        sn = s + BX_PD - 1;
-        fn = f;
-        if (sn >= NS) {  // NS >= BX_PD: at most one wrap
-            sn -= NS;
-            ++fn;
-        }
+    // Walk order.  The window of the tile at i0 starts i0 / 16 steps after
+    // that of the tile at 0, so the three tiles that read a given input row
+    // read it at local steps 16 apart in rows.  Each tile walks its window
+    // cyclically from local step rot = -i0 / 16 (mod NS): at position q it
+    // takes local step (q + rot) mod NS, whose absolute row position is the
+    // same for every tile, so workgroups that run side by side read each input
+    // row at about the same time and the re-reads hit L2.  (The order of the
+    // k-steps is fixed per tile: results stay deterministic.)
+    const int rot = (NS - (i0 / 16) % NS) % NS;
+    auto local_step = [&](int q) {
+        const int sl = q + rot;
+        return sl >= NS ? sl - NS : sl;
     };
     // first steps' input loads in flight while the band image is brought in
+    {
+        const auto rs0 = frame_rsrc(0);
 #pragma unroll
-    for (int u = 0; u < BX_PD - 1; ++u) load8(0, u, true, ring[u]);
+        for (int u = 0; u < BX_PD - 1; ++u) load8(rs0, local_step(u), true, ring[u]);
+    }
     bx_band_to_lds<ADJ>(img, Kb, K, Z, i0, lds);
     __syncthreads();
 
@@ -692,15 +703,41 @@ __device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const 
         }
     };
 
-    // step s of frame f on ring slot U = s % BX_PD; first refill slot
-    // (U + BX_PD - 1) % BX_PD (consumed by the previous step) BX_PD - 1 steps ahead
-    auto step = [&](auto U_, int f, int s) {
-        constexpr int U = decltype(U_)::value;
-        {
-            int fn, sn;
-            ahead(f, s, fn, sn);
-            load8(fn, sn, fn < nf, ring[(U + BX_PD - 1) % BX_PD]);
+    // position q of frame f on ring slot U = q % BX_PD; first refill slot
+    // (U + BX_PD - 1) % BX_PD (consumed by the previous step) BX_PD - 1 positions ahead
+    // split operand of one ring slot (both chains)
+    auto split_slot = [&](const floatx2(&x)[8], bf16x8(&Bp)[2][3]) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            uint32_t w0[8], w1[8], w2[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) split3(x[e][c], w0[e], w1[e], w2[e]);
+            Bp[c][0] = pack8(w0);
+            Bp[c][1] = pack8(w1);
+            Bp[c][2] = pack8(w2);
         }
+    };
+    // software pipeline: the matrix products of a step use the split operand
+    // made during the previous step, while this step splits the next slot's
+    // rows, so the products never wait on the conversion
+    bf16x8 BpA[2][3], BpB[2][3];
+    split_slot(ring[0], BpA);
+
+    // Position q + U of the current frame; its prefetch targets position
+    // q + U + BX_PD - 1, which lies in the next frame (at q + U + BX_PD - 1 - NS)
+    // when WRAP (the frame's last group of four) and U > 0.  The wrap is known
+    // at compile time, so a step is one basic block.
+    auto step = [&](auto U_, auto WRAP_, int q, __amdgpu_buffer_rsrc_t rs_cur, __amdgpu_buffer_rsrc_t rs_nxt,
+                    bool nxt_valid) {
+        constexpr int U = decltype(U_)::value;
+        constexpr bool WRAP = decltype(WRAP_)::value && U > 0;
+        bf16x8(&Bcur)[2][3] = (U % 2 == 0) ? BpA : BpB;
+        bf16x8(&Bnxt)[2][3] = (U % 2 == 0) ? BpB : BpA;
+        if (WRAP)
+            load8(rs_nxt, local_step(q + U + BX_PD - 1 - NS), nxt_valid, ring[(U + BX_PD - 1) % BX_PD]);
+        else
+            load8(rs_cur, local_step(q + U + BX_PD - 1), true, ring[(U + BX_PD - 1) % BX_PD]);
+        const int s = local_step(q + U);
         // keep the prefetch at the top of the step: the scheduler would sink the
         // loads below the matrix instructions to shorten their live ranges
         __builtin_amdgcn_sched_barrier(0);
@@ -712,23 +749,23 @@ __device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const 
 #pragma unroll
             for (int p = 0; p < 3; ++p)
                 A[b][p] = *reinterpret_cast<const bf16x8*>(a_base + p * plane + 32 * b * LS + 16 * s);
-        bf16x8 Bp[2][3];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            uint32_t w0[8], w1[8], w2[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) split3(ring[U][e][c], w0[e], w1[e], w2[e]);
-            Bp[c][0] = pack8(w0);
-            Bp[c][1] = pack8(w1);
-            Bp[c][2] = pack8(w2);
-        }
 #pragma unroll
         for (int t = 0; t < 6; ++t)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
-                    acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][TA[t]], Bp[c][TB[t]], acc[b][c], 0, 0, 0);
+                    acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][TA[t]], Bcur[c][TB[t]], acc[b][c], 0, 0, 0);
+        split_slot(ring[(U + 1) % BX_PD], Bnxt);
+        // issue order: each matrix product followed by four vector instructions
+        // of the next slot's split.  Instructions issue in order per wave, so a
+        // burst of 24 products would hold the split back until the matrix unit
+        // had accepted them all; interleaved, the split runs under the products.
+#pragma unroll
+        for (int i = 0; i < 24; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // four VALU
+        }
     };
 
     using I0 = std::integral_constant<int, 0>;
@@ -739,13 +776,22 @@ __device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const 
     // NS is a multiple of four: each frame is whole groups of four straight-line
     // steps (fixed ring slots), and the epilogue sits outside the group loop, so
     // the wait counts before each step leave the younger steps' loads in flight
+    using NoWrap = std::false_type;
+    using Wrap = std::true_type;
     for (int f = 0; f < nf; ++f) {
-        for (int s = 0; s < NS; s += BX_PD) {
-            step(I0{}, f, s);
-            step(I1{}, f, s + 1);
-            step(I2{}, f, s + 2);
-            step(I3{}, f, s + 3);
+        const auto rs_cur = frame_rsrc(f), rs_nxt = frame_rsrc(f + 1);
+        const bool nxt_valid = f + 1 < nf;
+        int q = 0;
+        for (; q < NS - BX_PD; q += BX_PD) {
+            step(I0{}, NoWrap{}, q, rs_cur, rs_nxt, nxt_valid);
+            step(I1{}, NoWrap{}, q, rs_cur, rs_nxt, nxt_valid);
+            step(I2{}, NoWrap{}, q, rs_cur, rs_nxt, nxt_valid);
+            step(I3{}, NoWrap{}, q, rs_cur, rs_nxt, nxt_valid);
         }
+        step(I0{}, Wrap{}, q, rs_cur, rs_nxt, nxt_valid);
+        step(I1{}, Wrap{}, q, rs_cur, rs_nxt, nxt_valid);
+        step(I2{}, Wrap{}, q, rs_cur, rs_nxt, nxt_valid);
+        step(I3{}, Wrap{}, q, rs_cur, rs_nxt, nxt_valid);
         store_frame(f);
     }
 }
