@@ -42,7 +42,6 @@ if ROOT not in sys.path:
 
 # MI355X published peaks, and the derived fp32 FMA ceiling of this build's VALU code
 HBM_PEAK_GBS = 8000.0
-FP32_MFMA_TFLOPS = 157.3                                     # dense fp32 matrix peak
 FP32_VALU_NOPACK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6: 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz
 # DAS work per active (pixel, element, angle) term, counted from the definition:
 # receive distance 4 (sub, mul, add, sqrt), index 2, interpolation 3, apodization 3
@@ -72,7 +71,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tidas_mfma_kernel_256x1024_k129_b64_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tidas_bx6_kernel_256x1024_k129_b64_traffic.json")
+BF16_MFMA_TFLOPS = 2500.0                                    # dense bf16 matrix peak
 
 
 def measured_traffic(batch):
@@ -185,6 +185,11 @@ def run_main(args):
     hbm_bytes = (8.0 * Z * X) * B + 4.0 * Z * K       # read R + write Y per frame, kernel bank once
     achieved_tflops = flops / (tid_ms * 1e-3) / 1e12
     achieved_gbs = hbm_bytes / (tid_ms * 1e-3) / 1e9
+    # matrix work the split-bf16 kernel issues: per 64-row tile and column, a
+    # window of 16 NS rows (NS = k-steps rounded up to a multiple of 4), six
+    # bf16 products per float32 product
+    ns = ((64 + K - 1 + 15) // 16 + 3) // 4 * 4
+    mfma_flops = 2.0 * 6 * (16 * ns) * (-(-Z // 64) * 64) * X * B
 
     out = {
         "metric": "frames/s tiDAS vs DAS (256x1024 px, 128 ch) at stated rel-L2 vs FP64 oracle",
@@ -208,10 +213,12 @@ def run_main(args):
                 "ms_per_step": das_ms},
         "tidas_speedup_vs_das": das_ms / tid_ms,
         "kernel_build_s": build_s,
-        "roofline": {"bound": "mfma", "achieved": achieved_tflops, "peak": FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_MFMA_TFLOPS, "traffic": measured_traffic(B),
-                     "kernel": "tidas_mfma_kernel<false>", "flops_per_launch": flops,
-                     "hbm_frac_algorithmic": achieved_gbs / HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(B),
+                     "kernel": "tidas_bx6_kernel<false,true>", "bytes_per_launch": hbm_bytes,
+                     "useful_fp32_tflops": achieved_tflops,
+                     "mfma_bf16_tflops_issued": mfma_flops / (tid_ms * 1e-3) / 1e12,
+                     "mfma_frac": mfma_flops / (tid_ms * 1e-3) / 1e12 / BF16_MFMA_TFLOPS},
     }
 
     # DAS terms per frame: (pixel, element) pairs inside the Hann aperture, times angles

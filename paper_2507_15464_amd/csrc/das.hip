@@ -1,11 +1,13 @@
 // Exact Delay-and-Sum beamformer for plane-wave transmits (Sec. 2, eqn:appF).
 //
-// Mapping on gfx950: one wavefront = 64 consecutive depth rows of ONE image
-// column, a workgroup = 4 columns.  For a fixed element n the 64 lanes then
-// read a short, nearly contiguous window of that element's channel (the
-// sample index grows by ~2 dz fs / c per row), so the channel-major RF reads
-// coalesce into a few cache lines per wave, and the lateral offset
-// x_j - x_n is the same for the whole wave.
+// Mapping on gfx950: one wavefront = a tile of 16 consecutive depth rows x 4
+// consecutive image columns (lane l: row l % 16, column l / 16); a workgroup
+// = 4 such waves stacked in depth (64 rows x 4 columns).  For a fixed element
+// n the wave's 64 lanes then read a short window of that element's channel:
+// the sample index grows by ~2 dz fs / c per row and by less than dx fs / c
+// per column, so a wave-load touches about three cache lines (a 64-row column
+// strip would span ~250 samples, eight lines: the gather path, not the
+// arithmetic, bounds this kernel).
 //
 // Delay precision.  The fractional sample index is split:
 //   u = fs (tau_tx(x_j, z_i; a) + z_i / c - t0)      [per pixel, float64]
@@ -16,9 +18,15 @@
 // at most a few hundred samples.  Plain float32 evaluation of the whole
 // index would lose ~2e-4 samples, i.e. ~1e-4 relative error per term.
 //
+// The element loop runs over the union of the tile's apertures with a
+// branch-free body: a lane outside its own aperture gets weight 0 (its reads
+// are in range or read 0, and add exactly 0), so loads of consecutive
+// elements can be in flight together.
+//
 // Each thread can beamform FB frames that share the geometry: delays and
 // apodization are computed once per (pixel, element) and reused.
 #include <algorithm>
+#include <climits>
 #include <vector>
 
 #include "common.hpp"
@@ -42,21 +50,25 @@ struct DasGrid {
     double z0, dz, x0, dx;
 };
 
-// One wave: 64 consecutive depth rows (lanes) starting at row i_base, of image
-// column j (wave-uniform), for FB frames sharing the geometry.  rf points at
-// the first frame's [A][C][T] record, img at its [nz][nx] image; frame f of
-// the group is rf + f * frame_rf, img + f * frame_img.
+constexpr int DAS_WZ = 16;  // depth rows per wave tile
+constexpr int DAS_WX = 4;   // image columns per wave tile
+
+// One wave: the 16 x 4 pixel tile at rows i_base.., columns j_base.., for FB
+// frames sharing the geometry.  rf points at the first frame's [A][C][T]
+// record, img at its [nz][nx] image; frame f of the group is rf + f *
+// frame_rf, img + f * frame_img.
 template <int FB, int NA>
-__device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, int i_base, int j, int nfr,
+__device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, int i_base, int j_base, int nfr,
                                          const float* __restrict__ rf, size_t frame_rf, float* img,
                                          size_t frame_img) {
     const int lane = threadIdx.x & 63;
-    const int i = i_base + lane;
+    const int i = i_base + (lane % DAS_WZ);
+    const int j = j_base + (lane / DAS_WZ);
     const int A = (NA > 0) ? NA : p.A;
 
-    const double xd = gr.x0 + (double)j * gr.dx;
+    const double xd = gr.x0 + (double)min(j, gr.nx - 1) * gr.dx;
     const double zd = gr.z0 + (double)min(i, gr.nz - 1) * gr.dz;
-    const bool active = (i < gr.nz) && (zd > 0.0);
+    const bool active = (i < gr.nz) && (j < gr.nx) && (zd > 0.0);
     const float zf = (float)zd;
     const float z2 = (float)(zd * zd);
     const float inv_az = active ? (float)(2.0 * p.fnumber / zd) : 0.0f;
@@ -74,14 +86,16 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
         }
     }
 
-    // element range covering the widest aperture among this wave's rows
-    const int i_last = min(i_base + 63, gr.nz - 1);
+    // element range covering the widest aperture among the tile's pixels
+    const int i_last = min(i_base + DAS_WZ - 1, gr.nz - 1);
     const double z_last = gr.z0 + (double)i_last * gr.dz;
+    const double x_lo = gr.x0 + (double)j_base * gr.dx;
+    const double x_hi = gr.x0 + (double)min(j_base + DAS_WX - 1, gr.nx - 1) * gr.dx;
     int n_lo = 0, n_hi = -1;
     if (z_last > 0.0) {
         const double a_max = z_last / (2.0 * p.fnumber);
-        n_lo = max(0, (int)floor((xd - a_max - p.x_first) / p.pitch));
-        n_hi = min(p.C - 1, (int)ceil((xd + a_max - p.x_first) / p.pitch));
+        n_lo = max(0, (int)floor((fmin(x_lo, x_hi) - a_max - p.x_first) / p.pitch));
+        n_hi = min(p.C - 1, (int)ceil((fmax(x_lo, x_hi) + a_max - p.x_first) / p.pitch));
     }
 
     float acc[FB];
@@ -89,57 +103,64 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
     for (int f = 0; f < FB; ++f) acc[f] = 0.0f;
 
     const uint32_t row_bytes = (uint32_t)p.T * 4u;
+#pragma unroll 2
     for (int n = n_lo; n <= n_hi; ++n) {
         const float dx = (float)(xd - (p.x_first + (double)n * p.pitch));
         const float t = fabsf(dx) * inv_az;
-        if (active && t <= 1.0f) {
-            const float w = hann_weight(t);
-            const float rho = __builtin_amdgcn_sqrtf(fmaf(dx, dx, z2));
-            const float ke = p.kappa * (dx * dx) * __builtin_amdgcn_rcpf(rho + zf);
+        const float wh = hann_weight(fminf(t, 1.0f));
+        const float w = (active && t <= 1.0f) ? wh : 0.0f;
+        const float rho = __builtin_amdgcn_sqrtf(fmaf(dx, dx, z2));
+        const float ke = p.kappa * (dx * dx) * __builtin_amdgcn_rcpf(rho + zf);
 #pragma unroll
-            for (int a = 0; a < ((NA > 0) ? NA : DAS_MAX_ANGLES); ++a) {
-                if (a < A) {
-                    const float v = f_a[a] + ke;
-                    const float qf = floorf(v);
-                    const float fr = v - qf;
-                    const int off = (q_a[a] + (int)qf) * 4;
+        for (int a = 0; a < ((NA > 0) ? NA : DAS_MAX_ANGLES); ++a) {
+            if (a < A) {
+                const float v = f_a[a] + ke;
+                const float qf = floorf(v);
+                const float fr = v - qf;
+                const int off = (q_a[a] + (int)qf) * 4;
+                // the neighbour's offset computed apart (not off + 4): the two
+                // dword loads must not be merged into one 8-byte load, whose
+                // range check at sample -1 (offset -4, huge unsigned) would
+                // also discard the in-range sample 0
+                const int off1 = (q_a[a] + (int)(qf + 1.0f)) * 4;
 #pragma unroll
-                    for (int f = 0; f < FB; ++f) {
-                        if (f < nfr) {
-                            const size_t ch = (size_t)a * p.C + n;
-                            const auto rs = make_rsrc(rf + f * frame_rf + ch * p.T, row_bytes);
-                            const float s0 = buffer_load_f32(rs, off);
-                            const float s1 = buffer_load_f32(rs, off + 4);
-                            acc[f] = fmaf(w, fmaf(fr, s1 - s0, s0), acc[f]);
-                        }
-                    }
+                for (int f = 0; f < FB; ++f) {
+                    // every frame slot loads (a slot past the group's last frame
+                    // reads 0 out of range and is never stored), so the loads of
+                    // all slots and of the next element are in flight together
+                    const bool fv = f < nfr;
+                    const size_t ch = (size_t)a * p.C + n;
+                    const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, row_bytes);
+                    const float s0 = buffer_load_f32(rs, fv ? off : INT32_MIN);
+                    const float s1 = buffer_load_f32(rs, fv ? off1 : INT32_MIN);
+                    acc[f] = fmaf(w, fmaf(fr, s1 - s0, s0), acc[f]);
                 }
             }
         }
     }
-    if (i < gr.nz) {
+    if (i < gr.nz && j < gr.nx) {
 #pragma unroll
         for (int f = 0; f < FB; ++f)
             if (f < nfr) img[f * frame_img + (size_t)i * gr.nx + j] = acc[f];
     }
 }
 
+// workgroup = 4 wave tiles stacked in depth: 64 rows x 4 columns
 template <int FB, int NA>
 __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid gr, const float* __restrict__ rf,
                                                   float* __restrict__ img) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int j = blockIdx.y * 4 + wave;
-    if (j >= gr.nx) return;
     const int fr0 = blockIdx.z * FB;
     const size_t frame_rf = (size_t)p.A * p.C * p.T;
     const size_t frame_img = (size_t)gr.nz * gr.nx;
-    das_wave<FB, NA>(p, gr, blockIdx.x * 64, j, min(FB, p.n_frames - fr0), rf + fr0 * frame_rf, frame_rf,
-                     img + fr0 * frame_img, frame_img);
+    das_wave<FB, NA>(p, gr, blockIdx.x * 64 + wave * DAS_WZ, blockIdx.y * DAS_WX, min(FB, p.n_frames - fr0),
+                     rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
 }
 
 // ----------------------------------------------------------------- batches ----
 // Ragged batch: every frame has its own grid, RF record and image.  One
-// persistent launch covers the tiles (64 rows x WAVES columns) of all frames.
+// persistent launch covers the tiles (64 rows x WAVES columns, each 4 columns
+// of it four 16 x 4 wave tiles) of all frames.
 // The tile list is cut into 8 contiguous chunks, chunk x served by the
 // workgroups the hardware places on XCD x (block id = x mod 8), so each frame's
 // RF stays in one XCD's L2.  Every workgroup walks its chunk with a fixed
@@ -178,8 +199,9 @@ __global__ __launch_bounds__(WAVES * 64) void das_batch_kernel(const DasArgs p, 
         const int row_tiles = (gr.nz + 63) / 64;
         const int rt = (int)(local % row_tiles);
         const int ct = (int)(local / row_tiles);
-        const int j = ct * WAVES + wave;
-        if (j < gr.nx) das_wave<1, NA>(p, gr, rt * 64, j, 1, fr[f].rf, 0, fr[f].out, 0);
+        // tile of 64 rows x WAVES columns: column group wave / 4, wave tile wave % 4 in depth
+        const int j_base = ct * WAVES + (wave / 4) * DAS_WX;
+        if (j_base < gr.nx) das_wave<1, NA>(p, gr, rt * 64 + (wave % 4) * DAS_WZ, j_base, 1, fr[f].rf, 0, fr[f].out, 0);
     }
 }
 

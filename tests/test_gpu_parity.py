@@ -190,6 +190,27 @@ def test_das_edge_grids(dev):
         assert np.all(img[zs <= 0] == 0)
 
 
+def test_das_reads_at_both_ends_of_the_record(dev):
+    """One element on the axis, dense random channel data and a depth axis whose
+    sample index sweeps from 1.5 samples before the record to 1.5 after it:
+    every interpolation that straddles an end (one neighbour inside, one outside)
+    must read the outside neighbour as 0 and the inside one exactly."""
+    T = 64
+    base = config(1).replace(n_elem=1, n_samples=T, angles=(0.0,))
+    z_min = 2e-3
+    t0 = 2 * z_min / base.c + 1.5 / base.fs           # u(z_min) = -1.5
+    nz = 500
+    dz = (T + 3.0) / (nz - 1) * base.c / (2 * base.fs)  # u sweeps -1.5 .. T + 1.5
+    s = base.replace(t0=t0, nz=nz, nx=1, z0=z_min, dz=dz, x0=0.0, dx=1e-4)
+    rf = generators.normal((1, 1, T), seed=13).astype(np.float32)
+    img, ref = das_case(dev, s, rf)
+    assert np.max(np.abs(img - ref)) <= 2e-6
+    zs = s.z0 + np.arange(nz) * s.dz
+    u = (2 * zs / s.c - s.t0) * s.fs
+    edge = ((u > -1) & (u < 0)) | ((u > T - 1) & (u < T))
+    assert edge.sum() > 10 and np.all(np.abs(img[edge, 0]) > 0)
+
+
 def test_das_single_element(dev):
     s = config(1).replace(n_elem=1, n_samples=900).with_grid(90, 5)
     rf = generators.normal((1, 1, 900), seed=7).astype(np.float32)
