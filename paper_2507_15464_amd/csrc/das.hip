@@ -1,13 +1,14 @@
 // Exact Delay-and-Sum beamformer for plane-wave transmits (Sec. 2, eqn:appF).
 //
-// Mapping on gfx950: one wavefront = a tile of 16 consecutive depth rows x 4
-// consecutive image columns (lane l: row l % 16, column l / 16); a workgroup
-// = 4 such waves stacked in depth (64 rows x 4 columns).  For a fixed element
-// n the wave's 64 lanes then read a short window of that element's channel:
-// the sample index grows by ~2 dz fs / c per row and by less than dx fs / c
-// per column, so a wave-load touches about three cache lines (a 64-row column
-// strip would span ~250 samples, eight lines: the gather path, not the
-// arithmetic, bounds this kernel).
+// Mapping on gfx950: one wavefront = 64 consecutive image columns of ONE depth
+// row (lane l: column l); a workgroup = 4 consecutive rows of those columns.
+// For a fixed element n the lanes read a short, monotone window of that
+// element's channel: along a row the sample index changes by at most
+// dx fs / (c F') per column (~1.5 samples here), while down a column it grows
+// by 2 dz fs / c (~3.8): a row of 64 pixels spans ~100 samples, a column of
+// 64 ~250, and the gather path, not the arithmetic, bounds this kernel
+// (measured on the benchmark workload: 0.83 ms per 64 frames as rows, 1.71 ms
+// as columns, 1.2 ms as 4 x 16 tiles).
 //
 // Delay precision.  The fractional sample index is split:
 //   u = fs (tau_tx(x_j, z_i; a) + z_i / c - t0)      [per pixel, float64]
@@ -50,10 +51,11 @@ struct DasGrid {
     double z0, dz, x0, dx;
 };
 
-constexpr int DAS_WZ = 16;  // depth rows per wave tile
-constexpr int DAS_WX = 4;   // image columns per wave tile
+constexpr int DAS_WZ = 1;   // depth rows per wave tile
+constexpr int DAS_WX = 64;  // image columns per wave tile
+constexpr int DAS_BZ = 4;   // wave tiles per workgroup, stacked in depth
 
-// One wave: the 16 x 4 pixel tile at rows i_base.., columns j_base.., for FB
+// One wave: the 1 x 64 pixel tile at row i_base, columns j_base.., for FB
 // frames sharing the geometry.  rf points at the first frame's [A][C][T]
 // record, img at its [nz][nx] image; frame f of the group is rf + f *
 // frame_rf, img + f * frame_img.
@@ -145,7 +147,7 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
     }
 }
 
-// workgroup = 4 wave tiles stacked in depth: 64 rows x 4 columns
+// workgroup = DAS_BZ wave tiles stacked in depth: 4 rows x 64 columns
 template <int FB, int NA>
 __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid gr, const float* __restrict__ rf,
                                                   float* __restrict__ img) {
@@ -153,14 +155,14 @@ __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid
     const int fr0 = blockIdx.z * FB;
     const size_t frame_rf = (size_t)p.A * p.C * p.T;
     const size_t frame_img = (size_t)gr.nz * gr.nx;
-    das_wave<FB, NA>(p, gr, blockIdx.x * 64 + wave * DAS_WZ, blockIdx.y * DAS_WX, min(FB, p.n_frames - fr0),
+    das_wave<FB, NA>(p, gr, (blockIdx.x * DAS_BZ + wave) * DAS_WZ, blockIdx.y * DAS_WX, min(FB, p.n_frames - fr0),
                      rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
 }
 
 // ----------------------------------------------------------------- batches ----
 // Ragged batch: every frame has its own grid, RF record and image.  One
-// persistent launch covers the tiles (64 rows x WAVES columns, each 4 columns
-// of it four 16 x 4 wave tiles) of all frames.
+// persistent launch covers the tiles (WAVES rows x 64 columns, one wave per
+// row) of all frames.
 // The tile list is cut into 8 contiguous chunks, chunk x served by the
 // workgroups the hardware places on XCD x (block id = x mod 8), so each frame's
 // RF stays in one XCD's L2.  Every workgroup walks its chunk with a fixed
@@ -196,18 +198,19 @@ __global__ __launch_bounds__(WAVES * 64) void das_batch_kernel(const DasArgs p, 
         const int f = find_frame(fr, n_frames, t);
         const DasGrid gr = fr[f].grid;
         const int64_t local = t - fr[f].tile_start;
-        const int row_tiles = (gr.nz + 63) / 64;
+        // tile of WAVES rows x 64 columns, one wave tile per row
+        const int row_tiles = (gr.nz + WAVES * DAS_WZ - 1) / (WAVES * DAS_WZ);
         const int rt = (int)(local % row_tiles);
         const int ct = (int)(local / row_tiles);
-        // tile of 64 rows x WAVES columns: column group wave / 4, wave tile wave % 4 in depth
-        const int j_base = ct * WAVES + (wave / 4) * DAS_WX;
-        if (j_base < gr.nx) das_wave<1, NA>(p, gr, rt * 64 + (wave % 4) * DAS_WZ, j_base, 1, fr[f].rf, 0, fr[f].out, 0);
+        const int i_base = (rt * WAVES + wave) * DAS_WZ;
+        if (i_base < gr.nz) das_wave<1, NA>(p, gr, i_base, ct * DAS_WX, 1, fr[f].rf, 0, fr[f].out, 0);
     }
 }
 
 template <int FB, int NA>
 static void launch_das(const DasArgs& p, const DasGrid& gr, const float* rf, float* img, hipStream_t s) {
-    dim3 grid((gr.nz + 63) / 64, (gr.nx + 3) / 4, (p.n_frames + FB - 1) / FB);
+    dim3 grid((gr.nz + DAS_BZ * DAS_WZ - 1) / (DAS_BZ * DAS_WZ), (gr.nx + DAS_WX - 1) / DAS_WX,
+              (p.n_frames + FB - 1) / FB);
     hipLaunchKernelGGL((das_kernel<FB, NA>), grid, dim3(256), 0, s, p, gr, rf, img);
 }
 
@@ -348,7 +351,7 @@ extern "C" int32_t das_beamform_batch(const tidas_array* array, const tidas_tx* 
     const int per_cu = (variant >> 1) == 0 ? 2 : ((variant >> 1) == 1 ? 4 : 8);
     hipStream_t s = (hipStream_t)stream;
     int64_t total = 0;
-    if ((st = upload_batch(frames, n_frames, 64, waves, workspace, s, total))) return st;
+    if ((st = upload_batch(frames, n_frames, waves * DAS_WZ, DAS_WX, workspace, s, total))) return st;
     int dev = 0, n_cu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
