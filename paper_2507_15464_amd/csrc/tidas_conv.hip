@@ -612,19 +612,11 @@ __device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const 
     };
 
     floatx2 ring[BX_PD][8];
-    // Walk order.  The window of the tile at i0 starts i0 / 16 steps after
-    // that of the tile at 0, so the three tiles that read a given input row
-    // read it at local steps 16 apart in rows.  Each tile walks its window
-    // cyclically from local step rot = -i0 / 16 (mod NS): at position q it
-    // takes local step (q + rot) mod NS, whose absolute row position is the
-    // same for every tile, so workgroups that run side by side read each input
-    // row at about the same time and the re-reads hit L2.  (The order of the
-    // k-steps is fixed per tile: results stay deterministic.)
-    const int rot = (NS - (i0 / 16) % NS) % NS;
-    auto local_step = [&](int q) {
-        const int sl = q + rot;
-        return sl >= NS ? sl - NS : sl;
-    };
+    // Walk order: ascending window steps.  (Every line-model kernel sums the
+    // same 16-row chunks of the window in the same ascending order, the
+    // products outside a row's band being exact zeros, so all of them give
+    // the same bits.)
+    auto local_step = [&](int q) { return q; };
     // first steps' input loads in flight while the band image is brought in
     {
         const auto rs0 = frame_rsrc(0);
@@ -796,6 +788,234 @@ __device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const 
     }
 }
 
+// ------------------------------------------------------------------------
+// Four-M-block variant for K <= 161 and batches that fill the GPU.
+// A workgroup (8 waves) owns 128 output rows x 256 columns; wave w owns
+// columns 32 w .. +31 (one chain: lane column j is image column j) and all
+// 128 rows as four 32-row M-blocks, so every split input element feeds up to
+// four M-blocks x six products (twice the two-block tile's reuse: half the
+// split work per product), and the source window per output row is (128 +
+// K - 1) / 128 instead of (64 + K - 1) / 64.  M-block b needs window steps
+// [2 b, 2 b + NSB) only; LDS holds each block's own band window (three planes
+// of 32 x (16 NSB + 8) bfloat16), and the walk over the NSB + 6 steps of a
+// frame is unrolled at compile time (NSB is a template parameter), so every
+// step issues exactly the products of the blocks its rows reach, with no
+// branches.  The 16-row chunks and their order are those of the two-block
+// tile: the results are bit-identical.
+constexpr int B4_TZ = 128;
+constexpr int B4_TN = 256;
+constexpr int B4_THREADS = 512;  // 8 waves
+
+__host__ __device__ constexpr int b4_lstride(int nsb) { return 16 * nsb + 8; }
+__host__ __device__ constexpr size_t b4_image_bytes(int nsb) { return (size_t)4 * 3 * 32 * b4_lstride(nsb) * 2; }
+// smallest supported NSB covering K (0: K too large for the four-block tile)
+__host__ __device__ constexpr int b4_nsb(int K) {
+    const int need = (32 + K - 1 + 15) / 16;
+    return need <= 4 ? 4 : need <= 6 ? 6 : need <= 8 ? 8 : need <= 10 ? 10 : need <= 12 ? 12 : 0;
+}
+
+// Band image of the 128-row tile at i0 in the four-block layout
+// [block][plane][32][16 NSB + 8]: entry (b, r, c) = M[32 b + r][32 b + c] of
+// the tile (apply: K[i0 + 32b + r][r - c + 2h]; adjoint: K[i0 - h + 32b + c][c - r]).
+__global__ __launch_bounds__(256) void b4_prepare_kernel(const float* __restrict__ Kb, int32_t K, int32_t Z,
+                                                         int32_t n_rt, int32_t nsb, uint16_t* __restrict__ prepared,
+                                                         int32_t mode0) {
+    const int LS = b4_lstride(nsb);
+    const int rt = blockIdx.y, adj = mode0 + (int)blockIdx.z;
+    const int e = blockIdx.x * 256 + threadIdx.x;  // over [block][row][column]
+    const int per_block = 32 * LS;
+    if (e >= 4 * per_block) return;
+    const int b = e / per_block, rc = e - b * per_block;
+    const int r = rc / LS, c = rc - r * LS;
+    const int h = (K - 1) >> 1;
+    const int i0 = rt * B4_TZ;
+    const int t = adj ? c - r : r - c + 2 * h;
+    const int row = adj ? i0 - h + 32 * b + c : i0 + 32 * b + r;
+    const bool ok = c < 16 * nsb && t >= 0 && t < K && row >= 0 && row < Z;
+    const float v = ok ? Kb[(size_t)row * K + t] : 0.0f;
+    uint16_t* img = prepared + (size_t)(blockIdx.z * n_rt + rt) * (b4_image_bytes(nsb) / 2) + (size_t)b * 3 * per_block;
+    uint32_t w0, w1, w2;
+    split3(v, w0, w1, w2);
+    img[rc] = (uint16_t)(w0 >> 16);
+    img[per_block + rc] = (uint16_t)(w1 >> 16);
+    img[2 * per_block + rc] = (uint16_t)(w2 >> 16);
+}
+
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// f(integral_constant<0>), ..., f(integral_constant<N - 1>) in order, unrolled
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+struct B4Geom {
+    int32_t K, B, Z, X, nf;
+    int32_t n_rt, n_ct, n_blocks;
+    float alpha, beta;
+    const float* base;
+};
+
+template <bool ADJ, int NSB>
+__global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, const uint16_t* __restrict__ images,
+                                                              const float* __restrict__ In, float* Out) {
+    constexpr int NW = NSB + 6;   // window steps of the tile
+    constexpr int LS = b4_lstride(NSB);
+    constexpr int PB = 32 * LS;   // one plane of one block, in bf16
+    constexpr int PD = 4;         // ring slots
+    extern __shared__ uint16_t b4_smem[];
+    const int lg = xcd_remap(blockIdx.x, g.n_blocks);
+    const int rt = lg % g.n_rt;
+    const int ct = (lg / g.n_rt) % g.n_ct;
+    const int fg = lg / (g.n_rt * g.n_ct);
+    const int f0 = fg * g.nf;
+    const int nf = min(g.nf, g.B - f0);
+    const int K = g.K, Z = g.Z, X = g.X;
+    const int h = (K - 1) >> 1;
+    const int i0 = rt * B4_TZ;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = lane & 31, gk = lane >> 5;
+    const int col = ct * B4_TN + 32 * wave + j;
+    const size_t fstride = (size_t)Z * X;
+    const uint32_t frame_bytes = (uint32_t)(fstride * sizeof(float));
+    const int row_bytes = X * 4;
+    // byte offset of window row 8 gk of step 0 at this lane's column; rows
+    // above or below the image fall outside the frame and read 0
+    const int off0 = ((i0 - h + 8 * gk) * X + col) * 4;
+    const float* In0 = In + (size_t)f0 * fstride;
+    float* Out0 = Out + (size_t)f0 * fstride;
+    const float* Base0 = g.base ? g.base + (size_t)f0 * fstride : nullptr;
+
+    auto frame_rsrc = [&](int f) {
+        const int fu = __builtin_amdgcn_readfirstlane(f < nf ? f : 0);
+        return make_rsrc(uniform_ptr(In0 + (size_t)fu * fstride), frame_bytes);
+    };
+    auto load8 = [&](__amdgpu_buffer_rsrc_t rs, int s, bool valid, float(&x)[8]) {
+        const int so = __builtin_amdgcn_readfirstlane(valid ? s * 16 * row_bytes : INT32_MIN - off0);
+        const int o = off0 + so;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = buffer_load_f32(rs, o + e * row_bytes);
+    };
+
+    float ring[PD][8];
+    {
+        const auto rs0 = frame_rsrc(0);
+#pragma unroll
+        for (int u = 0; u < PD - 1; ++u) load8(rs0, u, true, ring[u]);
+        // band image: a straight copy by direct-to-LDS 16-byte loads (1 KB per wave load)
+        const uint16_t* img = images + (size_t)rt * (b4_image_bytes(NSB) / 2);
+        constexpr int n_loads = (int)(b4_image_bytes(NSB) / 1024);
+        const auto rs = make_rsrc(img, (uint32_t)b4_image_bytes(NSB));
+        for (int q = wave; q < n_loads; q += B4_THREADS / 64)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(b4_smem + q * 512),
+                                                     16, q * 1024 + lane * 16, 0, 0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
+
+    floatx16 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[b][i] = 0.0f;
+
+    auto split8 = [&](const float(&x)[8], bf16x8(&Bp)[3]) {
+        uint32_t w0[8], w1[8], w2[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) split3(x[e], w0[e], w1[e], w2[e]);
+        Bp[0] = pack8(w0);
+        Bp[1] = pack8(w1);
+        Bp[2] = pack8(w2);
+    };
+    bf16x8 BpA[3], BpB[3];
+    split8(ring[0], BpA);
+
+    const uint16_t* a_base = b4_smem + j * LS + 8 * gk;
+    constexpr int TA[6] = {0, 0, 1, 0, 1, 2};
+    constexpr int TB[6] = {0, 1, 0, 2, 1, 0};
+    // first output row of this lane (D rows 4 gk + 8 (i / 4) + i % 4 of each block)
+    const int vstart = col < X ? ((i0 + 4 * gk) * X + col) * 4 : INT32_MIN;
+
+    for (int f = 0; f < nf; ++f) {
+        const auto rs_cur = frame_rsrc(f), rs_nxt = frame_rsrc(f + 1);
+        const bool nxt_valid = f + 1 < nf;
+        static_for<NW>([&](auto S_) {
+            constexpr int S = decltype(S_)::value;
+            bf16x8(&Bcur)[3] = (S % 2 == 0) ? BpA : BpB;
+            bf16x8(&Bnxt)[3] = (S % 2 == 0) ? BpB : BpA;
+            // prefetch the step PD - 1 ahead (of this frame or the next)
+            if constexpr (S + PD - 1 < NW)
+                load8(rs_cur, S + PD - 1, true, ring[(S + PD - 1) % PD]);
+            else
+                load8(rs_nxt, S + PD - 1 - NW, nxt_valid, ring[(S + PD - 1) % PD]);
+            __builtin_amdgcn_sched_barrier(0);
+            // blocks whose band reaches window step S: b with 2 b <= S < 2 b + NSB
+            constexpr int b_lo = (S >= NSB) ? (S - NSB) / 2 + 1 : 0;
+            constexpr int b_hi = (S / 2 < 3) ? S / 2 : 3;
+            bf16x8 A[4][3];
+            static_for<4>([&](auto B_) {
+                constexpr int b = decltype(B_)::value;
+                if constexpr (b >= b_lo && b <= b_hi) {
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+                        A[b][p] = *reinterpret_cast<const bf16x8*>(a_base + (3 * b + p) * PB + 16 * (S - 2 * b));
+                }
+            });
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+                static_for<4>([&](auto B_) {
+                    constexpr int b = decltype(B_)::value;
+                    if constexpr (b >= b_lo && b <= b_hi)
+                        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][TA[t]], Bcur[TB[t]], acc[b], 0, 0, 0);
+                });
+            split8(ring[(S + 1) % PD], Bnxt);
+            constexpr int n_mfma = 6 * (b_hi - b_lo + 1);
+            constexpr int per = (48 + n_mfma - 1) / n_mfma;
+            static_for<n_mfma>([&](auto) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, per, 0);  // vector instructions of the next split
+            });
+        });
+        // results of frame f: every store issued; rows below the image lie past
+        // the frame's last byte and columns past X start at INT32_MIN, so the
+        // range check drops both.  The offsets are rebuilt from values made
+        // opaque here, each frame: left loop-invariant they would be hoisted
+        // out of the frame loop and hold 64 registers.
+        const auto rs_o = make_rsrc(uniform_ptr(Out0 + (size_t)f * fstride), frame_bytes);
+        const bool has_base = Base0 != nullptr;
+        const auto rs_b = make_rsrc(uniform_ptr((has_base ? Base0 : Out0) + (size_t)f * fstride), frame_bytes);
+        int o = vstart, rb = row_bytes;
+        asm volatile("" : "+v"(o), "+s"(rb));
+        const int rb5 = 5 * rb;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int voff[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                voff[i] = o;
+                o += (i & 3) == 3 ? rb5 : rb;
+            }
+            float v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = g.alpha * acc[b][i];
+            if (has_base) {
+                float bv[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) bv[i] = buffer_load_f32(rs_b, voff[i]);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) v[i] = fmaf(g.beta, bv[i], v[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[i]), rs_o, voff[i], 0, 0);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[b][i] = 0.0f;
+        }
+    }
+}
+
 struct BxGeom {
     int32_t K, B, Z, X, nf;
     int32_t n_rt, n_ct, n_blocks;
@@ -920,6 +1140,65 @@ static void launch_bx6(bool adj, bool vec, const uint16_t* images, int32_t K, co
     }
 }
 
+// ---- four-M-block tiles
+static bool b4_image_ok(int K) {
+    const int nsb = b4_nsb(K);
+    return nsb > 0 && b4_image_bytes(nsb) <= 160 * 1024;
+}
+static bool b4_fits(int K, int Z, int X) {
+    return b4_image_ok(K) && ((int64_t)Z + 2 * K + 512) * X * 4 < INT32_MAX;
+}
+// worth it when the batch alone fills every compute unit
+static bool b4_path(int32_t K, int32_t B, int32_t Z, int32_t X) {
+    const int64_t tiles = (int64_t)((Z + B4_TZ - 1) / B4_TZ) * ((X + B4_TN - 1) / B4_TN) * B;
+    return b4_fits(K, Z, X) && tiles >= device_cu_count() && tiles <= INT32_MAX;
+}
+static size_t b4_bytes(int32_t K, int32_t Z, int n_modes) {
+    return (size_t)n_modes * ((Z + B4_TZ - 1) / B4_TZ) * b4_image_bytes(b4_nsb(K));
+}
+static void launch_b4_prepare(const float* kernels, int32_t K, int32_t Z, int mode0, int n_modes, uint16_t* out,
+                              hipStream_t stream) {
+    const int nsb = b4_nsb(K);
+    const int n_rt = (Z + B4_TZ - 1) / B4_TZ;
+    const int per_tile = 4 * 32 * b4_lstride(nsb);
+    const dim3 grid((unsigned)((per_tile + 255) / 256), (unsigned)n_rt, (unsigned)n_modes);
+    hipLaunchKernelGGL(b4_prepare_kernel, grid, dim3(256), 0, stream, kernels, K, Z, n_rt, nsb, out, mode0);
+}
+template <bool ADJ>
+static void launch_b4_mode(const B4Geom& g, int nsb, const uint16_t* images, const float* in, float* out,
+                           hipStream_t stream) {
+    const dim3 grid(g.n_blocks), block(B4_THREADS);
+    const size_t lds = b4_image_bytes(nsb);
+    switch (nsb) {
+        case 4: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 4>), grid, block, lds, stream, g, images, in, out); break;
+        case 6: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 6>), grid, block, lds, stream, g, images, in, out); break;
+        case 8: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 8>), grid, block, lds, stream, g, images, in, out); break;
+        case 10: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 10>), grid, block, lds, stream, g, images, in, out); break;
+        default: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 12>), grid, block, lds, stream, g, images, in, out); break;
+    }
+}
+// images: the four-block band images of the operator's mode, tile rt at
+// images + rt b4_image_bytes(nsb) / 2
+static void launch_b4(bool adj, const uint16_t* images, int32_t K, const float* in, int32_t B, int32_t Z, int32_t X,
+                      float alpha, float beta, const float* base, float* out, hipStream_t stream) {
+    B4Geom g;
+    g.K = K;
+    g.B = B;
+    g.Z = Z;
+    g.X = X;
+    g.n_rt = (Z + B4_TZ - 1) / B4_TZ;
+    g.n_ct = (X + B4_TN - 1) / B4_TN;
+    // frames per workgroup: one workgroup per compute unit in one round
+    const int64_t tiles = (int64_t)g.n_rt * g.n_ct;
+    g.nf = (int32_t)std::max<int64_t>(1, std::min<int64_t>(B, tiles * B / device_cu_count()));
+    g.n_blocks = (int32_t)(tiles * ((B + g.nf - 1) / g.nf));
+    g.alpha = alpha;
+    g.beta = beta;
+    g.base = base;
+    if (adj) launch_b4_mode<true>(g, b4_nsb(K), images, in, out, stream);
+    else launch_b4_mode<false>(g, b4_nsb(K), images, in, out, stream);
+}
+
 static bool mfma_fits(int K, int Z, int X) {
     // LDS tile fits; every int32 byte offset,
     // including rows prefetched past the band (< K + 4 PD + 64 rows beyond
@@ -990,15 +1269,19 @@ static int32_t conv_launch(bool adj, const char* name, const float* kernels, int
     int32_t st = conv_validate(name, kernels, K, in, B, Z, X, alpha, beta, base, out);
     if (st) return st;
     const bool vec = vec_ok(X, in, out, base);
-    if (bx_path(K, B, Z, X)) {
-        // the images of this one mode
+    const bool four = b4_path(K, B, Z, X);
+    if (four || bx_path(K, B, Z, X)) {
+        // the band images of this one mode, in the layout of the chosen tile
         void* buf = nullptr;
-        if ((st = check_hip(hipMallocAsync(&buf, prepared_bytes(K, Z, 1), stream), "band buffer")))
+        if ((st = check_hip(hipMallocAsync(&buf, four ? b4_bytes(K, Z, 1) : prepared_bytes(K, Z, 1), stream),
+                            "band buffer")))
             return st;
-        launch_prepare(kernels, K, Z, adj ? 1 : 0, 1, (uint16_t*)buf, stream);
+        if (four) launch_b4_prepare(kernels, K, Z, adj ? 1 : 0, 1, (uint16_t*)buf, stream);
+        else launch_prepare(kernels, K, Z, adj ? 1 : 0, 1, (uint16_t*)buf, stream);
         st = check_launch(name);
         if (!st) {
-            launch_bx6(adj, vec, (const uint16_t*)buf, K, in, B, Z, X, alpha, beta, base, out, stream);
+            if (four) launch_b4(adj, (const uint16_t*)buf, K, in, B, Z, X, alpha, beta, base, out, stream);
+            else launch_bx6(adj, vec, (const uint16_t*)buf, K, in, B, Z, X, alpha, beta, base, out, stream);
             st = check_launch(name);
         }
         const int32_t st2 = check_hip(hipFreeAsync(buf, stream), "band buffer");
@@ -1035,15 +1318,31 @@ static int32_t conv_launch(bool adj, const char* name, const float* kernels, int
     return check_launch(name);
 }
 
-// The split-bfloat16 operator on prepared band images of one mode.
-static int32_t conv_launch_images(bool adj, const char* name, const uint16_t* images, int32_t K, const float* in,
+// Full prepared form of a bank: [two-block images, forward | adjoint] then,
+// when K allows the four-block tile, [four-block images, forward | adjoint].
+static size_t full_prepared_bytes(int32_t K, int32_t Z) {
+    return prepared_bytes(K, Z, 2) + (b4_image_ok(K) ? b4_bytes(K, Z, 2) : 0);
+}
+static void prepare_full(const float* kernels, int32_t K, int32_t Z, uint16_t* buf, hipStream_t stream) {
+    launch_prepare(kernels, K, Z, 0, 2, buf, stream);
+    if (b4_image_ok(K)) launch_b4_prepare(kernels, K, Z, 0, 2, buf + prepared_bytes(K, Z, 2) / 2, stream);
+}
+
+// The split-bfloat16 operator on a full prepared form.
+static int32_t conv_launch_images(bool adj, const char* name, const uint16_t* prepared, int32_t K, const float* in,
                                   int32_t B, int32_t Z, int32_t X, float alpha, float beta, const float* base,
                                   float* out, hipStream_t stream) {
-    int32_t st = conv_validate(name, images, K, in, B, Z, X, alpha, beta, base, out);
+    int32_t st = conv_validate(name, prepared, K, in, B, Z, X, alpha, beta, base, out);
     if (st) return st;
+    if (b4_path(K, B, Z, X)) {
+        const uint16_t* img = prepared + prepared_bytes(K, Z, 2) / 2 + (adj ? b4_bytes(K, Z, 1) / 2 : 0);
+        launch_b4(adj, img, K, in, B, Z, X, alpha, beta, base, out, stream);
+        return check_launch(name);
+    }
     if (!bx_path(K, B, Z, X))
         return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": K or the frame size is outside the prepared path");
-    launch_bx6(adj, vec_ok(X, in, out, base), images, K, in, B, Z, X, alpha, beta, base, out, stream);
+    const uint16_t* img = prepared + (adj ? prepared_bytes(K, Z, 1) / 2 : 0);
+    launch_bx6(adj, vec_ok(X, in, out, base), img, K, in, B, Z, X, alpha, beta, base, out, stream);
     return check_launch(name);
 }
 
@@ -1102,7 +1401,7 @@ extern "C" int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float
 
 extern "C" size_t tidas_prepared_bytes(int32_t K, int32_t Z) {
     if (K < 1 || (K % 2) == 0 || Z < 1 || bx_lds_bytes(K) > 160 * 1024) return 0;
-    return prepared_bytes(K, Z, 2);
+    return full_prepared_bytes(K, Z);
 }
 
 extern "C" int32_t tidas_prepare(const float* kernels, int32_t K, int32_t Z, void* prepared, size_t bytes,
@@ -1110,10 +1409,10 @@ extern "C" int32_t tidas_prepare(const float* kernels, int32_t K, int32_t Z, voi
     if (!kernels || !prepared) return fail(TIDAS_EINVAL, "tidas_prepare: null pointer");
     if (K < 1 || (K % 2) == 0 || Z < 1) return fail(TIDAS_EINVAL, "tidas_prepare: K odd >= 1 and Z >= 1 required");
     if (bx_lds_bytes(K) > 160 * 1024) return fail(TIDAS_EUNSUPPORTED, "tidas_prepare: K too large for the prepared path");
-    if (bytes < prepared_bytes(K, Z, 2)) return fail(TIDAS_EINVAL, "tidas_prepare: buffer smaller than tidas_prepared_bytes");
+    if (bytes < full_prepared_bytes(K, Z)) return fail(TIDAS_EINVAL, "tidas_prepare: buffer smaller than tidas_prepared_bytes");
     if ((reinterpret_cast<uintptr_t>(prepared) & 15) != 0) return fail(TIDAS_EINVAL, "tidas_prepare: buffer not 16-byte aligned");
     if ((const void*)kernels == prepared) return fail(TIDAS_EINVAL, "tidas_prepare: output aliases the bank");
-    launch_prepare(kernels, K, Z, 0, 2, (uint16_t*)prepared, (hipStream_t)stream);
+    prepare_full(kernels, K, Z, (uint16_t*)prepared, (hipStream_t)stream);
     return check_launch("tidas_prepare");
 }
 
@@ -1127,10 +1426,8 @@ extern "C" int32_t tidas_apply_prepared(const void* prepared, int32_t K, const f
 extern "C" int32_t tidas_adjoint_prepared(const void* prepared, int32_t K, const float* image_bar, int32_t B,
                                           int32_t Z, int32_t X, float alpha, float beta, const float* base,
                                           float* refl_bar, void* stream) {
-    const uint16_t* adj = prepared ? (const uint16_t*)prepared + prepared_bytes(K, Z, 1) / 2 : nullptr;
-    if (K < 1 || (K % 2) == 0 || Z < 1) adj = (const uint16_t*)prepared;  // validation reports the sizes
-    return conv_launch_images(true, "tidas_adjoint_prepared", adj, K, image_bar, B, Z, X, alpha, beta, base, refl_bar,
-                              (hipStream_t)stream);
+    return conv_launch_images(true, "tidas_adjoint_prepared", (const uint16_t*)prepared, K, image_bar, B, Z, X, alpha,
+                              beta, base, refl_bar, (hipStream_t)stream);
 }
 
 extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float* y, int32_t B, int32_t Z, int32_t X,
@@ -1154,18 +1451,17 @@ extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float
     // the band images of both modes once for all iterations
     void* imgs = nullptr;
     const bool bx = bx_path(K, B, Z, X);
-    if (!st && bx && !(st = check_hip(hipMallocAsync(&imgs, prepared_bytes(K, Z, 2), s), "tidas_deconvolve: bands"))) {
-        launch_prepare(kernels, K, Z, 0, 2, (uint16_t*)imgs, s);
+    if (!st && bx && !(st = check_hip(hipMallocAsync(&imgs, full_prepared_bytes(K, Z), s), "tidas_deconvolve: bands"))) {
+        prepare_full(kernels, K, Z, (uint16_t*)imgs, s);
         st = check_launch("tidas_deconvolve(prepare)");
     }
-    const uint16_t* fwd = (const uint16_t*)imgs;
-    const uint16_t* adj = fwd ? fwd + prepared_bytes(K, Z, 1) / 2 : nullptr;
+    const uint16_t* prep = (const uint16_t*)imgs;
     for (int it = 0; it < iters && !st; ++it) {
         // work = A r - y ;  r = -eta A^T work + (1 - eta lam) r
         if (bx) {
-            st = conv_launch_images(false, "tidas_deconvolve(residual)", fwd, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
+            st = conv_launch_images(false, "tidas_deconvolve(residual)", prep, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
             if (!st)
-                st = conv_launch_images(true, "tidas_deconvolve(update)", adj, K, work, B, Z, X, -eta, decay, r, r, s);
+                st = conv_launch_images(true, "tidas_deconvolve(update)", prep, K, work, B, Z, X, -eta, decay, r, r, s);
         } else {
             st = conv_launch(false, "tidas_deconvolve(residual)", kernels, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
             if (!st)
@@ -1195,17 +1491,16 @@ extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32
     int32_t st = check_launch("tidas_operator_norm_sq(init)");
     void* imgs = nullptr;
     const bool bx = bx_path(K, 1, Z, 1);
-    if (!st && bx && !(st = check_hip(hipMallocAsync(&imgs, prepared_bytes(K, Z, 2), s), "tidas_operator_norm_sq: bands"))) {
-        launch_prepare(kernels, K, Z, 0, 2, (uint16_t*)imgs, s);
+    if (!st && bx && !(st = check_hip(hipMallocAsync(&imgs, full_prepared_bytes(K, Z), s), "tidas_operator_norm_sq: bands"))) {
+        prepare_full(kernels, K, Z, (uint16_t*)imgs, s);
         st = check_launch("tidas_operator_norm_sq(prepare)");
     }
-    const uint16_t* fwd = (const uint16_t*)imgs;
-    const uint16_t* adj = fwd ? fwd + prepared_bytes(K, Z, 1) / 2 : nullptr;
+    const uint16_t* prep = (const uint16_t*)imgs;
     for (int it = 0; it < iters && !st; ++it) {
         // v <- A^T A v / ||A^T A v||; the last norm is the largest eigenvalue of A^T A
         if (bx) {
-            st = conv_launch_images(false, "tidas_operator_norm_sq", fwd, K, v, 1, Z, 1, 1.0f, 0.0f, nullptr, av, s);
-            if (!st) st = conv_launch_images(true, "tidas_operator_norm_sq", adj, K, av, 1, Z, 1, 1.0f, 0.0f, nullptr, w, s);
+            st = conv_launch_images(false, "tidas_operator_norm_sq", prep, K, v, 1, Z, 1, 1.0f, 0.0f, nullptr, av, s);
+            if (!st) st = conv_launch_images(true, "tidas_operator_norm_sq", prep, K, av, 1, Z, 1, 1.0f, 0.0f, nullptr, w, s);
         } else {
             st = conv_launch(false, "tidas_operator_norm_sq", kernels, K, v, 1, Z, 1, 1.0f, 0.0f, nullptr, av, s);
             if (!st) st = conv_launch(true, "tidas_operator_norm_sq", kernels, K, av, 1, Z, 1, 1.0f, 0.0f, nullptr, w, s);

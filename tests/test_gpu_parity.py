@@ -78,6 +78,58 @@ def test_prepared_bank_matches_the_bank_bit_for_bit(dev, B, Z, X, K):
     assert rel(td.apply(prep, R).cpu().numpy(), ref) <= RTOL
 
 
+# Batches whose 128 x 256 tiles number at least the compute units (256) run
+# on the four-block tile; in chunks of 8 frames the same operator runs on the
+# two-block tile.  The two sum the same 16-row chunks in the same order: the
+# results agree bit for bit.  K spans every window length of the four-block
+# tile (4, 4, 6, 8, 10, 12 steps and the largest K of 12 steps); Z and X are
+# ragged against the tile.
+FOUR_BLOCK_SHAPES = [(128, 130, 40, 1), (128, 130, 40, 33), (128, 130, 40, 65), (128, 130, 40, 97),
+                     (128, 130, 40, 129), (128, 130, 40, 145), (128, 130, 40, 161), (43, 300, 300, 129)]
+
+
+def _in_chunks(fn, kb, x, n, *rest):
+    return torch.cat([fn(kb, x[i:i + n], *[r[i:i + n] if torch.is_tensor(r) else r for r in rest])
+                      for i in range(0, x.shape[0], n)])
+
+
+@pytest.mark.parametrize("B,Z,X,K", FOUR_BLOCK_SHAPES)
+def test_four_block_tile_matches_oracle_and_two_block_tile(dev, B, Z, X, K):
+    kb = g(generators.normal((Z, K), seed=K + 5), dev)
+    R = g(generators.normal((B, Z, X), seed=Z + X + K), dev)
+    base = g(generators.normal((B, Z, X), seed=Z + X + K + 1), dev)
+    prep = td.prepare(kb)
+    y, r = td.apply(kb, R), td.adjoint(kb, R)
+    assert torch.equal(y, _in_chunks(td.apply, kb, R, 8))
+    assert torch.equal(r, _in_chunks(td.adjoint, kb, R, 8))
+    assert torch.equal(td.apply(prep, R), y)
+    assert torch.equal(td.adjoint(prep, R), r)
+    ye = td.apply_ex(prep, R, 0.5, -2.0, base)
+    assert torch.equal(ye, _in_chunks(lambda k, x, b: td.apply_ex(k, x, 0.5, -2.0, b), prep, R, 8, base))
+    re_ = td.adjoint_ex(kb, R, -1.5, 0.25, base)
+    assert torch.equal(re_, _in_chunks(lambda k, x, b: td.adjoint_ex(k, x, -1.5, 0.25, b), kb, R, 8, base))
+    kn, Rn = kb.cpu().numpy(), R.cpu().numpy()
+    assert rel(y.cpu().numpy(), o_t.apply(kn, Rn)) <= RTOL
+    assert rel(r.cpu().numpy(), o_t.adjoint(kn, Rn)) <= RTOL
+    assert rel(ye.cpu().numpy(), 0.5 * o_t.apply(kn, Rn) - 2.0 * base.cpu().numpy()) <= RTOL
+
+
+def test_four_block_tile_full_frames(dev):
+    """64 frames of 1024 x 256, K = 129: oracle on three sampled frames, and
+    bit-identity with the two-block tile (chunks of 16 frames)."""
+    B, Z, X, K = 64, 1024, 256, 129
+    kb = g(generators.normal((Z, K), seed=77), dev)
+    R = g(generators.normal((B, Z, X), seed=78), dev)
+    y, r = td.apply(kb, R), td.adjoint(kb, R)
+    assert torch.equal(y, _in_chunks(td.apply, kb, R, 16))
+    assert torch.equal(r, _in_chunks(td.adjoint, kb, R, 16))
+    kn = kb.cpu().numpy()
+    for f in (0, 37, 63):
+        Rf = R[f:f + 1].cpu().numpy()
+        assert rel(y[f:f + 1].cpu().numpy(), o_t.apply(kn, Rf)) <= RTOL
+        assert rel(r[f:f + 1].cpu().numpy(), o_t.adjoint(kn, Rf)) <= RTOL
+
+
 def test_prepared_bank_through_autograd(dev):
     Z, X, K = 256, 64, 65
     kb = g(generators.normal((Z, K), seed=21), dev)
