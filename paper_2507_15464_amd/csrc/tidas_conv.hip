@@ -864,7 +864,11 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
     constexpr int NW = NSB + 6;   // window steps of the tile
     constexpr int LS = b4_lstride(NSB);
     constexpr int PB = 32 * LS;   // one plane of one block, in bf16
-    constexpr int PD = 4;         // ring slots
+    // ring slots: window step s of every frame lives in slot s % PD, and the
+    // loads that run ahead into the next frame land in slot (NW + s) % PD, so
+    // PD must divide NW
+    constexpr int PD = NW % 4 == 0 ? 4 : NW % 5 == 0 ? 5 : NW % 6 == 0 ? 6 : 7;
+    static_assert(NW % PD == 0, "ring slots must divide the window steps");
     extern __shared__ uint16_t b4_smem[];
     const int lg = xcd_remap(blockIdx.x, g.n_blocks);
     const int rt = lg % g.n_rt;
@@ -936,8 +940,60 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
     const uint16_t* a_base = b4_smem + j * LS + 8 * gk;
     constexpr int TA[6] = {0, 0, 1, 0, 1, 2};
     constexpr int TB[6] = {0, 1, 0, 2, 1, 0};
-    // first output row of this lane (D rows 4 gk + 8 (i / 4) + i % 4 of each block)
+    // Results.  Block b's window ends at step 2 b + NSB - 1; its 16 results per
+    // lane are stored at the next step (blocks 0-2 within the frame, block 3 at
+    // step 0 of the next frame or after the last), so the stores spread over
+    // the frame instead of waiting at its end.  D row 8 (i / 4) + 4 gk + i % 4
+    // of block b is tile row 32 b + that.  Every store is issued: rows below the
+    // image lie past the frame's last byte and columns past X start at
+    // INT32_MIN, so the range check drops both.
     const int vstart = col < X ? ((i0 + 4 * gk) * X + col) * 4 : INT32_MIN;
+    const bool has_base = Base0 != nullptr;
+    // base values of the block to be stored two steps on (two buffers: the
+    // store steps of consecutive blocks are two steps apart)
+    float bv[2][16];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) bv[u][i] = 0.0f;
+    // offset of block b's first result row; rebuilt from opaque values at
+    // each use, else the compiler hoists all 64 offsets out of the frame loop
+    auto block_offsets = [&](int b, int(&voff)[16]) {
+        int o = vstart, rb = row_bytes;
+        asm volatile("" : "+v"(o), "+s"(rb));
+        o += 32 * b * rb;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            voff[i] = o;
+            o += (i & 3) == 3 ? 5 * rb : rb;
+        }
+    };
+    auto frame_out = [&](int f, const float* P) {
+        // frames before the first or past the last: no record, every access dropped
+        const int fu = __builtin_amdgcn_readfirstlane(f >= 0 && f < nf ? f : 0);
+        return make_rsrc(uniform_ptr(P + (size_t)fu * fstride), f >= 0 && f < nf ? frame_bytes : 0u);
+    };
+    auto load_base = [&](int b, int f, float(&dst)[16]) {
+        if (has_base) {
+            const auto rs_b = frame_out(f, Base0);
+            int voff[16];
+            block_offsets(b, voff);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) dst[i] = buffer_load_f32(rs_b, voff[i]);
+        }
+    };
+    auto store_block = [&](int b, int f, floatx16& a, const float(&bsrc)[16]) {
+        const auto rs_o = frame_out(f, Out0);
+        int voff[16];
+        block_offsets(b, voff);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float v = fmaf(g.beta, bsrc[i], g.alpha * a[i]);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs_o, voff[i], 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = 0.0f;
+    };
 
     for (int f = 0; f < nf; ++f) {
         const auto rs_cur = frame_rsrc(f), rs_nxt = frame_rsrc(f + 1);
@@ -951,6 +1007,14 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
                 load8(rs_cur, S + PD - 1, true, ring[(S + PD - 1) % PD]);
             else
                 load8(rs_nxt, S + PD - 1 - NW, nxt_valid, ring[(S + PD - 1) % PD]);
+            // block 3 of the previous frame (none before the first)
+            if constexpr (S == 0) store_block(3, f - 1, acc[3], bv[1]);
+            // block b of this frame, its window done at the previous step
+            if constexpr (S >= NSB && S <= NSB + 4 && (S - NSB) % 2 == 0)
+                store_block((S - NSB) / 2, f, acc[(S - NSB) / 2], bv[((S - NSB) / 2) % 2]);
+            // base values for the store two steps on
+            if constexpr (S + 2 >= NSB && S + 2 <= NSB + 6 && (S + 2 - NSB) % 2 == 0)
+                load_base((S + 2 - NSB) / 2, f, bv[((S + 2 - NSB) / 2) % 2]);
             __builtin_amdgcn_sched_barrier(0);
             // blocks whose band reaches window step S: b with 2 b <= S < 2 b + NSB
             constexpr int b_lo = (S >= NSB) ? (S - NSB) / 2 + 1 : 0;
@@ -979,41 +1043,8 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
                 __builtin_amdgcn_sched_group_barrier(0x002, per, 0);  // vector instructions of the next split
             });
         });
-        // results of frame f: every store issued; rows below the image lie past
-        // the frame's last byte and columns past X start at INT32_MIN, so the
-        // range check drops both.  The offsets are rebuilt from values made
-        // opaque here, each frame: left loop-invariant they would be hoisted
-        // out of the frame loop and hold 64 registers.
-        const auto rs_o = make_rsrc(uniform_ptr(Out0 + (size_t)f * fstride), frame_bytes);
-        const bool has_base = Base0 != nullptr;
-        const auto rs_b = make_rsrc(uniform_ptr((has_base ? Base0 : Out0) + (size_t)f * fstride), frame_bytes);
-        int o = vstart, rb = row_bytes;
-        asm volatile("" : "+v"(o), "+s"(rb));
-        const int rb5 = 5 * rb;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int voff[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                voff[i] = o;
-                o += (i & 3) == 3 ? rb5 : rb;
-            }
-            float v[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = g.alpha * acc[b][i];
-            if (has_base) {
-                float bv[16];
-#pragma unroll
-                for (int i = 0; i < 16; ++i) bv[i] = buffer_load_f32(rs_b, voff[i]);
-#pragma unroll
-                for (int i = 0; i < 16; ++i) v[i] = fmaf(g.beta, bv[i], v[i]);
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[i]), rs_o, voff[i], 0, 0);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) acc[b][i] = 0.0f;
-        }
     }
+    store_block(3, nf - 1, acc[3], bv[1]);
 }
 
 struct BxGeom {

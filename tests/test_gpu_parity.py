@@ -83,9 +83,11 @@ def test_prepared_bank_matches_the_bank_bit_for_bit(dev, B, Z, X, K):
 # two-block tile.  The two sum the same 16-row chunks in the same order: the
 # results agree bit for bit.  K spans every window length of the four-block
 # tile (4, 4, 6, 8, 10, 12 steps and the largest K of 12 steps); Z and X are
-# ragged against the tile.
-FOUR_BLOCK_SHAPES = [(128, 130, 40, 1), (128, 130, 40, 33), (128, 130, 40, 65), (128, 130, 40, 97),
-                     (128, 130, 40, 129), (128, 130, 40, 145), (128, 130, 40, 161), (43, 300, 300, 129)]
+# ragged against the tile.  257 frames of two tiles give workgroups of two
+# frames (the ring of loads runs ahead across the frame boundary) and a last
+# workgroup of one frame; 43 frames of six tiles give one frame each.
+FOUR_BLOCK_SHAPES = [(257, 130, 40, 1), (257, 130, 40, 33), (257, 130, 40, 65), (257, 130, 40, 97),
+                     (257, 130, 40, 129), (257, 130, 40, 145), (257, 130, 40, 161), (43, 300, 300, 129)]
 
 
 def _in_chunks(fn, kb, x, n, *rest):
