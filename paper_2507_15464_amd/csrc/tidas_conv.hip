@@ -1019,15 +1019,16 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
             // blocks whose band reaches window step S: b with 2 b <= S < 2 b + NSB
             constexpr int b_lo = (S >= NSB) ? (S - NSB) / 2 + 1 : 0;
             constexpr int b_hi = (S / 2 < 3) ? S / 2 : 3;
+            // band operands of the step, plane-major: the first products (plane
+            // 0 of every block) wait for the first reads only
             bf16x8 A[4][3];
-            static_for<4>([&](auto B_) {
-                constexpr int b = decltype(B_)::value;
-                if constexpr (b >= b_lo && b <= b_hi) {
 #pragma unroll
-                    for (int p = 0; p < 3; ++p)
+            for (int p = 0; p < 3; ++p)
+                static_for<4>([&](auto B_) {
+                    constexpr int b = decltype(B_)::value;
+                    if constexpr (b >= b_lo && b <= b_hi)
                         A[b][p] = *reinterpret_cast<const bf16x8*>(a_base + (3 * b + p) * PB + 16 * (S - 2 * b));
-                }
-            });
+                });
 #pragma unroll
             for (int t = 0; t < 6; ++t)
                 static_for<4>([&](auto B_) {
@@ -1038,6 +1039,7 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
             split8(ring[(S + 1) % PD], Bnxt);
             constexpr int n_mfma = 6 * (b_hi - b_lo + 1);
             constexpr int per = (48 + n_mfma - 1) / n_mfma;
+            __builtin_amdgcn_sched_group_barrier(0x100, 3 * (b_hi - b_lo + 1), 0);  // the band reads first
             static_for<n_mfma>([&](auto) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
                 __builtin_amdgcn_sched_group_barrier(0x002, per, 0);  // vector instructions of the next split
