@@ -498,7 +498,7 @@ __device__ __forceinline__ void split3(float v, uint32_t& w0, uint32_t& w1, uint
 __device__ __forceinline__ bf16x8 pack8(const uint32_t (&w)[8]) {
     u32x4 p;
 #pragma unroll
-    for (int d = 0; d < 4; ++d) p[d] = (w[2 * d] >> 16) | (w[2 * d + 1] & 0xffff0000u);
+    for (int d = 0; d < 4; ++d) p[d] = __builtin_amdgcn_perm(w[2 * d + 1], w[2 * d], 0x07060302u);  // one v_perm_b32
     return __builtin_bit_cast(bf16x8, p);
 }
 
@@ -807,7 +807,10 @@ constexpr int B4_TN = 256;
 constexpr int B4_THREADS = 512;  // 8 waves
 
 __host__ __device__ constexpr int b4_lstride(int nsb) { return 16 * nsb + 8; }
-__host__ __device__ constexpr size_t b4_image_bytes(int nsb) { return (size_t)4 * 3 * 32 * b4_lstride(nsb) * 2; }
+// one block's three planes, padded to a multiple of 8 KB: each of the eight
+// waves copies the same number of 1 KB pieces of every block
+__host__ __device__ constexpr int b4_block_bytes(int nsb) { return (3 * 32 * b4_lstride(nsb) * 2 + 8191) / 8192 * 8192; }
+__host__ __device__ constexpr size_t b4_image_bytes(int nsb) { return (size_t)4 * b4_block_bytes(nsb); }
 // smallest supported NSB covering K (0: K too large for the four-block tile)
 __host__ __device__ constexpr int b4_nsb(int K) {
     const int need = (32 + K - 1 + 15) / 16;
@@ -815,7 +818,7 @@ __host__ __device__ constexpr int b4_nsb(int K) {
 }
 
 // Band image of the 128-row tile at i0 in the four-block layout
-// [block][plane][32][16 NSB + 8]: entry (b, r, c) = M[32 b + r][32 b + c] of
+// [block (stride b4_block_bytes)][plane][32][16 NSB + 8]: entry (b, r, c) = M[32 b + r][32 b + c] of
 // the tile (apply: K[i0 + 32b + r][r - c + 2h]; adjoint: K[i0 - h + 32b + c][c - r]).
 __global__ __launch_bounds__(256) void b4_prepare_kernel(const float* __restrict__ Kb, int32_t K, int32_t Z,
                                                          int32_t n_rt, int32_t nsb, uint16_t* __restrict__ prepared,
@@ -833,7 +836,8 @@ __global__ __launch_bounds__(256) void b4_prepare_kernel(const float* __restrict
     const int row = adj ? i0 - h + 32 * b + c : i0 + 32 * b + r;
     const bool ok = c < 16 * nsb && t >= 0 && t < K && row >= 0 && row < Z;
     const float v = ok ? Kb[(size_t)row * K + t] : 0.0f;
-    uint16_t* img = prepared + (size_t)(blockIdx.z * n_rt + rt) * (b4_image_bytes(nsb) / 2) + (size_t)b * 3 * per_block;
+    uint16_t* img =
+        prepared + (size_t)(blockIdx.z * n_rt + rt) * (b4_image_bytes(nsb) / 2) + (size_t)b * (b4_block_bytes(nsb) / 2);
     uint32_t w0, w1, w2;
     split3(v, w0, w1, w2);
     img[rc] = (uint16_t)(w0 >> 16);
@@ -904,21 +908,40 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         for (int e = 0; e < 8; ++e) x[e] = buffer_load_f32(rs, o + e * row_bytes);
     };
 
+    // Band image: a straight copy by direct-to-LDS 16-byte loads, 1 KB per wave
+    // load, block by block; each wave copies L pieces of every block.  Block b
+    // is first used at window step 2 b, so in the first frame each wave waits
+    // (vmcnt) for its own pieces of block b just before that step and the
+    // workgroup meets at a barrier; the copy of the later blocks overlaps the
+    // first steps.  The first steps' input loads are issued before the copy.
+    constexpr int BSE = b4_block_bytes(NSB) / 2;  // block stride in bf16
+    constexpr int L = b4_block_bytes(NSB) / 8192;
     float ring[PD][8];
     {
         const auto rs0 = frame_rsrc(0);
 #pragma unroll
         for (int u = 0; u < PD - 1; ++u) load8(rs0, u, true, ring[u]);
-        // band image: a straight copy by direct-to-LDS 16-byte loads (1 KB per wave load)
         const uint16_t* img = images + (size_t)rt * (b4_image_bytes(NSB) / 2);
-        constexpr int n_loads = (int)(b4_image_bytes(NSB) / 1024);
         const auto rs = make_rsrc(img, (uint32_t)b4_image_bytes(NSB));
-        for (int q = wave; q < n_loads; q += B4_THREADS / 64)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(b4_smem + q * 512),
-                                                     16, q * 1024 + lane * 16, 0, 0, 0);
-        __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+        for (int q = 0; q < 4 * L; ++q) {
+            const int piece = 8 * q + wave;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rs, (__attribute__((address_space(3))) void*)(b4_smem + piece * 512), 16, piece * 1024 + lane * 16, 0, 0, 0);
+        }
     }
-    __syncthreads();
+    // at window step 2 b of the first frame: this wave's pieces of block b have
+    // landed once at most n vector-memory operations issued after them are
+    // outstanding (the pieces of the later blocks and the input loads of steps
+    // 0 .. 2 b - 1; later stores and loads only make the wait longer)
+    auto band_ready = [&](auto B_) {
+        constexpr int b = decltype(B_)::value;
+        constexpr int n = (3 - b) * L + 8 * 2 * b;
+        static_assert(n <= 63, "vmcnt range");
+        __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");  // no band read is moved above the barrier
+    };
 
     floatx16 acc[4];
 #pragma unroll
@@ -949,6 +972,7 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
     // INT32_MIN, so the range check drops both.
     const int vstart = col < X ? ((i0 + 4 * gk) * X + col) * 4 : INT32_MIN;
     const bool has_base = Base0 != nullptr;
+    const bool plain = g.alpha == 1.0f && !has_base;  // results stored as accumulated
     // base values of the block to be stored two steps on (two buffers: the
     // store steps of consecutive blocks are two steps apart)
     float bv[2][16];
@@ -986,10 +1010,15 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         const auto rs_o = frame_out(f, Out0);
         int voff[16];
         block_offsets(b, voff);
+        if (plain) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const float v = fmaf(g.beta, bsrc[i], g.alpha * a[i]);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs_o, voff[i], 0, 0);
+            for (int i = 0; i < 16; ++i) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a[i]), rs_o, voff[i], 0, 0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float v = fmaf(g.beta, bsrc[i], g.alpha * a[i]);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs_o, voff[i], 0, 0);
+            }
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) a[i] = 0.0f;
@@ -1002,6 +1031,8 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
             constexpr int S = decltype(S_)::value;
             bf16x8(&Bcur)[3] = (S % 2 == 0) ? BpA : BpB;
             bf16x8(&Bnxt)[3] = (S % 2 == 0) ? BpB : BpA;
+            if constexpr (S % 2 == 0 && S <= 6)
+                if (f == 0) band_ready(std::integral_constant<int, S / 2>{});
             // prefetch the step PD - 1 ahead (of this frame or the next)
             if constexpr (S + PD - 1 < NW)
                 load8(rs_cur, S + PD - 1, true, ring[(S + PD - 1) % PD]);
@@ -1027,7 +1058,7 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
                 static_for<4>([&](auto B_) {
                     constexpr int b = decltype(B_)::value;
                     if constexpr (b >= b_lo && b <= b_hi)
-                        A[b][p] = *reinterpret_cast<const bf16x8*>(a_base + (3 * b + p) * PB + 16 * (S - 2 * b));
+                        A[b][p] = *reinterpret_cast<const bf16x8*>(a_base + b * BSE + p * PB + 16 * (S - 2 * b));
                 });
 #pragma unroll
             for (int t = 0; t < 6; ++t)

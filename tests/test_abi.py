@@ -176,13 +176,16 @@ def test_batch_entry_points_reject_invalid_arguments(lib):
 def test_prepared_bank_size_and_invalid_arguments(lib):
     # two-block images: 16 tiles of 64 rows, two modes, three bf16 planes of
     # 64 x 200 (K = 129); four-block images: 8 tiles of 128 rows, two modes,
-    # four blocks of three planes of 32 x 168 (ten 16-row window steps)
+    # four blocks of three planes of 32 x 168 (ten 16-row window steps), each
+    # block padded to a multiple of 8 KB
     two = 2 * 16 * 3 * 64 * 200 * 2
-    assert lib.tidas_prepared_bytes(129, 1024) == two + 2 * 8 * 4 * 3 * 32 * 168 * 2
+    block = -(-3 * 32 * 168 * 2 // 8192) * 8192
+    assert block == 32768
+    assert lib.tidas_prepared_bytes(129, 1024) == two + 2 * 8 * 4 * block
     # K = 163: a 32-row block's window spans 13 steps of 16 rows, more than the
     # four-block tile's 12: two-block images only (16 steps, planes 64 x 264)
     assert lib.tidas_prepared_bytes(163, 128) == 2 * 2 * 3 * 64 * 264 * 2
-    assert lib.tidas_prepared_bytes(161, 128) == 2 * 2 * 3 * 64 * 264 * 2 + 2 * 1 * 4 * 3 * 32 * 200 * 2
+    assert lib.tidas_prepared_bytes(161, 128) == 2 * 2 * 3 * 64 * 264 * 2 + 2 * 1 * 4 * 40960
     assert lib.tidas_prepared_bytes(129, 1000) == lib.tidas_prepared_bytes(129, 1024)
     assert lib.tidas_prepared_bytes(64, 1024) == 0      # even K
     assert lib.tidas_prepared_bytes(0, 1024) == 0
