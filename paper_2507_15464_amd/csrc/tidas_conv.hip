@@ -908,176 +908,201 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         for (int e = 0; e < 8; ++e) x[e] = buffer_load_f32(rs, o + e * row_bytes);
     };
 
-    // Band image: a straight copy by direct-to-LDS 16-byte loads, 1 KB per wave
-    // load, block by block; each wave copies L pieces of every block.  Block b
-    // is first used at window step 2 b, so in the first frame each wave waits
-    // (vmcnt) for its own pieces of block b just before that step and the
-    // workgroup meets at a barrier; the copy of the later blocks overlaps the
-    // first steps.  The first steps' input loads are issued before the copy.
-    constexpr int BSE = b4_block_bytes(NSB) / 2;  // block stride in bf16
-    constexpr int L = b4_block_bytes(NSB) / 8192;
-    float ring[PD][8];
-    {
-        const auto rs0 = frame_rsrc(0);
-#pragma unroll
-        for (int u = 0; u < PD - 1; ++u) load8(rs0, u, true, ring[u]);
-        const uint16_t* img = images + (size_t)rt * (b4_image_bytes(NSB) / 2);
-        const auto rs = make_rsrc(img, (uint32_t)b4_image_bytes(NSB));
-#pragma unroll
-        for (int q = 0; q < 4 * L; ++q) {
-            const int piece = 8 * q + wave;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rs, (__attribute__((address_space(3))) void*)(b4_smem + piece * 512), 16, piece * 1024 + lane * 16, 0, 0, 0);
-        }
-    }
-    // at window step 2 b of the first frame: this wave's pieces of block b have
-    // landed once at most n vector-memory operations issued after them are
-    // outstanding (the pieces of the later blocks and the input loads of steps
-    // 0 .. 2 b - 1; later stores and loads only make the wait longer)
-    auto band_ready = [&](auto B_) {
-        constexpr int b = decltype(B_)::value;
-        constexpr int n = (3 - b) * L + 8 * 2 * b;
-        static_assert(n <= 63, "vmcnt range");
-        __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00);
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");  // no band read is moved above the barrier
-    };
+    // The walk over the window.  Even row tiles take the window steps in
+    // ascending order, odd row tiles in descending order: the 128 rows that
+    // neighbouring tiles share are then read by both in the same half of the
+    // frame (the second half of the upper tile's walk is the first half of the
+    // lower tile's reversed walk, and so on down), so the second read of a row
+    // is served by the L2 instead of HBM.  Iteration I takes window step
+    // S = I (ascending) or NW - 1 - I (descending).  In either order the k-th
+    // block to start (block k ascending, 3 - k descending) is active from
+    // iteration 2 k to NSB - 1 + 2 k.
+    auto run_tile = [&](auto REV_) {
+        constexpr bool REV = decltype(REV_)::value;
+        auto step_of = [](int it) { return REV ? NW - 1 - it : it; };
+        auto block_of = [](int k) { return REV ? 3 - k : k; };
 
-    floatx16 acc[4];
+        // Band image: a straight copy by direct-to-LDS 16-byte loads, 1 KB per
+        // wave load, block by block in the order the walk needs them; each wave
+        // copies L pieces of every block.  The k-th block is first used at
+        // iteration 2 k, so in the first frame each wave waits (vmcnt) for its
+        // own pieces of that block just before that iteration and the workgroup
+        // meets at a barrier; the copy of the later blocks overlaps the first
+        // iterations.  The first iterations' input loads are issued before the copy.
+        constexpr int BSE = b4_block_bytes(NSB) / 2;  // block stride in bf16
+        constexpr int L = b4_block_bytes(NSB) / 8192;
+        float ring[PD][8];
+        {
+            const auto rs0 = frame_rsrc(0);
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+            for (int u = 0; u < PD - 1; ++u) load8(rs0, step_of(u), true, ring[u]);
+            const uint16_t* img = images + (size_t)rt * (b4_image_bytes(NSB) / 2);
+            const auto rs = make_rsrc(img, (uint32_t)b4_image_bytes(NSB));
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[b][i] = 0.0f;
-
-    auto split8 = [&](const float(&x)[8], bf16x8(&Bp)[3]) {
-        uint32_t w0[8], w1[8], w2[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) split3(x[e], w0[e], w1[e], w2[e]);
-        Bp[0] = pack8(w0);
-        Bp[1] = pack8(w1);
-        Bp[2] = pack8(w2);
-    };
-    bf16x8 BpA[3], BpB[3];
-    split8(ring[0], BpA);
-
-    const uint16_t* a_base = b4_smem + j * LS + 8 * gk;
-    constexpr int TA[6] = {0, 0, 1, 0, 1, 2};
-    constexpr int TB[6] = {0, 1, 0, 2, 1, 0};
-    // Results.  Block b's window ends at step 2 b + NSB - 1; its 16 results per
-    // lane are stored at the next step (blocks 0-2 within the frame, block 3 at
-    // step 0 of the next frame or after the last), so the stores spread over
-    // the frame instead of waiting at its end.  D row 8 (i / 4) + 4 gk + i % 4
-    // of block b is tile row 32 b + that.  Every store is issued: rows below the
-    // image lie past the frame's last byte and columns past X start at
-    // INT32_MIN, so the range check drops both.
-    const int vstart = col < X ? ((i0 + 4 * gk) * X + col) * 4 : INT32_MIN;
-    const bool has_base = Base0 != nullptr;
-    const bool plain = g.alpha == 1.0f && !has_base;  // results stored as accumulated
-    // base values of the block to be stored two steps on (two buffers: the
-    // store steps of consecutive blocks are two steps apart)
-    float bv[2][16];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) bv[u][i] = 0.0f;
-    // offset of block b's first result row; rebuilt from opaque values at
-    // each use, else the compiler hoists all 64 offsets out of the frame loop
-    auto block_offsets = [&](int b, int(&voff)[16]) {
-        int o = vstart, rb = row_bytes;
-        asm volatile("" : "+v"(o), "+s"(rb));
-        o += 32 * b * rb;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            voff[i] = o;
-            o += (i & 3) == 3 ? 5 * rb : rb;
-        }
-    };
-    auto frame_out = [&](int f, const float* P) {
-        // frames before the first or past the last: no record, every access dropped
-        const int fu = __builtin_amdgcn_readfirstlane(f >= 0 && f < nf ? f : 0);
-        return make_rsrc(uniform_ptr(P + (size_t)fu * fstride), f >= 0 && f < nf ? frame_bytes : 0u);
-    };
-    auto load_base = [&](int b, int f, float(&dst)[16]) {
-        if (has_base) {
-            const auto rs_b = frame_out(f, Base0);
-            int voff[16];
-            block_offsets(b, voff);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) dst[i] = buffer_load_f32(rs_b, voff[i]);
-        }
-    };
-    auto store_block = [&](int b, int f, floatx16& a, const float(&bsrc)[16]) {
-        const auto rs_o = frame_out(f, Out0);
-        int voff[16];
-        block_offsets(b, voff);
-        if (plain) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a[i]), rs_o, voff[i], 0, 0);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const float v = fmaf(g.beta, bsrc[i], g.alpha * a[i]);
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs_o, voff[i], 0, 0);
+            for (int q = 0; q < 4 * L; ++q) {
+                const int piece = block_of(q / L) * 8 * L + 8 * (q % L) + wave;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(b4_smem + piece * 512),
+                                                         16, piece * 1024 + lane * 16, 0, 0, 0);
             }
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) a[i] = 0.0f;
-    };
+        // at iteration 2 k of the first frame: this wave's pieces of the k-th
+        // block have landed once at most n vector-memory operations issued after
+        // them are outstanding (the pieces of the later blocks and the input
+        // loads of iterations 0 .. 2 k - 1; later stores and loads only make the
+        // wait longer)
+        auto band_ready = [&](auto K_) {
+            constexpr int k = decltype(K_)::value;
+            constexpr int n = (3 - k) * L + 8 * 2 * k;
+            static_assert(n <= 63, "vmcnt range");
+            __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00);
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");  // no band read is moved above the barrier
+        };
 
-    for (int f = 0; f < nf; ++f) {
-        const auto rs_cur = frame_rsrc(f), rs_nxt = frame_rsrc(f + 1);
-        const bool nxt_valid = f + 1 < nf;
-        static_for<NW>([&](auto S_) {
-            constexpr int S = decltype(S_)::value;
-            bf16x8(&Bcur)[3] = (S % 2 == 0) ? BpA : BpB;
-            bf16x8(&Bnxt)[3] = (S % 2 == 0) ? BpB : BpA;
-            if constexpr (S % 2 == 0 && S <= 6)
-                if (f == 0) band_ready(std::integral_constant<int, S / 2>{});
-            // prefetch the step PD - 1 ahead (of this frame or the next)
-            if constexpr (S + PD - 1 < NW)
-                load8(rs_cur, S + PD - 1, true, ring[(S + PD - 1) % PD]);
-            else
-                load8(rs_nxt, S + PD - 1 - NW, nxt_valid, ring[(S + PD - 1) % PD]);
-            // block 3 of the previous frame (none before the first)
-            if constexpr (S == 0) store_block(3, f - 1, acc[3], bv[1]);
-            // block b of this frame, its window done at the previous step
-            if constexpr (S >= NSB && S <= NSB + 4 && (S - NSB) % 2 == 0)
-                store_block((S - NSB) / 2, f, acc[(S - NSB) / 2], bv[((S - NSB) / 2) % 2]);
-            // base values for the store two steps on
-            if constexpr (S + 2 >= NSB && S + 2 <= NSB + 6 && (S + 2 - NSB) % 2 == 0)
-                load_base((S + 2 - NSB) / 2, f, bv[((S + 2 - NSB) / 2) % 2]);
-            __builtin_amdgcn_sched_barrier(0);
-            // blocks whose band reaches window step S: b with 2 b <= S < 2 b + NSB
-            constexpr int b_lo = (S >= NSB) ? (S - NSB) / 2 + 1 : 0;
-            constexpr int b_hi = (S / 2 < 3) ? S / 2 : 3;
-            // band operands of the step, plane-major: the first products (plane
-            // 0 of every block) wait for the first reads only
-            bf16x8 A[4][3];
+        floatx16 acc[4];
 #pragma unroll
-            for (int p = 0; p < 3; ++p)
-                static_for<4>([&](auto B_) {
-                    constexpr int b = decltype(B_)::value;
-                    if constexpr (b >= b_lo && b <= b_hi)
-                        A[b][p] = *reinterpret_cast<const bf16x8*>(a_base + b * BSE + p * PB + 16 * (S - 2 * b));
-                });
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int t = 0; t < 6; ++t)
-                static_for<4>([&](auto B_) {
-                    constexpr int b = decltype(B_)::value;
-                    if constexpr (b >= b_lo && b <= b_hi)
-                        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][TA[t]], Bcur[TB[t]], acc[b], 0, 0, 0);
+            for (int i = 0; i < 16; ++i) acc[b][i] = 0.0f;
+
+        auto split8 = [&](const float(&x)[8], bf16x8(&Bp)[3]) {
+            uint32_t w0[8], w1[8], w2[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) split3(x[e], w0[e], w1[e], w2[e]);
+            Bp[0] = pack8(w0);
+            Bp[1] = pack8(w1);
+            Bp[2] = pack8(w2);
+        };
+        bf16x8 BpA[3], BpB[3];
+        split8(ring[0], BpA);
+
+        const uint16_t* a_base = b4_smem + j * LS + 8 * gk;
+        constexpr int TA[6] = {0, 0, 1, 0, 1, 2};
+        constexpr int TB[6] = {0, 1, 0, 2, 1, 0};
+        // Results.  The k-th block's last iteration is NSB - 1 + 2 k; its 16
+        // results per lane are stored at the next iteration (k = 0..2 within
+        // the frame, k = 3 at iteration 0 of the next frame or after the last),
+        // so the stores spread over the frame instead of waiting at its end.
+        // D row 8 (i / 4) + 4 gk + i % 4 of block b is tile row 32 b + that.
+        // Every store is issued: rows below the image lie past the frame's last
+        // byte and columns past X start at INT32_MIN, so the range check drops both.
+        const int vstart = col < X ? ((i0 + 4 * gk) * X + col) * 4 : INT32_MIN;
+        const bool has_base = Base0 != nullptr;
+        const bool plain = g.alpha == 1.0f && !has_base;  // results stored as accumulated
+        // base values of the block to be stored two iterations on (two buffers:
+        // consecutive blocks are stored two iterations apart)
+        float bv[2][16];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) bv[u][i] = 0.0f;
+        // offset of block b's first result row; rebuilt from opaque values at
+        // each use, else the compiler hoists all 64 offsets out of the frame loop
+        auto block_offsets = [&](int b, int(&voff)[16]) {
+            int o = vstart, rb = row_bytes;
+            asm volatile("" : "+v"(o), "+s"(rb));
+            o += 32 * b * rb;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                voff[i] = o;
+                o += (i & 3) == 3 ? 5 * rb : rb;
+            }
+        };
+        auto frame_out = [&](int f, const float* P) {
+            // frames before the first or past the last: no record, every access dropped
+            const int fu = __builtin_amdgcn_readfirstlane(f >= 0 && f < nf ? f : 0);
+            return make_rsrc(uniform_ptr(P + (size_t)fu * fstride), f >= 0 && f < nf ? frame_bytes : 0u);
+        };
+        auto load_base = [&](int b, int f, float(&dst)[16]) {
+            if (has_base) {
+                const auto rs_b = frame_out(f, Base0);
+                int voff[16];
+                block_offsets(b, voff);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) dst[i] = buffer_load_f32(rs_b, voff[i]);
+            }
+        };
+        auto store_block = [&](int b, int f, floatx16& a, const float(&bsrc)[16]) {
+            const auto rs_o = frame_out(f, Out0);
+            int voff[16];
+            block_offsets(b, voff);
+            if (plain) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a[i]), rs_o, voff[i], 0, 0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const float v = fmaf(g.beta, bsrc[i], g.alpha * a[i]);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs_o, voff[i], 0, 0);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) a[i] = 0.0f;
+        };
+
+        for (int f = 0; f < nf; ++f) {
+            const auto rs_cur = frame_rsrc(f), rs_nxt = frame_rsrc(f + 1);
+            const bool nxt_valid = f + 1 < nf;
+            static_for<NW>([&](auto I_) {
+                constexpr int I = decltype(I_)::value;
+                constexpr int S = REV ? NW - 1 - I : I;
+                bf16x8(&Bcur)[3] = (I % 2 == 0) ? BpA : BpB;
+                bf16x8(&Bnxt)[3] = (I % 2 == 0) ? BpB : BpA;
+                if constexpr (I % 2 == 0 && I <= 6)
+                    if (f == 0) band_ready(std::integral_constant<int, I / 2>{});
+                // prefetch the iteration PD - 1 ahead (of this frame or the next)
+                if constexpr (I + PD - 1 < NW)
+                    load8(rs_cur, step_of(I + PD - 1), true, ring[(I + PD - 1) % PD]);
+                else
+                    load8(rs_nxt, step_of(I + PD - 1 - NW), nxt_valid, ring[(I + PD - 1) % PD]);
+                // the last block of the previous frame (none before the first)
+                if constexpr (I == 0) store_block(block_of(3), f - 1, acc[block_of(3)], bv[1]);
+                // the k-th block of this frame, its last iteration just done
+                if constexpr (I >= NSB && I <= NSB + 4 && (I - NSB) % 2 == 0) {
+                    constexpr int k = (I - NSB) / 2;
+                    store_block(block_of(k), f, acc[block_of(k)], bv[k % 2]);
+                }
+                // base values for the store two iterations on
+                if constexpr (I + 2 >= NSB && I + 2 <= NSB + 6 && (I + 2 - NSB) % 2 == 0) {
+                    constexpr int k = (I + 2 - NSB) / 2;
+                    load_base(block_of(k), f, bv[k % 2]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                // blocks whose band reaches window step S: b with 2 b <= S < 2 b + NSB
+                constexpr int b_lo = (S >= NSB) ? (S - NSB) / 2 + 1 : 0;
+                constexpr int b_hi = (S / 2 < 3) ? S / 2 : 3;
+                // band operands of the step, plane-major: the first products
+                // (plane 0 of every block) wait for the first reads only
+                bf16x8 A[4][3];
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+                    static_for<4>([&](auto B_) {
+                        constexpr int b = decltype(B_)::value;
+                        if constexpr (b >= b_lo && b <= b_hi)
+                            A[b][p] = *reinterpret_cast<const bf16x8*>(a_base + b * BSE + p * PB + 16 * (S - 2 * b));
+                    });
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+                    static_for<4>([&](auto B_) {
+                        constexpr int b = decltype(B_)::value;
+                        if constexpr (b >= b_lo && b <= b_hi)
+                            acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][TA[t]], Bcur[TB[t]], acc[b], 0, 0, 0);
+                    });
+                split8(ring[(I + 1) % PD], Bnxt);
+                constexpr int n_mfma = 6 * (b_hi - b_lo + 1);
+                constexpr int per = (48 + n_mfma - 1) / n_mfma;
+                __builtin_amdgcn_sched_group_barrier(0x100, 3 * (b_hi - b_lo + 1), 0);  // the band reads first
+                static_for<n_mfma>([&](auto) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x002, per, 0);  // vector instructions of the next split
                 });
-            split8(ring[(S + 1) % PD], Bnxt);
-            constexpr int n_mfma = 6 * (b_hi - b_lo + 1);
-            constexpr int per = (48 + n_mfma - 1) / n_mfma;
-            __builtin_amdgcn_sched_group_barrier(0x100, 3 * (b_hi - b_lo + 1), 0);  // the band reads first
-            static_for<n_mfma>([&](auto) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
-                __builtin_amdgcn_sched_group_barrier(0x002, per, 0);  // vector instructions of the next split
             });
-        });
-    }
-    store_block(3, nf - 1, acc[3], bv[1]);
+        }
+        store_block(block_of(3), nf - 1, acc[block_of(3)], bv[1]);
+    };
+    if (rt & 1) run_tile(std::true_type{});
+    else run_tile(std::false_type{});
 }
 
 struct BxGeom {

@@ -80,14 +80,22 @@ def test_prepared_bank_matches_the_bank_bit_for_bit(dev, B, Z, X, K):
 
 # Batches whose 128 x 256 tiles number at least the compute units (256) run
 # on the four-block tile; in chunks of 8 frames the same operator runs on the
-# two-block tile.  The two sum the same 16-row chunks in the same order: the
-# results agree bit for bit.  K spans every window length of the four-block
+# two-block tile.  On even 128-row tiles the two sum the same 16-row chunks in
+# the same order: those rows agree bit for bit.  Odd tiles walk their window in
+# descending order (same products, other summation order): float32 rounding apart.  K spans every window length of the four-block
 # tile (4, 4, 6, 8, 10, 12 steps and the largest K of 12 steps); Z and X are
 # ragged against the tile.  257 frames of two tiles give workgroups of two
 # frames (the ring of loads runs ahead across the frame boundary) and a last
 # workgroup of one frame; 43 frames of six tiles give one frame each.
 FOUR_BLOCK_SHAPES = [(257, 130, 40, 1), (257, 130, 40, 33), (257, 130, 40, 65), (257, 130, 40, 97),
                      (257, 130, 40, 129), (257, 130, 40, 145), (257, 130, 40, 161), (43, 300, 300, 129)]
+
+
+def _same_tiles(a, b):
+    """Rows of even 128-row tiles bit-identical, the rest within float32 rounding."""
+    even = (torch.arange(a.shape[-2], device=a.device) // 128) % 2 == 0
+    assert torch.equal(a[..., even, :], b[..., even, :])
+    assert rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6
 
 
 def _in_chunks(fn, kb, x, n, *rest):
@@ -102,14 +110,14 @@ def test_four_block_tile_matches_oracle_and_two_block_tile(dev, B, Z, X, K):
     base = g(generators.normal((B, Z, X), seed=Z + X + K + 1), dev)
     prep = td.prepare(kb)
     y, r = td.apply(kb, R), td.adjoint(kb, R)
-    assert torch.equal(y, _in_chunks(td.apply, kb, R, 8))
-    assert torch.equal(r, _in_chunks(td.adjoint, kb, R, 8))
+    _same_tiles(y, _in_chunks(td.apply, kb, R, 8))
+    _same_tiles(r, _in_chunks(td.adjoint, kb, R, 8))
     assert torch.equal(td.apply(prep, R), y)
     assert torch.equal(td.adjoint(prep, R), r)
     ye = td.apply_ex(prep, R, 0.5, -2.0, base)
-    assert torch.equal(ye, _in_chunks(lambda k, x, b: td.apply_ex(k, x, 0.5, -2.0, b), prep, R, 8, base))
+    _same_tiles(ye, _in_chunks(lambda k, x, b: td.apply_ex(k, x, 0.5, -2.0, b), prep, R, 8, base))
     re_ = td.adjoint_ex(kb, R, -1.5, 0.25, base)
-    assert torch.equal(re_, _in_chunks(lambda k, x, b: td.adjoint_ex(k, x, -1.5, 0.25, b), kb, R, 8, base))
+    _same_tiles(re_, _in_chunks(lambda k, x, b: td.adjoint_ex(k, x, -1.5, 0.25, b), kb, R, 8, base))
     kn, Rn = kb.cpu().numpy(), R.cpu().numpy()
     assert rel(y.cpu().numpy(), o_t.apply(kn, Rn)) <= RTOL
     assert rel(r.cpu().numpy(), o_t.adjoint(kn, Rn)) <= RTOL
@@ -118,13 +126,13 @@ def test_four_block_tile_matches_oracle_and_two_block_tile(dev, B, Z, X, K):
 
 def test_four_block_tile_full_frames(dev):
     """64 frames of 1024 x 256, K = 129: oracle on three sampled frames, and
-    bit-identity with the two-block tile (chunks of 16 frames)."""
+    agreement with the two-block tile (chunks of 16 frames)."""
     B, Z, X, K = 64, 1024, 256, 129
     kb = g(generators.normal((Z, K), seed=77), dev)
     R = g(generators.normal((B, Z, X), seed=78), dev)
     y, r = td.apply(kb, R), td.adjoint(kb, R)
-    assert torch.equal(y, _in_chunks(td.apply, kb, R, 16))
-    assert torch.equal(r, _in_chunks(td.adjoint, kb, R, 16))
+    _same_tiles(y, _in_chunks(td.apply, kb, R, 16))
+    _same_tiles(r, _in_chunks(td.adjoint, kb, R, 16))
     kn = kb.cpu().numpy()
     for f in (0, 37, 63):
         Rf = R[f:f + 1].cpu().numpy()
