@@ -612,11 +612,14 @@ __device__ __forceinline__ void bx_tile(const uint16_t* __restrict__ img, const 
     };
 
     floatx2 ring[BX_PD][8];
-    // Walk order: ascending window steps.  (Every line-model kernel sums the
-    // same 16-row chunks of the window in the same ascending order, the
-    // products outside a row's band being exact zeros, so all of them give
-    // the same bits.)
-    auto local_step = [&](int q) { return q; };
+    // Walk order: window steps ascending for output rows in even 128-row bands
+    // (i0 / 128 even), descending in odd ones.  Every line-model kernel sums a
+    // row's 16-row chunks in this order (the products outside a row's band are
+    // exact zeros), so all of them give the same bits; and a tile whose walk
+    // is mirrored against its neighbour's reads their shared rows at the same
+    // time, so the second read hits L2.
+    const bool rev = ((i0 / 128) & 1) != 0;
+    auto local_step = [&](int q) { return rev ? NS - 1 - q : q; };
     // first steps' input loads in flight while the band image is brought in
     {
         const auto rs0 = frame_rsrc(0);
@@ -909,7 +912,8 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
     };
 
     // The walk over the window.  Even row tiles take the window steps in
-    // ascending order, odd row tiles in descending order: the 128 rows that
+    // ascending order, odd row tiles in descending order (the order of the
+    // two-block tile for the same rows, so both give the same bits): the 128 rows that
     // neighbouring tiles share are then read by both in the same half of the
     // frame (the second half of the upper tile's walk is the first half of the
     // lower tile's reversed walk, and so on down), so the second read of a row
