@@ -938,25 +938,34 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         float ring[PD][8];
         {
             const auto rs0 = frame_rsrc(0);
-#pragma unroll
-            for (int u = 0; u < PD - 1; ++u) load8(rs0, step_of(u), true, ring[u]);
             const uint16_t* img = images + (size_t)rt * (b4_image_bytes(NSB) / 2);
             const auto rs = make_rsrc(img, (uint32_t)b4_image_bytes(NSB));
+            auto copy_block = [&](int k) {
 #pragma unroll
-            for (int q = 0; q < 4 * L; ++q) {
-                const int piece = block_of(q / L) * 8 * L + 8 * (q % L) + wave;
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(b4_smem + piece * 512),
-                                                         16, piece * 1024 + lane * 16, 0, 0, 0);
-            }
+                for (int u = 0; u < L; ++u) {
+                    const int piece = block_of(k) * 8 * L + 8 * u + wave;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rs, (__attribute__((address_space(3))) void*)(b4_smem + piece * 512), 16,
+                        piece * 1024 + lane * 16, 0, 0, 0);
+                }
+            };
+            // what the first iteration needs goes first: its input rows and
+            // the first block, then the other prefetched rows and blocks
+            load8(rs0, step_of(0), true, ring[0]);
+            copy_block(0);
+#pragma unroll
+            for (int u = 1; u < PD - 1; ++u) load8(rs0, step_of(u), true, ring[u]);
+#pragma unroll
+            for (int k = 1; k < 4; ++k) copy_block(k);
         }
         // at iteration 2 k of the first frame: this wave's pieces of the k-th
         // block have landed once at most n vector-memory operations issued after
-        // them are outstanding (the pieces of the later blocks and the input
-        // loads of iterations 0 .. 2 k - 1; later stores and loads only make the
-        // wait longer)
+        // them are outstanding (the pieces of the later blocks, the input loads
+        // of iterations 1 .. PD - 2 for the first block, those issued by
+        // iterations 0 .. 2 k - 1; later stores and loads only make the wait longer)
         auto band_ready = [&](auto K_) {
             constexpr int k = decltype(K_)::value;
-            constexpr int n = (3 - k) * L + 8 * 2 * k;
+            constexpr int n = (3 - k) * L + (k == 0 ? 8 * (PD - 2) : 8 * 2 * k);
             static_assert(n <= 63, "vmcnt range");
             __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00);
             __builtin_amdgcn_s_barrier();
