@@ -34,6 +34,8 @@
 
 namespace tidas {
 
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
 constexpr int DAS_MAX_ANGLES = 32;
 
 struct DasArgs {
@@ -110,6 +112,7 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
     for (int f = 0; f < FB; ++f) acc[f] = 0.0f;
 
     const uint32_t row_bytes = (uint32_t)p.T * 4u;
+    const int last_pair = (p.T - 2) * 4;  // byte offset of the last sample pair
 #pragma unroll 2
     for (int n = n_lo; n <= n_hi; ++n) {
         const float dx = fmaf(-(float)n, pitch_f, dx0);
@@ -124,12 +127,18 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
                 const float v = f_a[a] + ke;
                 const float qf = floorf(v);
                 const float fr = v - qf;
+                // Both samples of the read come from one 8-byte load at the
+                // pair's offset clamped into [0, T - 2]; the clamp's shift d
+                // (in bytes) says which of the two loaded samples the read
+                // needs: d = 0 both, d = -4 (q = -1) the first as S[q + 1],
+                // d = +4 (q = T - 1) the second as S[q], otherwise none (the
+                // read lies outside the record and is 0).  The weights fold
+                // the interpolation, the case and the apodization.
                 const int off = (q_a[a] + (int)qf) * 4;
-                // the neighbour's offset computed apart (not off + 4): the two
-                // dword loads must not be merged into one 8-byte load, whose
-                // range check at sample -1 (offset -4, huge unsigned) would
-                // also discard the in-range sample 0
-                const int off1 = (q_a[a] + (int)(qf + 1.0f)) * 4;
+                const int oc = min(max(off, 0), last_pair);
+                const int d = off - oc;
+                const float wa = d == 0 ? w * (1.0f - fr) : (d == -4 ? w * fr : 0.0f);
+                const float wb = d == 0 ? w * fr : (d == 4 ? w * (1.0f - fr) : 0.0f);
 #pragma unroll
                 for (int f = 0; f < FB; ++f) {
                     // every frame slot loads (a slot past the group's last frame
@@ -138,9 +147,8 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
                     const bool fv = f < nfr;
                     const size_t ch = (size_t)a * p.C + n;
                     const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
-                    const float s0 = buffer_load_f32(rs, off);
-                    const float s1 = buffer_load_f32(rs, off1);
-                    acc[f] = fmaf(w, fmaf(fr, s1 - s0, s0), acc[f]);
+                    const floatx2 s = __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
+                    acc[f] = fmaf(wb, s[1], fmaf(wa, s[0], acc[f]));
                 }
             }
         }
