@@ -1,14 +1,16 @@
 // Exact Delay-and-Sum beamformer for plane-wave transmits (Sec. 2, eqn:appF).
 //
-// Mapping on gfx950: one wavefront = 64 consecutive image columns of ONE depth
-// row (lane l: column l); a workgroup = 4 consecutive rows of those columns.
-// For a fixed element n the lanes read a short, monotone window of that
-// element's channel: along a row the sample index changes by at most
-// dx fs / (c F') per column (~1.5 samples here), while down a column it grows
-// by 2 dz fs / c (~3.8): a row of 64 pixels spans ~100 samples, a column of
-// 64 ~250, and the gather path, not the arithmetic, bounds this kernel
-// (measured on the benchmark workload: 0.83 ms per 64 frames as rows, 1.71 ms
-// as columns, 1.2 ms as 4 x 16 tiles).
+// Mapping on gfx950: one wavefront = a tile of 2 depth rows x 32 consecutive
+// image columns (lane l: row l % 2, column l / 2); a workgroup stacks 4 such
+// tiles in depth (8 rows x 32 columns).  For a fixed element n the lanes read
+// a short, monotone window of that element's channel: along a row the sample
+// index changes by at most dx fs / (c F') per column (~1.5 samples here),
+// down a column by 2 dz fs / c (~3.8), so the tile spans ~55 samples (a row of
+// 64 pixels ~100, a column of 64 ~250).  The channel gathers, not the
+// arithmetic, bound this kernel; measured on the benchmark workload (64
+// frames, with the paired 8-byte reads below): 0.57 ms as 2 x 32 tiles, 0.60
+// as 1 x 64 and as 4 x 16, 0.72 as 8 x 8 (wider tiles also waste lanes on
+// elements outside their own aperture).
 //
 // Delay precision.  The fractional sample index is split:
 //   u = fs (tau_tx(x_j, z_i; a) + z_i / c - t0)      [per pixel, float64]
@@ -53,11 +55,16 @@ struct DasGrid {
     double z0, dz, x0, dx;
 };
 
-constexpr int DAS_WZ = 1;   // depth rows per wave tile
-constexpr int DAS_WX = 64;  // image columns per wave tile
+// Wave tile: WZ depth rows x 64 / WZ columns.  One angle: 2 x 32 (the
+// narrowest sample windows); several angles: 1 x 64 (a steered transmit adds
+// x sin(alpha) to the index, so rows of pixels spread less than two-row tiles
+// over the angles' windows; measured on the 11-angle batch: 5.5 ms as 1 x 64,
+// 9.2 ms as 2 x 32).
+__host__ __device__ constexpr int das_wz(int na) { return na == 1 ? 2 : 1; }
+__host__ __device__ constexpr int das_wx(int na) { return 64 / das_wz(na); }
 constexpr int DAS_BZ = 4;   // wave tiles per workgroup, stacked in depth
 
-// One wave: the 1 x 64 pixel tile at row i_base, columns j_base.., for FB
+// One wave: the WZ x WX pixel tile at rows i_base.., columns j_base.., for FB
 // frames sharing the geometry.  rf points at the first frame's [A][C][T]
 // record, img at its [nz][nx] image; frame f of the group is rf + f *
 // frame_rf, img + f * frame_img.
@@ -65,17 +72,21 @@ template <int FB, int NA>
 __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, int i_base, int j_base, int nfr,
                                          const float* __restrict__ rf, size_t frame_rf, float* img,
                                          size_t frame_img) {
+    constexpr int WZ = das_wz(NA), WX = das_wx(NA);
     const int lane = threadIdx.x & 63;
-    const int i = i_base + (lane % DAS_WZ);
-    const int j = j_base + (lane / DAS_WZ);
+    const int i = i_base + (lane % WZ);
+    const int j = j_base + (lane / WZ);
     const int A = (NA > 0) ? NA : p.A;
 
     const double xd = gr.x0 + (double)min(j, gr.nx - 1) * gr.dx;
-    // lateral offset to element n: x_j - x_n = (x_j - x_0) - n pitch, the first
-    // term rounded once to float32 per pixel, the second by one fused
-    // multiply-add per element (both errors ~1e-9 m: ~2e-5 samples of delay)
-    const float dx0 = (float)(xd - p.x_first);
-    const float pitch_f = (float)p.pitch;
+    // lateral offset to element n: x_j - x_n = (x_j - x_0) - n pitch with the
+    // origin and the pitch as float32 pairs (hi + lo): fma(-n, pitch_hi,
+    // origin_hi) is rounded once from its exact value, and the lo terms carry
+    // the rest, so dx keeps float32 accuracy relative to its own size (as the
+    // float64 difference rounded to float32 would), not to the origin's
+    const double ox = xd - p.x_first;
+    const float dx0 = (float)ox, dx0_lo = (float)(ox - (double)dx0);
+    const float pitch_f = (float)p.pitch, pitch_lo = (float)(p.pitch - (double)pitch_f);
     const double zd = gr.z0 + (double)min(i, gr.nz - 1) * gr.dz;
     const bool active = (i < gr.nz) && (j < gr.nx) && (zd > 0.0);
     const float zf = (float)zd;
@@ -96,10 +107,10 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
     }
 
     // element range covering the widest aperture among the tile's pixels
-    const int i_last = min(i_base + DAS_WZ - 1, gr.nz - 1);
+    const int i_last = min(i_base + WZ - 1, gr.nz - 1);
     const double z_last = gr.z0 + (double)i_last * gr.dz;
     const double x_lo = gr.x0 + (double)j_base * gr.dx;
-    const double x_hi = gr.x0 + (double)min(j_base + DAS_WX - 1, gr.nx - 1) * gr.dx;
+    const double x_hi = gr.x0 + (double)min(j_base + WX - 1, gr.nx - 1) * gr.dx;
     int n_lo = 0, n_hi = -1;
     if (z_last > 0.0) {
         const double a_max = z_last / (2.0 * p.fnumber);
@@ -115,7 +126,8 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
     const int last_pair = (p.T - 2) * 4;  // byte offset of the last sample pair
 #pragma unroll 2
     for (int n = n_lo; n <= n_hi; ++n) {
-        const float dx = fmaf(-(float)n, pitch_f, dx0);
+        const float nf = (float)n;
+        const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
         const float t = fabsf(dx) * inv_az;
         const float wh = hann_weight(fminf(t, 1.0f));
         const float w = (active && t <= 1.0f) ? wh : 0.0f;
@@ -127,28 +139,44 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
                 const float v = f_a[a] + ke;
                 const float qf = floorf(v);
                 const float fr = v - qf;
-                // Both samples of the read come from one 8-byte load at the
-                // pair's offset clamped into [0, T - 2]; the clamp's shift d
-                // (in bytes) says which of the two loaded samples the read
-                // needs: d = 0 both, d = -4 (q = -1) the first as S[q + 1],
-                // d = +4 (q = T - 1) the second as S[q], otherwise none (the
-                // read lies outside the record and is 0).  The weights fold
-                // the interpolation, the case and the apodization.
                 const int off = (q_a[a] + (int)qf) * 4;
-                const int oc = min(max(off, 0), last_pair);
-                const int d = off - oc;
-                const float wa = d == 0 ? w * (1.0f - fr) : (d == -4 ? w * fr : 0.0f);
-                const float wb = d == 0 ? w * fr : (d == 4 ? w * (1.0f - fr) : 0.0f);
+                const size_t ch = (size_t)a * p.C + n;
+                if constexpr (FB > 1) {
+                    // Both samples of the read come from one 8-byte load at the
+                    // pair's offset clamped into [0, T - 2]; the clamp's shift d
+                    // (in bytes) says which of the two loaded samples the read
+                    // needs: d = 0 both, d = -4 (q = -1) the first as S[q + 1],
+                    // d = +4 (q = T - 1) the second as S[q], otherwise none (the
+                    // read lies outside the record and is 0).  The weights fold
+                    // the interpolation, the case and the apodization, once for
+                    // the FB frames.
+                    const int oc = min(max(off, 0), last_pair);
+                    const int d = off - oc;
+                    const float wa = d == 0 ? w * (1.0f - fr) : (d == -4 ? w * fr : 0.0f);
+                    const float wb = d == 0 ? w * fr : (d == 4 ? w * (1.0f - fr) : 0.0f);
 #pragma unroll
-                for (int f = 0; f < FB; ++f) {
-                    // every frame slot loads (a slot past the group's last frame
-                    // has an empty record: it reads 0 and is never stored), so the
-                    // loads of all slots and of the next element are in flight together
-                    const bool fv = f < nfr;
-                    const size_t ch = (size_t)a * p.C + n;
-                    const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
-                    const floatx2 s = __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
-                    acc[f] = fmaf(wb, s[1], fmaf(wa, s[0], acc[f]));
+                    for (int f = 0; f < FB; ++f) {
+                        // every frame slot loads (a slot past the group's last
+                        // frame has an empty record: it reads 0 and is never
+                        // stored), so the loads of all slots and of the next
+                        // element are in flight together
+                        const bool fv = f < nfr;
+                        const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
+                        const floatx2 sp =
+                            __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
+                        acc[f] = fmaf(wb, sp[1], fmaf(wa, sp[0], acc[f]));
+                    }
+                } else {
+                    // one frame (per-angle work not shared): two dword reads, each
+                    // range-checked on its own.  The neighbour's offset is computed
+                    // apart (not off + 4) so that the two loads are not merged into
+                    // one 8-byte load, whose range check at sample -1 (offset -4,
+                    // huge unsigned) would also discard the in-range sample 0.
+                    const int off1 = (q_a[a] + (int)(qf + 1.0f)) * 4;
+                    const auto rs = make_rsrc(rf + ch * p.T, nfr > 0 ? row_bytes : 0u);
+                    const float s0 = buffer_load_f32(rs, off);
+                    const float s1 = buffer_load_f32(rs, off1);
+                    acc[0] = fmaf(w, fmaf(fr, s1 - s0, s0), acc[0]);
                 }
             }
         }
@@ -160,7 +188,7 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
     }
 }
 
-// workgroup = DAS_BZ wave tiles stacked in depth: 4 rows x 64 columns
+// workgroup = DAS_BZ wave tiles stacked in depth
 template <int FB, int NA>
 __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid gr, const float* __restrict__ rf,
                                                   float* __restrict__ img) {
@@ -168,14 +196,14 @@ __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid
     const int fr0 = blockIdx.z * FB;
     const size_t frame_rf = (size_t)p.A * p.C * p.T;
     const size_t frame_img = (size_t)gr.nz * gr.nx;
-    das_wave<FB, NA>(p, gr, (blockIdx.x * DAS_BZ + wave) * DAS_WZ, blockIdx.y * DAS_WX, min(FB, p.n_frames - fr0),
+    das_wave<FB, NA>(p, gr, (blockIdx.x * DAS_BZ + wave) * das_wz(NA), blockIdx.y * das_wx(NA), min(FB, p.n_frames - fr0),
                      rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
 }
 
 // ----------------------------------------------------------------- batches ----
 // Ragged batch: every frame has its own grid, RF record and image.  One
-// persistent launch covers the tiles (WAVES rows x 64 columns, one wave per
-// row) of all frames.
+// persistent launch covers the tiles (WAVES wave tiles stacked in depth) of
+// all frames.
 // The tile list is cut into 8 contiguous chunks, chunk x served by the
 // workgroups the hardware places on XCD x (block id = x mod 8), so each frame's
 // RF stays in one XCD's L2.  Every workgroup walks its chunk with a fixed
@@ -211,18 +239,19 @@ __global__ __launch_bounds__(WAVES * 64) void das_batch_kernel(const DasArgs p, 
         const int f = find_frame(fr, n_frames, t);
         const DasGrid gr = fr[f].grid;
         const int64_t local = t - fr[f].tile_start;
-        // tile of WAVES rows x 64 columns, one wave tile per row
-        const int row_tiles = (gr.nz + WAVES * DAS_WZ - 1) / (WAVES * DAS_WZ);
+        // tile of WAVES wave tiles stacked in depth
+        constexpr int WZ = das_wz(NA);
+        const int row_tiles = (gr.nz + WAVES * WZ - 1) / (WAVES * WZ);
         const int rt = (int)(local % row_tiles);
         const int ct = (int)(local / row_tiles);
-        const int i_base = (rt * WAVES + wave) * DAS_WZ;
-        if (i_base < gr.nz) das_wave<1, NA>(p, gr, i_base, ct * DAS_WX, 1, fr[f].rf, 0, fr[f].out, 0);
+        const int i_base = (rt * WAVES + wave) * WZ;
+        if (i_base < gr.nz) das_wave<1, NA>(p, gr, i_base, ct * das_wx(NA), 1, fr[f].rf, 0, fr[f].out, 0);
     }
 }
 
 template <int FB, int NA>
 static void launch_das(const DasArgs& p, const DasGrid& gr, const float* rf, float* img, hipStream_t s) {
-    dim3 grid((gr.nz + DAS_BZ * DAS_WZ - 1) / (DAS_BZ * DAS_WZ), (gr.nx + DAS_WX - 1) / DAS_WX,
+    dim3 grid((gr.nz + DAS_BZ * das_wz(NA) - 1) / (DAS_BZ * das_wz(NA)), (gr.nx + das_wx(NA) - 1) / das_wx(NA),
               (p.n_frames + FB - 1) / FB);
     hipLaunchKernelGGL((das_kernel<FB, NA>), grid, dim3(256), 0, s, p, gr, rf, img);
 }
@@ -364,7 +393,9 @@ extern "C" int32_t das_beamform_batch(const tidas_array* array, const tidas_tx* 
     const int per_cu = (variant >> 1) == 0 ? 2 : ((variant >> 1) == 1 ? 4 : 8);
     hipStream_t s = (hipStream_t)stream;
     int64_t total = 0;
-    if ((st = upload_batch(frames, n_frames, waves * DAS_WZ, DAS_WX, workspace, s, total))) return st;
+    // the tile of the kernel launched below (one angle: das_wz(1); else das_wz(0) = das_wz(11))
+    const int na = p.A == 1 ? 1 : 0;
+    if ((st = upload_batch(frames, n_frames, waves * das_wz(na), das_wx(na), workspace, s, total))) return st;
     int dev = 0, n_cu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
