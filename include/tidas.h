@@ -195,12 +195,13 @@ int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float* image_bar
  * Prepared kernel bank.  The line model's kernels (Sec. 2.4, eqn:line_conv)
  * depend on the geometry only, so a caller that applies one bank to many
  * frames can convert it once: tidas_prepare writes, for the forward operator
- * and its adjoint, the banded matrix of every 64-row tile of the bank with
- * each float32 tap cut exactly into three bfloat16 parts (the form the
- * split-bfloat16 matrix-core kernels of tidas_apply read; tidas_apply builds
- * it in a temporary buffer on every call).  tidas_apply_prepared and
- * tidas_adjoint_prepared then give the same results as tidas_apply_ex and
- * tidas_adjoint_ex on that bank, bit for bit.
+ * and its adjoint, the banded matrix of every 64-row tile of the bank and (K
+ * <= 161) of every 128-row tile, with each float32 tap cut exactly into three
+ * bfloat16 parts (the forms the split-bfloat16 matrix-core kernels of
+ * tidas_apply read; tidas_apply builds the one it needs in a temporary buffer
+ * on every call).  tidas_apply_prepared and tidas_adjoint_prepared then give
+ * the same results as tidas_apply_ex and tidas_adjoint_ex on that bank, bit
+ * for bit (every line-model kernel sums a row's taps in the same order).
  *
  * tidas_prepared_bytes: size of the prepared form for K taps and Z rows; 0
  * when K is even, < 1, or too large for the matrix-core tiles (K > 321).
