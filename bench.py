@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=64, help="frames per step")
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle parity check")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
+    ap.add_argument("--cpu-pool", action="store_true",
+                    help="also time the CPU oracle over a pool of worker processes (one per host core, at most 16)")
     ap.add_argument("--only", choices=["tidas", "das"], default=None, help="time one op only (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one plain device copy of the input batch (known byte count) so "
@@ -102,8 +104,44 @@ def main():
      "approx": run_approx}[args.workload](args)
 
 
+def _oracle_apply_frames(task):
+    """One worker task of the pooled CPU baseline: the oracle line model on a
+    batch of frames (runs in a process forked before the GPU is touched)."""
+    from oracle import tidas as o_t
+    kb, R = task
+    o_t.apply(kb, R)
+    return R.shape[0]
+
+
+def _cpu_pool():
+    """Worker processes for the pooled CPU baseline, forked before anything
+    initialises the GPU (they never touch it): one per host core the job may
+    use, at most 16.  None when the host has a single core."""
+    import multiprocessing
+    n = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1))
+    if n < 2:
+        return None
+    return multiprocessing.get_context("fork").Pool(n)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def run_main(args):
     import numpy as np
+
+    # the pooled CPU baseline's workers are forked here, before torch touches the GPU
+    # (opt-in: with the idle workers present the DAS launches measured ~40 % slower)
+    pool = _cpu_pool() if (args.cpu_pool and not args.no_cpu_baseline) else None
+
     import torch
 
     import paper_2507_15464_amd as td
@@ -320,6 +358,21 @@ def run_main(args):
             n_d += 1
         out["cpu_baseline_das"] = {"value": n_d / (time.perf_counter() - t_c), "unit": "frames/s", "cores": 1,
                                    "kind": "oracle", "sample": f"FP64 oracle DAS on {n_d} frames, about 8 s"}
+        out["cpu_model"] = _cpu_model()
+        if pool is not None:
+            # the same oracle over a process pool, one batch of 4 frames per task, for ~12 s
+            n_w = pool._processes
+            tasks = [(kb_o, Rc)] * n_w
+            n_fr, t_c = 0, time.perf_counter()
+            while time.perf_counter() - t_c < 12.0:
+                n_fr += sum(pool.map(_oracle_apply_frames, tasks))
+            out["cpu_baseline_pool"] = {"value": n_fr / (time.perf_counter() - t_c), "unit": "frames/s",
+                                        "cores": n_w, "kind": "oracle",
+                                        "sample": f"FP64 oracle line model on {n_fr} frames over {n_w} worker "
+                                                  f"processes (batches of 4 frames), about 12 s"}
+    if pool is not None:
+        pool.close()
+        pool.join()
     print(json.dumps(out), flush=True)
 
 
