@@ -228,17 +228,16 @@ def run_main(args):
     hbm_bytes = (8.0 * Z * X) * B + 4.0 * Z * K       # read R + write Y per frame, kernel bank once
     achieved_tflops = flops / (tid_ms * 1e-3) / 1e12
     achieved_gbs = hbm_bytes / (tid_ms * 1e-3) / 1e9
-    # The line-model kernel the library picks for this launch: the four-block
-    # tile (128 x 256) when its band window fits (K <= 161), X % 4 == 0 and the
+    # The line-model kernel the library picks for this launch (tidas_line_kernel):
+    # the four-block tile (128 x 256) when its band window fits (K <= 161) and the
     # batch's tiles cover every compute unit, else the two-block tile (64 x 256).
     # Matrix work issued: per tile row and column, a window of 16 NSB (four-block:
     # NSB in 4..12 steps per 32-row block) or 16 NS rows (two-block: NS a multiple
     # of 4), six bf16 products per float32 product.
-    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
     need = (32 + K - 1 + 15) // 16
     nsb = next((n for n in (4, 6, 8, 10, 12) if n >= need), 0)
     cols = -(-X // 256) * 256
-    if nsb and X % 4 == 0 and (-(-Z // 128)) * (cols // 256) * B >= n_cu:
+    if td.line_kernel(K, B, Z, X) == td._lib.LINE_FOUR_BLOCK:
         kernel = f"tidas_b4_kernel<false,{nsb}>"
         mfma_flops = 2.0 * 6 * (16 * nsb) * (-(-Z // 128) * 128) * cols * B
     else:

@@ -192,6 +192,26 @@ int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float* image_bar
                          float alpha, float beta, const float* base, float* refl_bar, void* stream);
 
 /*
+ * Which line-model kernel tidas_apply / tidas_adjoint (and their fused and
+ * prepared forms) run for K taps, B frames of Z x X (16-byte aligned
+ * buffers): a diagnostic for callers and tests, enqueues nothing.
+ *   TIDAS_LINE_FOUR_BLOCK  split-bfloat16 matrix cores, 128 x 256 tiles (K <= 161,
+ *                          at least one tile per compute unit)
+ *   TIDAS_LINE_TWO_BLOCK   split-bfloat16 matrix cores, 64 x 256 tiles (K <= 321)
+ *   TIDAS_LINE_FP32_MATRIX float32 matrix cores (larger K)
+ *   TIDAS_LINE_VECTOR      vector ALU
+ * TIDAS_EINVAL for even or non-positive K or sizes, TIDAS_EUNSUPPORTED when no
+ * kernel takes K.  The four forms give the same results to float32 rounding;
+ * the two split-bfloat16 tiles give the same bits.
+ */
+#define TIDAS_LINE_FOUR_BLOCK 1
+#define TIDAS_LINE_TWO_BLOCK 2
+#define TIDAS_LINE_FP32_MATRIX 3
+#define TIDAS_LINE_VECTOR 4
+int32_t tidas_line_kernel(int32_t K, int32_t B, int32_t Z, int32_t X);
+
+/*
+ * Prepared kernel bank./*
  * Prepared kernel bank.  The line model's kernels (Sec. 2.4, eqn:line_conv)
  * depend on the geometry only, so a caller that applies one bank to many
  * frames can convert it once: tidas_prepare writes, for the forward operator

@@ -19,6 +19,7 @@ TIDAS_EUNSUPPORTED = -4
 MODE_EXACT = 0
 MODE_PAPER = 1
 MODE_LINE = 2
+LINE_FOUR_BLOCK, LINE_TWO_BLOCK, LINE_FP32_MATRIX, LINE_VECTOR = 1, 2, 3, 4
 
 
 class TidasError(RuntimeError):
@@ -69,6 +70,7 @@ _SIGS = {
     "tidas_simulate_rf": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), _P, _I, _I, _P, _P]),
     "tidas_apply_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_adjoint_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
+    "tidas_line_kernel": (_I, [_I, _I, _I, _I]),
     "tidas_prepared_bytes": (ctypes.c_size_t, [_I, _I]),
     "tidas_prepare": (_I, [_P, _I, _I, _P, ctypes.c_size_t, _P]),
     "tidas_apply_prepared": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),

@@ -107,6 +107,14 @@ class Prepared:
         self.shape = (self.Z, self.K)
 
 
+def line_kernel(K, B, Z, X):
+    """Which line-model kernel a launch of B frames of Z x X with K taps runs
+    (``_lib.LINE_FOUR_BLOCK`` … ``_lib.LINE_VECTOR``)."""
+    r = _lib.load().tidas_line_kernel(int(K), int(B), int(Z), int(X))
+    _lib.check(r if r < 0 else 0)
+    return r
+
+
 def prepare(kernels):
     """Convert a kernel bank [Z][K] once for repeated ``apply`` / ``adjoint``."""
     return Prepared(kernels)

@@ -1501,6 +1501,17 @@ extern "C" int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float
                        (hipStream_t)stream);
 }
 
+extern "C" int32_t tidas_line_kernel(int32_t K, int32_t B, int32_t Z, int32_t X) {
+    if (K < 1 || (K % 2) == 0 || B < 1 || Z < 1 || X < 1)
+        return fail(TIDAS_EINVAL, "tidas_line_kernel: K must be odd, K, B, Z, X >= 1");
+    if (b4_path(K, B, Z, X)) return TIDAS_LINE_FOUR_BLOCK;
+    if (bx_path(K, B, Z, X)) return TIDAS_LINE_TWO_BLOCK;
+    if (mfma_fits(K, Z, X) && (int64_t)((Z + MF_TZ - 1) / MF_TZ) * ((X + MF_TN - 1) / MF_TN) * B <= INT32_MAX)
+        return TIDAS_LINE_FP32_MATRIX;
+    const size_t lds = (size_t)(CONV_RZ + CONV_RZ * CONV_WAVES + K - 1) * 64 * sizeof(float);
+    return lds <= LDS_LIMIT ? TIDAS_LINE_VECTOR : fail(TIDAS_EUNSUPPORTED, "tidas_line_kernel: K too large");
+}
+
 extern "C" size_t tidas_prepared_bytes(int32_t K, int32_t Z) {
     if (K < 1 || (K % 2) == 0 || Z < 1 || bx_lds_bytes(K) > 160 * 1024) return 0;
     return full_prepared_bytes(K, Z);

@@ -173,6 +173,14 @@ def test_batch_entry_points_reject_invalid_arguments(lib):
     assert lib.das_beamform_batch(*geo, 2048, bad, 1, ws, need, 0, NUL) == -1              # null output
 
 
+def test_line_kernel_rejects_invalid_sizes(lib):
+    assert lib.tidas_line_kernel(64, 1, 64, 64) == _lib.TIDAS_EINVAL   # even K
+    assert lib.tidas_line_kernel(0, 1, 64, 64) == _lib.TIDAS_EINVAL
+    assert lib.tidas_line_kernel(65, 0, 64, 64) == _lib.TIDAS_EINVAL
+    assert lib.tidas_line_kernel(65, 1, 0, 64) == _lib.TIDAS_EINVAL
+    assert lib.tidas_line_kernel(65, 1, 64, 0) == _lib.TIDAS_EINVAL
+
+
 def test_prepared_bank_size_and_invalid_arguments(lib):
     # two-block images: 16 tiles of 64 rows, two modes, three bf16 planes of
     # 64 x 200 (K = 129); four-block images: 8 tiles of 128 rows, two modes,

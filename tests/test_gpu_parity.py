@@ -84,11 +84,12 @@ def test_prepared_bank_matches_the_bank_bit_for_bit(dev, B, Z, X, K):
 # the same order (ascending in even 128-row bands, descending in odd ones):
 # the results agree bit for bit.  K spans every window length of the four-block
 # tile (4, 4, 6, 8, 10, 12 steps and the largest K of 12 steps); Z and X are
-# ragged against the tile.  257 frames of two tiles give workgroups of two
+# ragged against the tile (X = 43: rows not 16-byte aligned).  257 frames of two tiles give workgroups of two
 # frames (the ring of loads runs ahead across the frame boundary) and a last
 # workgroup of one frame; 43 frames of six tiles give one frame each.
 FOUR_BLOCK_SHAPES = [(257, 130, 40, 1), (257, 130, 40, 33), (257, 130, 40, 65), (257, 130, 40, 97),
-                     (257, 130, 40, 129), (257, 130, 40, 145), (257, 130, 40, 161), (43, 300, 300, 129)]
+                     (257, 130, 40, 129), (257, 130, 40, 145), (257, 130, 40, 161), (43, 300, 300, 129),
+                     (257, 130, 43, 65)]
 
 
 def _same_tiles(a, b):
@@ -98,6 +99,19 @@ def _same_tiles(a, b):
 def _in_chunks(fn, kb, x, n, *rest):
     return torch.cat([fn(kb, x[i:i + n], *[r[i:i + n] if torch.is_tensor(r) else r for r in rest])
                       for i in range(0, x.shape[0], n)])
+
+
+def test_line_kernel_choice(dev):
+    L = td._lib
+    assert td.line_kernel(129, 64, 1024, 256) == L.LINE_FOUR_BLOCK      # the benchmark's launch
+    assert td.line_kernel(129, 16, 1024, 256) == L.LINE_TWO_BLOCK       # 128 tiles < 256 compute units
+    assert td.line_kernel(129, 64, 1024, 258) == L.LINE_FOUR_BLOCK      # any X
+    assert td.line_kernel(163, 64, 1024, 256) == L.LINE_TWO_BLOCK       # window longer than 12 steps
+    assert td.line_kernel(321, 1, 300, 70) == L.LINE_TWO_BLOCK
+    assert td.line_kernel(513, 1, 600, 40) in (L.LINE_FP32_MATRIX, L.LINE_VECTOR)
+    for B, Z, X, K in FOUR_BLOCK_SHAPES:
+        assert td.line_kernel(K, B, Z, X) == L.LINE_FOUR_BLOCK
+        assert td.line_kernel(K, 8, Z, X) == L.LINE_TWO_BLOCK
 
 
 @pytest.mark.parametrize("B,Z,X,K", FOUR_BLOCK_SHAPES)
