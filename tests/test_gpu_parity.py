@@ -84,12 +84,13 @@ def test_prepared_bank_matches_the_bank_bit_for_bit(dev, B, Z, X, K):
 # the same order (ascending in even 128-row bands, descending in odd ones):
 # the results agree bit for bit.  K spans every window length of the four-block
 # tile (4, 4, 6, 8, 10, 12 steps and the largest K of 12 steps); Z and X are
-# ragged against the tile (X = 43: rows not 16-byte aligned).  257 frames of two tiles give workgroups of two
+# ragged against the tile (X = 43: rows not 16-byte aligned; Z = 50: a single
+# tile taller than the image).  257 frames of two tiles give workgroups of two
 # frames (the ring of loads runs ahead across the frame boundary) and a last
 # workgroup of one frame; 43 frames of six tiles give one frame each.
 FOUR_BLOCK_SHAPES = [(257, 130, 40, 1), (257, 130, 40, 33), (257, 130, 40, 65), (257, 130, 40, 97),
                      (257, 130, 40, 129), (257, 130, 40, 145), (257, 130, 40, 161), (43, 300, 300, 129),
-                     (257, 130, 43, 65)]
+                     (257, 130, 43, 65), (300, 50, 40, 33)]
 
 
 def _same_tiles(a, b):
