@@ -520,7 +520,7 @@ def run_surrogate(args):
 
     # ---- training
     model = sg.Surrogate()
-    model.load_layers([(W, np.zeros_like(b)) for W, b in generators.mlp_init(SURROGATE["widths"], 0)])
+    model.load_layers([(W, b) for W, b in generators.mlp_init(SURROGATE["widths"], 0)])
     B = SURROGATE["batch"]
     idx_all = torch.from_numpy(generators.batch_indices(args.train_rows, B, args.train_steps, seed=2).astype(np.int32))
     idx_all = idx_all.to(dev)

@@ -165,7 +165,7 @@ def small_dataset(dev, n, seed):
 def test_training_reduces_loss_and_resumes_bit_exactly(dev, tmp_path):
     x, t = small_dataset(dev, 4096, 11)
     idx = [torch.from_numpy(b.astype(np.int32)).to(dev) for b in generators.batch_indices(4096, 256, 120, seed=3)]
-    layers = [(W, np.zeros_like(b)) for W, b in generators.mlp_init((4, 256, 256, 256, 129), 0)]
+    layers = [(W, b) for W, b in generators.mlp_init((4, 256, 256, 256, 129), 0)]
     a = sg.Surrogate()
     a.load_layers(layers)
     first = float(a.train_step(x, t, idx=idx[0]))

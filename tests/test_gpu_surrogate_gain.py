@@ -45,7 +45,7 @@ def trained(dev):
     x = sg.features(P, LO, HI)
     t, _ = sg.kernels_at(S5, S5.fs, S5.t0, S5.cycles, S5.n_samples, S5.dz, P, S5.K, normalise=True)
     m = sg.Surrogate()
-    m.load_layers([(W, np.zeros_like(b)) for W, b in generators.mlp_init(SURROGATE["widths"], 0)])
+    m.load_layers([(W, b) for W, b in generators.mlp_init(SURROGATE["widths"], 0)])
     idx = torch.from_numpy(generators.batch_indices(n, 1024, steps, seed=2).astype(np.int32)).to(dev)
     m.fit(x, t, [idx[i] for i in range(steps)], total_steps=steps)
     return m
