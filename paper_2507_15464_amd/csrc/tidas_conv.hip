@@ -4,7 +4,16 @@
 //   forward:  Y[b][i][j]  = sum_t K[i][t] * R[b][i - t + h][j]          t = 0..K-1
 //   adjoint:  Rb[b][s][j] = sum_t K[s + t - h][t] * Yb[b][s + t - h][j]
 //
-// gfx950 mapping.  A workgroup owns a tile of 64 lateral columns (one per
+// Kernels, in the order the dispatcher tries them (conv_launch):
+//   tidas_b4_kernel    split-bfloat16 matrix cores, 128 x 256 tiles (K <= 161,
+//                      batches with a tile per compute unit)
+//   tidas_bx6_kernel   split-bfloat16 matrix cores, 64 x 256 tiles (K <= 321;
+//                      also the tile of the ragged batch kernel)
+//   tidas_mfma_kernel  float32 matrix cores (larger K)
+//   tidas_fwd_kernel / tidas_adj_kernel  vector ALU (the first version,
+//                      described next; the fallback when no tile fits LDS)
+//
+// Vector-ALU mapping.  A workgroup owns a tile of 64 lateral columns (one per
 // lane) x TZ = WAVES * RZ depth rows (RZ consecutive rows per wave).  The
 // input rows the tile needs, [i0 - h, i0 + TZ + h), are staged once in LDS
 // with coalesced 256-byte row loads (zero outside the image), so each input
