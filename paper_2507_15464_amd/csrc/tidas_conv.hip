@@ -552,6 +552,8 @@ __global__ __launch_bounds__(256) void bx_prepare_kernel(const float* __restrict
 // direct-to-LDS 16-byte loads (every wave load moves 1 KB; the image is a
 // whole number of them since LS = 0 (mod 8)).  From the bank: a rolled loop
 // over the entries (the ragged batch path, whose frames each bring a bank).
+// Neither (both null): the band already in LDS is kept (the next column tile
+// of the same row tile).
 template <bool ADJ>
 __device__ __forceinline__ void bx_band_to_lds(const uint16_t* __restrict__ img, const float* __restrict__ Kb, int K,
                                                int Z, int i0, uint16_t* lds) {
@@ -563,7 +565,7 @@ __device__ __forceinline__ void bx_band_to_lds(const uint16_t* __restrict__ img,
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(lds + q * 512), 16,
                                                      q * 1024 + lane * 16, 0, 0, 0);
         __builtin_amdgcn_s_waitcnt(0);  // the copy is in LDS (also drains the input prefetch)
-    } else {
+    } else if (Kb) {
         const int LS = bx_lstride(K);
         const int n = BX_TZ * LS;
 #pragma unroll 4
@@ -1151,22 +1153,17 @@ __global__ __launch_bounds__(BX_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 }
 
 // Ragged batch on the split-bfloat16 tile: as tidas_batch_kernel, over the
-// 64 x 256 tiles of all frames (one frame per tile visit).
-// One tile of the persistent batch kernel, kept out of line: inlined into the
-// tile loop, the loop-invariant parts of the band fill are hoisted out of it
-// and hold registers through the whole tile.
-template <bool VEC>
-__device__ __attribute__((noinline)) void bx_batch_tile(const float* Kb, const float* In, float* Out, int K, int Z,
-                                                        int X, int i0, int j0) {
-    extern __shared__ uint16_t bx_smem[];
-    bx_tile<false, VEC>(nullptr, Kb, In, Out, nullptr, 1, 1.0f, 0.0f, K, Z, X, i0, j0, bx_smem);
-}
-
-// VEC: every frame of the table is a VEC frame (the host launches the VEC and
-// the other frames as two tables, so one kernel inlines one tile variant).
-template <bool VEC>
+// 64-row tiles of all frames.  A visit takes one row tile of one frame: its
+// band is filled from the frame's bank once and serves every 256-column tile
+// of that row.  The tile is inlined into the visit loop; K goes through an
+// opaque copy made per visit, else the loop-invariant parts of the band fill
+// are hoisted out of the loop and hold registers through the whole tile.
+// (Kept out of line instead, the call saved and restored ~100 callee-saved
+// registers through scratch on every visit and built every buffer
+// descriptor from pointer arguments in vector registers.)
 __global__ __launch_bounds__(BX_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void tidas_bx6_batch_kernel(
     const ConvFrameDev* __restrict__ fr, int32_t n_frames, int64_t total, int32_t K) {
+    extern __shared__ uint16_t bx_smem[];
     const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
     const int per_xcd = ((int)gridDim.x - x + 7) >> 3;
     const int64_t lo = total * x / 8, hi = total * (x + 1) / 8;
@@ -1181,13 +1178,19 @@ __global__ __launch_bounds__(BX_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
         // buffer descriptor built from it becomes a per-lane loop
         const ConvFrameDev f = fr[__builtin_amdgcn_readfirstlane(a)];
         const int Zf = __builtin_amdgcn_readfirstlane(f.Z), Xf = __builtin_amdgcn_readfirstlane(f.X);
-        const int64_t local = t - f.tile_start;
-        const int row_tiles = (Zf + BX_TZ - 1) / BX_TZ;
-        const int i0 = __builtin_amdgcn_readfirstlane((int)(local % row_tiles) * BX_TZ);
-        const int j0 = __builtin_amdgcn_readfirstlane((int)(local / row_tiles) * BX_TN);
-        __syncthreads();  // the previous tile's readers of the LDS band are done
-        bx_batch_tile<VEC>(uniform_ptr(f.kernels), uniform_ptr(f.in), const_cast<float*>(uniform_ptr(f.out)), K, Zf,
-                           Xf, i0, j0);
+        const bool vec = __builtin_amdgcn_readfirstlane(f.vec) != 0;
+        const int i0 = __builtin_amdgcn_readfirstlane((int)(t - f.tile_start) * BX_TZ);
+        const float* kb = uniform_ptr(f.kernels);
+        const float* in = uniform_ptr(f.in);
+        float* out = const_cast<float*>(uniform_ptr(f.out));
+        int Kv = K;
+        asm volatile("" : "+s"(Kv));
+        __syncthreads();  // the previous visit's readers of the LDS band are done
+        for (int j0 = 0; j0 < Xf; j0 += BX_TN) {
+            const float* fill = j0 == 0 ? kb : nullptr;  // one fill per row tile
+            if (vec) bx_tile<false, true>(nullptr, fill, in, out, nullptr, 1, 1.0f, 0.0f, Kv, Zf, Xf, i0, j0, bx_smem);
+            else bx_tile<false, false>(nullptr, fill, in, out, nullptr, 1, 1.0f, 0.0f, Kv, Zf, Xf, i0, j0, bx_smem);
+        }
     }
 }
 
@@ -1650,9 +1653,10 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
     if (variant < 0 || variant >= TIDAS_APPLY_BATCH_VARIANTS)
         return fail(TIDAS_EINVAL, "tidas_apply_batch: variant out of range");
     // the same arithmetic as tidas_apply on each frame: the split-bfloat16
-    // tiles when the band fits, else the float32 matrix-core tiles
+    // tiles when the band fits (a visit = one 64-row tile, all its columns),
+    // else the float32 matrix-core tiles
     const bool bx = bx_lds_bytes(K) <= 160 * 1024;
-    const int TZ = bx ? BX_TZ : MF_TZ, TN = bx ? BX_TN : MF_TN;
+    const int TZ = bx ? BX_TZ : MF_TZ, TN = bx ? INT32_MAX / 2 : MF_TN;
     std::vector<ConvFrameDev> tab(n_frames);
     int64_t total = 0;
     for (int f = 0; f < n_frames; ++f) {
@@ -1672,24 +1676,6 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
         tab[f].tile_start = total;
         total += (int64_t)((Z + TZ - 1) / TZ) * ((X + TN - 1) / TN);
     }
-    // split-bfloat16 tiles: VEC frames first, then the others, each group with
-    // its own tile numbering (one launch per group)
-    int n_vec = 0;
-    int64_t total_vec = 0, total_other = 0;
-    if (bx) {
-        std::stable_partition(tab.begin(), tab.end(), [](const ConvFrameDev& e) { return e.vec != 0; });
-        for (auto& e : tab) {
-            const int64_t tiles = (int64_t)((e.Z + TZ - 1) / TZ) * ((e.X + TN - 1) / TN);
-            if (e.vec) {
-                e.tile_start = total_vec;
-                total_vec += tiles;
-                ++n_vec;
-            } else {
-                e.tile_start = total_other;
-                total_other += tiles;
-            }
-        }
-    }
     hipStream_t s = (hipStream_t)stream;
     // hipMemcpyAsync from pageable memory returns once the source is staged
     if ((st = check_hip(hipMemcpyAsync(workspace, tab.data(), sizeof(ConvFrameDev) * n_frames, hipMemcpyHostToDevice, s),
@@ -1704,12 +1690,8 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
             const int64_t nb = std::max<int64_t>(8, std::min<int64_t>(t, (int64_t)n_cu * bx_per_cu[variant]));
             return (unsigned)((nb + 7) / 8 * 8);
         };
-        if (n_vec > 0)
-            hipLaunchKernelGGL(tidas_bx6_batch_kernel<true>, dim3(grid_for(total_vec)), dim3(BX_THREADS),
-                               bx_lds_bytes(K), s, d, n_vec, total_vec, K);
-        if (n_vec < n_frames)
-            hipLaunchKernelGGL(tidas_bx6_batch_kernel<false>, dim3(grid_for(total_other)), dim3(BX_THREADS),
-                               bx_lds_bytes(K), s, d + n_vec, n_frames - n_vec, total_other, K);
+        hipLaunchKernelGGL(tidas_bx6_batch_kernel, dim3(grid_for(total)), dim3(BX_THREADS), bx_lds_bytes(K), s, d,
+                           n_frames, total, K);
         return check_launch("tidas_apply_batch");
     }
     const int pd_sel = variant % 3, per_cu = (variant / 3) == 0 ? 2 : 4;
