@@ -568,10 +568,19 @@ __device__ __forceinline__ void bx_band_to_lds(const uint16_t* __restrict__ img,
     } else if (Kb) {
         const int LS = bx_lstride(K);
         const int n = BX_TZ * LS;
+        // entry e = r LS + c, (r, c) stepped without a division per entry
+        // (dc < LS: at most one carry past the row end per step)
+        const int dr = BX_THREADS / LS, dc = BX_THREADS - dr * LS;
+        int r = threadIdx.x / LS, c = threadIdx.x - r * LS;
 #pragma unroll 4
         for (int e = threadIdx.x; e < n; e += BX_THREADS) {
-            const int r = e / LS, c = e - r * LS;
             bx_band_put<ADJ>(lds, n, e, bx_band_value<ADJ>(Kb, K, Z, i0, r, c));
+            r += dr;
+            c += dc;
+            if (c >= LS) {
+                c -= LS;
+                ++r;
+            }
         }
     }
 }
