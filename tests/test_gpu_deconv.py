@@ -36,7 +36,9 @@ def g(x, dev):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
 
 
-@pytest.mark.parametrize("B,Z,X,K", [(2, 100, 64, 65), (1, 77, 33, 17), (3, 1024, 256, 129)])
+# (257, 130, 40, 65) runs on the four-block tile (workgroups of two frames),
+# the others on the two-block tile
+@pytest.mark.parametrize("B,Z,X,K", [(2, 100, 64, 65), (1, 77, 33, 17), (3, 1024, 256, 129), (257, 130, 40, 65)])
 @pytest.mark.parametrize("adj", [False, True])
 def test_fused_forms_match_oracle(dev, B, Z, X, K, adj):
     kb = generators.normal((Z, K), seed=K).astype(np.float32)
