@@ -211,7 +211,6 @@ int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float* image_bar
 int32_t tidas_line_kernel(int32_t K, int32_t B, int32_t Z, int32_t X);
 
 /*
- * Prepared kernel bank./*
  * Prepared kernel bank.  The line model's kernels (Sec. 2.4, eqn:line_conv)
  * depend on the geometry only, so a caller that applies one bank to many
  * frames can convert it once: tidas_prepare writes, for the forward operator
