@@ -16,7 +16,8 @@ Every function is a direct, slow, readable transcription of a definition:
                 and the paper's fixed-delay + least-squares theta kernel
                 (Sec. 2.3, eqn:tDAS / eqn:theta; Sec. 3.1-3.2 FWHM window).
 * ``tidas``     the per-row convolutional line model (Sec. 2.4,
-                eqn:line_conv), its adjoint and its explicit banded matrix.
+                eqn:line_conv), its adjoint, its gradient in the kernels and
+                its explicit banded matrix.
 * ``deconv``    Tikhonov-regularised gradient deconvolution through it.
 * ``mlp``       the kernel-surrogate MLP in FP64 and with BF16 rounding
                 emulated at the GPU's rounding points.

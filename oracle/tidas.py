@@ -13,8 +13,14 @@ The adjoint (transpose) is
 
     Rbar[b][s][j] = sum_{m=-h..h} K[s+m][m+h] * Ybar[b][s+m][j],
 
-terms with s + m outside [0, Z) dropped.  Both are written as plain loops
-over the tap index m.
+terms with s + m outside [0, Z) dropped.  The gradient of a loss L with
+respect to the kernels, given Ybar = dL/dY, follows from differentiating the
+sum above term by term (the conclusion, Sec. 4, treats the weights as
+learnable):
+
+    Kbar[i][m+h] = sum_b sum_j Ybar[b][i][j] * R[b][i-m][j],   R = 0 outside [0, Z).
+
+All three are written as plain loops over the tap index m.
 """
 import numpy as np
 
@@ -60,6 +66,27 @@ def adjoint(K, Yb):
             if 0 <= i < Z:
                 Rb[:, s, :] += K[i, m + h] * Y3[:, i, :]
     return Rb[0] if squeeze else Rb
+
+
+def kernel_grad(R, Yb, K):
+    """Kbar = dL/dK for Ybar = dL/dY: [Z][K] from R, Ybar ([Z][X] or [B][Z][X]) and the tap count K."""
+    R = np.asarray(R, np.float64)
+    Yb = np.asarray(Yb, np.float64)
+    if R.shape != Yb.shape or R.ndim not in (2, 3):
+        raise ValueError("R and Ybar must have the same [Z][X] or [B][Z][X] shape")
+    if K < 1 or K % 2 != 1:
+        raise ValueError("K must be odd")
+    R3 = R[None] if R.ndim == 2 else R
+    Y3 = Yb[None] if Yb.ndim == 2 else Yb
+    Z = R3.shape[1]
+    h = (K - 1) // 2
+    G = np.zeros((Z, K), np.float64)
+    for m in range(-h, h + 1):
+        for i in range(Z):
+            s = i - m
+            if 0 <= s < Z:
+                G[i, m + h] = np.sum(Y3[:, i, :] * R3[:, s, :])
+    return G
 
 
 def matrix(K):

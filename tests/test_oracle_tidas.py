@@ -1,5 +1,5 @@
-"""Pins of the oracle's line model (Sec. 2.4 eqn:line_conv), its adjoint, the
-deconvolution built on it, and the tiDAS = DAS identity where the PSF is
+"""Pins of the oracle's line model (Sec. 2.4 eqn:line_conv), its adjoint, its
+gradient in the kernels, the deconvolution built on it, and the tiDAS = DAS identity where the PSF is
 truly row-invariant."""
 import numpy as np
 import pytest
@@ -93,6 +93,75 @@ def test_gradient_matches_central_finite_differences_32x64():
         d = generators.normal((32, 64), seed=100 + k)
         fd = (f(R + eps * d) - f(R - eps * d)) / (2 * eps)
         assert abs(fd - np.sum(g * d)) <= 1e-7 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("Z,X,K,B", [(1, 1, 1, 1), (9, 3, 5, 2), (40, 7, 17, 1), (33, 4, 65, 3)])
+def test_kernel_grad_is_the_band_of_ybar_times_r_transposed(Z, X, K, B):
+    """Kbar[i][m+h] is entry (i, i - m) of sum_b Ybar_b R_b^T (a matrix
+    product), and zero where i - m leaves the image."""
+    R = generators.normal((B, Z, X), seed=Z + 1)
+    Yb = generators.normal((B, Z, X), seed=Z + 2)
+    G = tidas.kernel_grad(R, Yb, K)
+    P = sum(Yb[b] @ R[b].T for b in range(B))
+    h = (K - 1) // 2
+    for i in range(Z):
+        for m in range(-h, h + 1):
+            expect = P[i, i - m] if 0 <= i - m < Z else 0.0
+            assert abs(G[i, m + h] - expect) <= 1e-12 * max(1.0, abs(expect))
+
+
+@pytest.mark.parametrize("Z,X,K,B", [(8, 2, 3, 1), (30, 5, 9, 2), (64, 3, 65, 2)])
+def test_kernel_grad_dot_product_test(Z, X, K, B):
+    """<dK, Kbar(R, Ybar)> = <A_dK R, Ybar> for any direction dK: the gradient
+    is the line model's derivative in its kernels (the model is linear in K)."""
+    R = generators.normal((B, Z, X), seed=11)
+    Yb = generators.normal((B, Z, X), seed=12)
+    dK = generators.normal((Z, K), seed=13)
+    lhs = np.sum(dK * tidas.kernel_grad(R, Yb, K))
+    rhs = np.sum(tidas.apply(dK, R) * Yb)
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs))
+
+
+def test_kernel_grad_matches_central_finite_differences_32x64():
+    """FP64 central differences of 1/2 ||A_K R - y||^2 in single taps and along
+    random directions of the kernel bank, at 32 x 64 with K = 65."""
+    Z, X, K = 32, 64, 65
+    kb = generators.normal((Z, K), seed=20) * 0.1
+    R = generators.normal((2, Z, X), seed=21)
+    y = generators.normal((2, Z, X), seed=22)
+
+    def f(k):
+        res = tidas.apply(k, R) - y
+        return 0.5 * np.sum(res * res)
+    g = tidas.kernel_grad(R, tidas.apply(kb, R) - y, K)
+    rng = np.random.default_rng(23)
+    eps = 1e-5
+    for _ in range(25):
+        i, t = rng.integers(Z), rng.integers(K)
+        e = np.zeros_like(kb)
+        e[i, t] = eps
+        fd = (f(kb + e) - f(kb - e)) / (2 * eps)
+        assert abs(fd - g[i, t]) <= 1e-7 * max(1.0, abs(g[i, t]))
+    for k in range(5):
+        d = generators.normal((Z, K), seed=200 + k)
+        fd = (f(kb + eps * d) - f(kb - eps * d)) / (2 * eps)
+        assert abs(fd - np.sum(g * d)) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_kernel_grad_impulses_read_single_products():
+    """R and Ybar single impulses: only the tap that joins them is non-zero."""
+    Z, X, K = 20, 3, 7
+    h = 3
+    for (i, s, j) in [(5, 5, 0), (10, 8, 2), (0, 3, 1), (19, 16, 0), (4, 12, 1)]:
+        R = np.zeros((Z, X))
+        Yb = np.zeros((Z, X))
+        R[s, j] = 2.0
+        Yb[i, j] = -3.0
+        G = tidas.kernel_grad(R, Yb, K)
+        expect = np.zeros((Z, K))
+        if abs(i - s) <= h:
+            expect[i, i - s + h] = -6.0
+        assert np.array_equal(G, expect)
 
 
 def test_tidas_equals_das_where_psf_is_row_invariant():
