@@ -192,6 +192,22 @@ int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float* image_bar
                          float alpha, float beta, const float* base, float* refl_bar, void* stream);
 
 /*
+ * Gradient of the line model in its kernels.  The model (Sec. 2.4,
+ * eqn:line_conv) is linear in the per-row kernels, which the conclusion
+ * (Sec. 4) treats as learnable weights; for image_bar = dL/d(image):
+ *   kernels_bar[i][m+h] = sum_b sum_j image_bar[b][i][j] * refl[b][i-m][j],
+ * refl taken as zero outside [0, Z) (those taps get 0).  refl, image_bar DEV
+ * [B][Z][X]; kernels_bar DEV [Z][K], overwritten, must not alias an input.
+ * K odd >= 1; B, Z, X >= 1; EUNSUPPORTED when (Z + 2 K + 512) X 4 bytes
+ * reach 2^31.  Float32 products on the matrix cores, partial sums over fixed
+ * ranges of (frame, column) added in double in a fixed order (bit-
+ * reproducible on one device type); a stream-ordered temporary buffer holds
+ * the partial sums (about 2 x compute units x 128 Z K / ceil(Z / 128) bytes).
+ */
+int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* image_bar, int32_t B, int32_t Z, int32_t X,
+                          float* kernels_bar, void* stream);
+
+/*
  * Which line-model kernel tidas_apply / tidas_adjoint (and their fused and
  * prepared forms) run for K taps, B frames of Z x X (16-byte aligned
  * buffers): a diagnostic for callers and tests, enqueues nothing.

@@ -11,7 +11,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["das_beamform", "build_kernels", "apply", "adjoint", "simulate_rf", "version"]
+__all__ = ["das_beamform", "build_kernels", "apply", "adjoint", "kernel_grad", "simulate_rf", "version"]
 
 
 def _stream():
@@ -177,6 +177,23 @@ def apply(kernels, refl, out=None):
 def adjoint(kernels, image_bar, out=None):
     """Transpose of ``apply``."""
     return _conv("tidas_adjoint", kernels, image_bar, out)
+
+
+def kernel_grad(refl, image_bar, K, out=None):
+    """Gradient of the line model in its kernels: [Z][K] from refl and image_bar ([B][Z][X] or [Z][X])."""
+    lib = _lib.load()
+    _check_tensor(refl, "refl")
+    _check_tensor(image_bar, "image_bar")
+    if refl.shape != image_bar.shape or refl.dim() not in (2, 3):
+        raise ValueError("refl and image_bar must share one [B][Z][X] or [Z][X] shape")
+    B, Z, X = (1,) + tuple(refl.shape) if refl.dim() == 2 else tuple(refl.shape)
+    if out is None:
+        out = torch.empty((Z, int(K)), device=refl.device, dtype=torch.float32)
+    _check_tensor(out, "out")
+    if tuple(out.shape) != (Z, int(K)):
+        raise ValueError("out must be [Z][K]")
+    _lib.check(lib.tidas_kernel_grad(int(K), _ptr(refl), _ptr(image_bar), B, Z, X, _ptr(out), _stream()))
+    return out
 
 
 def simulate_rf(setup, scat, n_samples=None, out=None):

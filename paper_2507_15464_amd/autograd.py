@@ -1,9 +1,10 @@
 """torch.autograd integration and Tikhonov deconvolution through the line model.
 
 ``TiDASFunction``: forward = tidas_apply, backward = tidas_adjoint (the exact
-transpose), so any loss built on the line model's output back-propagates to
-the reflectivity map through the library's own kernels.  The kernel bank is
-treated as a constant (no gradient).
+transpose) for the reflectivity map and tidas_kernel_grad for a kernel bank
+that requires a gradient, so any loss built on the line model's output
+back-propagates through the library's own kernels to the map and to the
+kernels (a prepared bank is a constant).
 
 ``deconvolve``: the library's native gradient loop for
 1/2 ||A r - y||^2 + lam/2 ||r||^2 (two fused launches per step).
@@ -15,7 +16,7 @@ import ctypes
 import torch
 
 from . import _lib
-from .api import Prepared, _check_tensor, _ptr, _stream, adjoint, apply, conv_ex
+from .api import Prepared, _check_tensor, _ptr, _stream, adjoint, apply, conv_ex, kernel_grad
 
 __all__ = ["TiDASFunction", "tidas", "apply_ex", "adjoint_ex", "deconvolve", "operator_norm_sq", "step_size"]
 
@@ -23,17 +24,26 @@ __all__ = ["TiDASFunction", "tidas", "apply_ex", "adjoint_ex", "deconvolve", "op
 class TiDASFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, refl, kernels):
+        refl = refl.contiguous()
         if isinstance(kernels, Prepared):
             ctx.prepared = kernels
+            ctx.save_for_backward(None, None)
         else:
             ctx.prepared = None
-            ctx.save_for_backward(kernels)
-        return apply(kernels, refl.contiguous())
+            ctx.save_for_backward(kernels, refl if ctx.needs_input_grad[1] else None)
+        return apply(kernels, refl)
 
     @staticmethod
     def backward(ctx, grad_out):
-        kernels = ctx.prepared if ctx.prepared is not None else ctx.saved_tensors[0]
-        return adjoint(kernels, grad_out.contiguous()), None
+        kernels, refl = ctx.saved_tensors
+        if ctx.prepared is not None:
+            kernels = ctx.prepared
+        grad_out = grad_out.contiguous()
+        g_refl = adjoint(kernels, grad_out) if ctx.needs_input_grad[0] else None
+        g_k = None
+        if ctx.prepared is None and ctx.needs_input_grad[1]:
+            g_k = kernel_grad(refl, grad_out, kernels.shape[1])
+        return g_refl, g_k
 
 
 def tidas(refl, kernels):

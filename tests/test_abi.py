@@ -173,6 +173,23 @@ def test_batch_entry_points_reject_invalid_arguments(lib):
     assert lib.das_beamform_batch(*geo, 2048, bad, 1, ws, need, 0, NUL) == -1              # null output
 
 
+def test_kernel_grad_rejects_invalid_arguments(lib):
+    out = ctypes.c_void_p(0x3000)
+    f = lib.tidas_kernel_grad
+    assert f(65, NUL, FAKE, 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL      # null refl
+    assert f(65, FAKE, NUL, 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL      # null image_bar
+    assert f(65, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, NUL, NUL) == _lib.TIDAS_EINVAL  # null output
+    assert f(64, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL  # even K
+    assert f(0, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL   # K = 0
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 0, 16, 16, out, NUL) == _lib.TIDAS_EINVAL   # B = 0
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 0, 16, out, NUL) == _lib.TIDAS_EINVAL    # Z = 0
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 16, -1, out, NUL) == _lib.TIDAS_EINVAL   # X < 0
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, FAKE, NUL) == _lib.TIDAS_EINVAL  # output aliases refl
+    # a frame whose 32-bit byte offsets would overflow
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 1 << 20, 1024, out, NUL) == _lib.TIDAS_EUNSUPPORTED
+    assert lib.tidas_last_error()
+
+
 def test_line_kernel_rejects_invalid_sizes(lib):
     assert lib.tidas_line_kernel(64, 1, 64, 64) == _lib.TIDAS_EINVAL   # even K
     assert lib.tidas_line_kernel(0, 1, 64, 64) == _lib.TIDAS_EINVAL
