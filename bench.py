@@ -25,6 +25,8 @@ Other workloads (one JSON line each, not the headline):
                         plane wave): single scatterers at every row and 5 / 5 rising /
                         100 scatterer lines, exact kernels and one reference curve
                         at 25 and 35 mm, local and global squared errors
+    --workload kgrad    gradient of the line model in its kernels (tidas_kernel_grad)
+                        over B frames of 1024 x 256 with 129 taps
     --workload surrogate  train the BF16-MFMA kernel surrogate on 200k exact
                         kernels (depth, F# 1-3, angle +-15 deg, fc 3-10 MHz), then
                         surrogate-kernel vs exact-kernel line model on 512 x 2048
@@ -52,7 +54,7 @@ DAS_FLOPS_PER_TERM = 14
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["main", "batch", "deconv", "surrogate", "approx"], default="main")
+    ap.add_argument("--workload", choices=["main", "batch", "deconv", "kgrad", "surrogate", "approx"], default="main")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate workload: Adam steps")
     ap.add_argument("--train-rows", type=int, default=200_000, help="surrogate workload: training kernels")
     ap.add_argument("--steps", type=int, default=100)
@@ -75,6 +77,7 @@ def log(msg):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tidas_b4_kernel_256x1024_k129_b64_traffic.json")
 BF16_MFMA_TFLOPS = 2500.0                                    # dense bf16 matrix peak
+FP32_MFMA_TFLOPS = 157.3                                     # dense fp32 matrix peak
 
 
 def measured_traffic(batch):
@@ -100,7 +103,7 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
-    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "surrogate": run_surrogate,
+    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "kgrad": run_kgrad, "surrogate": run_surrogate,
      "approx": run_approx}[args.workload](args)
 
 
@@ -484,6 +487,62 @@ def run_deconv(args):
         "us_per_iteration": ms * 1e3 / iters, "achieved_tflops": flops / (ms * 1e-3) / 1e12,
         "rel_error_to_truth": err,
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_kgrad(args):
+    """Gradient of the line model in its kernels: B frames of 1024 x 256, 129 taps."""
+    import numpy as np
+    import torch
+
+    import paper_2507_15464_amd as td
+    from workloads import config, generators
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = config(2)
+    B, Z, X, K = args.batch, s.nz, s.nx, s.K
+    R = generators.normal((B, Z, X), seed=0).astype(np.float32)
+    Yb = generators.normal((B, Z, X), seed=1).astype(np.float32)
+    Rd, Yd = torch.from_numpy(R).to(dev), torch.from_numpy(Yb).to(dev)
+    G = torch.empty((Z, K), device=dev, dtype=torch.float32)
+    ms = _events_ms(lambda: td.kernel_grad(Rd, Yd, K, out=G), args.steps, args.warmup)
+    flops = 2.0 * B * Z * X * K
+    tflops = flops / (ms * 1e-3) / 1e12
+    out = {
+        "metric": "kernel-gradient frames/s of the line model (1024 x 256 px, 129 taps) vs FP64 oracle",
+        "value": B / (ms * 1e-3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (N(0,1) reflectivity maps and output gradients, seeded)",
+        "config": {"workload": f"{B} frames of 1024 x 256 px, 129 taps (kernel gradient)", "global_batch": B},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_MFMA_TFLOPS, "traffic": None, "flops_per_launch": flops,
+                     "kernel": "kgrad_kernel + kgrad_reduce_kernel (whole call)"},
+    }
+    if not args.no_parity:
+        # sampled entries against FP64 dot products over all frames and columns
+        Gh = G.cpu().numpy()
+        h = (K - 1) // 2
+        rng = np.random.default_rng(2)
+        got, want = [], []
+        for _ in range(200):
+            i, m = int(rng.integers(Z)), int(rng.integers(-h, h + 1))
+            exp = (float(np.sum(Yb[:, i, :].astype(np.float64) * R[:, i - m, :].astype(np.float64)))
+                   if 0 <= i - m < Z else 0.0)
+            got.append(Gh[i, m + h])
+            want.append(exp)
+        got, want = np.asarray(got, np.float64), np.asarray(want, np.float64)
+        out["rel_l2_vs_fp64"] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        out["parity_sample"] = "200 sampled (row, tap) entries of the timed launch"
+    if not args.no_cpu_baseline:
+        from oracle import tidas as o_t
+        t_c = time.perf_counter()
+        n_fr = 0
+        while n_fr < 1 or time.perf_counter() - t_c < 5.0:
+            o_t.kernel_grad(R[n_fr:n_fr + 1], Yb[n_fr:n_fr + 1], K)
+            n_fr += 1
+        out["cpu_baseline"] = {"value": n_fr / (time.perf_counter() - t_c), "unit": "frames/s", "cores": 1,
+                               "kind": "oracle", "sample": f"FP64 oracle kernel gradient on {n_fr} frames, about 5 s"}
     print(json.dumps(out), flush=True)
 
 
