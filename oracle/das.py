@@ -9,6 +9,18 @@ sampled channel data (readings recorded with the design), the image is
 
 with L the linear-interpolation read of ``lerp_read`` (zero outside the
 record) and w the apodization of ``geometry.hann_apod``.
+
+The time-invariant beamformer of the paper (Sec. 2.3 eqn:tDAS: the delays of
+one point applied to a whole line; Sec. 2.4 eqn:line_conv: a convolution with
+fixed parameters scaled by Theta) is the same read with the receive law frozen:
+row i uses the delays D_n and the weights of its reference row r = r(i), in
+every column, and is scaled by theta_i:
+
+    I[i][j] = theta_i sum_a sum_n w(x_j - x_n, z_r) *
+              L(RF[a][n], (tau_tx(x_j, z_i; a) + z_i / c - D_n(x_j, z_r) - t0) * fs)
+
+with D_n(x, z) = (z - rho_n(x, z)) / c, the delay law of eqn:delay at lateral
+position x.  With r(i) = i and theta = 1 it is DAS.
 """
 import math
 
@@ -44,6 +56,31 @@ def das(rf, xs, zs, n_elem, pitch, c, fs, t0, angles, fnumber):
             w = geometry.hann_apod(X - xn, Z, fnumber)
             u = (ttx + geometry.rho(X, Z, xn) / c - t0) * fs
             img += w * lerp_read(rf[ai, n], u)
+    return img
+
+
+def fixed_delay_das(rf, xs, zs, ref_rows, n_elem, pitch, c, fs, t0, angles, fnumber, theta=None):
+    """FP64 fixed-delay (time-invariant) beamformer over the whole grid.
+    rf [A][C][T]; xs [X], zs [Z]; ref_rows [Z] row indices; theta [Z] or None
+    (ones).  Returns the image [Z][X]."""
+    rf = np.asarray(rf, np.float64)
+    xs = np.asarray(xs, np.float64)
+    zs = np.asarray(zs, np.float64)
+    ref_rows = np.asarray(ref_rows, np.int64)
+    if ref_rows.shape != zs.shape or np.any(ref_rows < 0) or np.any(ref_rows >= zs.size):
+        raise ValueError("ref_rows must hold one row index in [0, Z) per row")
+    xn_all = geometry.element_x(n_elem, pitch)
+    X, Zi = np.meshgrid(xs, zs)
+    Zr = np.meshgrid(xs, zs[ref_rows])[1]
+    img = np.zeros(Zi.shape, np.float64)
+    for ai, alpha in enumerate(angles):
+        t_line = geometry.tau_tx(X, Zi, alpha, c) + Zi / c
+        for n, xn in enumerate(xn_all):
+            w = geometry.hann_apod(X - xn, Zr, fnumber)
+            u = (t_line - geometry.receive_delay(xn - X, Zr, c) - t0) * fs
+            img += w * lerp_read(rf[ai, n], u)
+    if theta is not None:
+        img *= np.asarray(theta, np.float64)[:, None]
     return img
 
 

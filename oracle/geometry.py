@@ -46,7 +46,8 @@ def arrival_time(x, z, xn, alpha, c):
 
 def receive_delay(xn, z, c):
     """Receive delay law on the centre line, Sec. 2.1 eqn:delay:
-    D_n(z) = (z - sqrt(x_n^2 + z^2)) / c."""
+    D_n(z) = (z - sqrt(x_n^2 + z^2)) / c.  At lateral position x the same law
+    with x_n - x in place of x_n."""
     z = np.asarray(z, np.float64)
     return (z - np.sqrt(np.asarray(xn, np.float64) ** 2 + z ** 2)) / c
 

@@ -1,10 +1,13 @@
-"""Pins of the oracle's RF synthesis (Sec. 2 eqn:SRX, Born superposition) and
+"""Pins of the oracle's RF synthesis (Sec. 2 eqn:SRX, Born superposition),
 DAS (Sec. 2 eqn:appF): brute force, a textbook interpolation routine, the PSF
-peak position, lateral symmetry and linearity."""
+peak position, lateral symmetry and linearity; and of the fixed-delay
+(time-invariant) beamformer of Sec. 2.3-2.4: DAS where every row is its own
+reference, the centre-line fixed-delay line, the closed-form depth of its
+shifted peak, symmetry and linearity."""
 import numpy as np
 import pytest
 
-from oracle import das, geometry, pulse, simulate
+from oracle import das, geometry, kernels, pulse, simulate
 from workloads import config, generators
 from tests.helpers import das_kw, sim_kw, axes
 
@@ -139,3 +142,72 @@ def test_das_config1_speckle_finite_and_nonzero():
     xs, zs = axes(s)
     img = das.das(rf, xs, zs, **das_kw(s))
     assert img.shape == (256, 128) and np.all(np.isfinite(img)) and np.max(np.abs(img)) > 1.0
+
+
+@pytest.mark.parametrize("C,nz,nx,angles", [(1, 9, 3, (0.0,)), (8, 16, 8, (-0.1, 0.0, 0.13)), (5, 12, 6, (0.2,))])
+def test_fixed_delay_das_with_own_rows_is_das(C, nz, nx, angles):
+    s = tiny_setup(C, nz, nx, angles)
+    rf = generators.normal((len(angles), C, s.n_samples), seed=3 + C)
+    xs, zs = axes(s)
+    ref = das.das(rf, xs, zs, **das_kw(s))
+    got = das.fixed_delay_das(rf, xs, zs, np.arange(nz), **das_kw(s))
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    # rows that are their own reference stay DAS rows when the others are not
+    refs = np.arange(nz)
+    refs[1::2] = nz // 2
+    got = das.fixed_delay_das(rf, xs, zs, refs, **das_kw(s))
+    own = refs == np.arange(nz)
+    assert np.max(np.abs(got[own] - ref[own])) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(got[~own] - ref[~own])) > 1e-3 * np.max(np.abs(ref))
+    # theta scales rows
+    th = np.linspace(0.5, 2.0, nz)
+    got_t = das.fixed_delay_das(rf, xs, zs, refs, **das_kw(s), theta=th)
+    assert np.max(np.abs(got_t - th[:, None] * got)) <= 1e-13 * max(1.0, np.max(np.abs(got_t)))
+
+
+def test_fixed_delay_das_centre_column_is_the_fixed_delay_line():
+    s = finer_grid_case()
+    xs, zs = axes(s)
+    x_c = np.array([0.0])
+    rf = simulate.simulate_rf([0.7e-3, -1.1e-3], [zs[40], zs[70]], [1.0, -0.6], **sim_kw(s))
+    refs = np.clip((np.arange(s.nz) // 16) * 16 + 8, 0, s.nz - 1)
+    got = das.fixed_delay_das(rf, x_c, zs, refs, **das_kw(s))[:, 0]
+    line = kernels.fixed_delay_beamform(rf, zs, zs[refs], **das_kw(s))
+    assert np.max(np.abs(got - line)) <= 1e-12 * np.max(np.abs(line))
+
+
+def test_fixed_delay_peak_moves_to_the_closed_form_depth():
+    """One element at x = 0, unsteered, a unit scatterer at (x_s, z_s) and every
+    row frozen at depth z_r: along the column x = x_s the read time equals the
+    echo's arrival time at 2 z/c = (z_s + rho_s + z_r - rho_r) / c, so the
+    peak sits at z* = (z_s + rho_s + z_r - rho_r) / 2 (rho at lateral offset x_s)."""
+    s = C1.replace(n_elem=1, n_samples=4000, angles=(0.0,), fs=100e6)
+    x_s, z_s = 3.0e-3, 20.0e-3
+    dzf = s.c / (2 * s.fs) / 8
+    zs = z_s - 2e-3 + np.arange(int(4e-3 / dzf)) * dzf
+    rf = simulate.simulate_rf([x_s], [z_s], [1.0], **sim_kw(s))
+    for z_r in (17.0e-3, 20.0e-3, 24.0e-3):
+        r = int(np.argmin(np.abs(zs - z_r))) if zs[0] <= z_r <= zs[-1] else 0
+        zs_r = zs.copy()
+        refs = np.full(zs.size, r)
+        if not (zs[0] <= z_r <= zs[-1]):
+            zs_r = np.concatenate([zs, [z_r]])
+            refs = np.full(zs_r.size, zs_r.size - 1)
+        img = das.fixed_delay_das(rf, [x_s], zs_r, refs, **das_kw(s))[:zs.size, 0]
+        zr = zs_r[refs[0]]
+        rho_s, rho_r = np.hypot(x_s, z_s), np.hypot(x_s, zr)
+        z_star = (z_s + rho_s + zr - rho_r) / 2
+        assert abs(zs[np.argmax(np.abs(img))] - z_star) <= 1.5 * dzf
+
+
+def test_fixed_delay_das_symmetric_and_linear():
+    s = finer_grid_case()
+    xs, zs = axes(s)
+    refs = np.full(s.nz, 60)
+    rf = simulate.simulate_rf([0.0], [zs[50]], [1.0], **sim_kw(s))
+    img = das.fixed_delay_das(rf, xs, zs, refs, **das_kw(s))
+    assert np.max(np.abs(img - img[:, ::-1])) <= 1e-13 * np.max(np.abs(img))
+    rf2 = simulate.simulate_rf([1.3e-3], [zs[80]], [-0.7], **sim_kw(s))
+    both = das.fixed_delay_das(rf + 2.0 * rf2, xs, zs, refs, **das_kw(s))
+    sep = img + 2.0 * das.fixed_delay_das(rf2, xs, zs, refs, **das_kw(s))
+    assert np.max(np.abs(both - sep)) <= 1e-13 * np.max(np.abs(both))
