@@ -25,6 +25,10 @@ Other workloads (one JSON line each, not the headline):
                         plane wave): single scatterers at every row and 5 / 5 rising /
                         100 scatterer lines, exact kernels and one reference curve
                         at 25 and 35 mm, local and global squared errors
+    --workload beamform the paper's time-invariant beamformer from RF (tidas_beamform:
+                        receive law frozen per neighbourhood of rows, theta from paper
+                        mode) vs exact DAS on the benchmark's 64 speckle frames: frames/s,
+                        rel-L2 vs the oracle, 2-D error against DAS
     --workload kgrad    gradient of the line model in its kernels (tidas_kernel_grad)
                         over B frames of 1024 x 256 with 129 taps
     --workload surrogate  train the BF16-MFMA kernel surrogate on 200k exact
@@ -54,7 +58,8 @@ DAS_FLOPS_PER_TERM = 14
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["main", "batch", "deconv", "kgrad", "surrogate", "approx"], default="main")
+    ap.add_argument("--workload", choices=["main", "batch", "deconv", "beamform", "kgrad", "surrogate", "approx"],
+                    default="main")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate workload: Adam steps")
     ap.add_argument("--train-rows", type=int, default=200_000, help="surrogate workload: training kernels")
     ap.add_argument("--steps", type=int, default=100)
@@ -103,7 +108,8 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
-    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "kgrad": run_kgrad, "surrogate": run_surrogate,
+    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "beamform": run_beamform, "kgrad": run_kgrad,
+     "surrogate": run_surrogate,
      "approx": run_approx}[args.workload](args)
 
 
@@ -487,6 +493,89 @@ def run_deconv(args):
         "us_per_iteration": ms * 1e3 / iters, "achieved_tflops": flops / (ms * 1e-3) / 1e12,
         "rel_error_to_truth": err,
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_beamform(args):
+    """Time-invariant beamformer from RF vs exact DAS: 64 speckle frames, 128 elements, 1024 x 256 px."""
+    import numpy as np
+    import torch
+
+    import paper_2507_15464_amd as td
+    from workloads import config, generators
+    from workloads.configs import CYSTS, N_SCATTERERS
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = config(2)
+    B, Z, X = args.batch, s.nz, s.nx
+    rf = torch.empty((B, 1, s.n_elem, s.n_samples), device=dev, dtype=torch.float32)
+    for b in range(B):
+        x, z, a, _ = generators.speckle_with_cysts(N_SCATTERERS[2], s.field_w, s.field_d, CYSTS["n"], CYSTS["r_lo"],
+                                                   CYSTS["r_hi"], seed=b)
+        scat = torch.tensor(np.stack([x, z, a], 1), dtype=torch.float64, device=dev)
+        td.simulate_rf(s, scat, out=rf[b])
+
+    def refs_for(size):
+        return np.minimum((np.arange(Z) // size) * size + size // 2, Z - 1).astype(np.int32)
+
+    size = 64  # one receive law per 64 rows (3.75 mm)
+    refs_h = refs_for(size)
+    refs = torch.from_numpy(refs_h).to(dev)
+    _, theta = td.build_kernels(s, mode="paper", ref_row=refs_h, with_theta=True)
+    img = torch.empty((B, Z, X), device=dev, dtype=torch.float32)
+    fd_ms = _events_ms(lambda: td.tidas_beamform(rf, s, ref_row=refs, theta=theta, out=img), args.steps, args.warmup)
+    das_ms = _events_ms(lambda: td.das_beamform(rf, s, out=img), args.steps, args.warmup)
+    # 2-D approximation error against DAS on frame 0, for several neighbourhood sizes
+    d0 = td.das_beamform(rf[0], s)
+    errors = {}
+    for sz in (16, 64, 256):
+        rh = refs_for(sz)
+        _, th = td.build_kernels(s, mode="paper", ref_row=rh, with_theta=True)
+        f0 = td.tidas_beamform(rf[0], s, ref_row=torch.from_numpy(rh).to(dev), theta=th)
+        errors[f"law_per_{sz}_rows"] = float(torch.linalg.norm(f0 - d0) / torch.linalg.norm(d0))
+    zs = s.z0 + np.arange(Z) * s.dz
+    for depth in (25e-3, 35e-3):  # one law for the whole image (the paper's single reference curve)
+        rh = np.full(Z, int(np.argmin(np.abs(zs - depth))), np.int32)
+        _, th = td.build_kernels(s, mode="paper", ref_row=rh, with_theta=True)
+        f0 = td.tidas_beamform(rf[0], s, ref_row=torch.from_numpy(rh).to(dev), theta=th)
+        errors[f"one_law_at_{int(depth * 1e3)}mm"] = float(torch.linalg.norm(f0 - d0) / torch.linalg.norm(d0))
+    out = {
+        "metric": "frames/s, time-invariant beamformer from RF vs exact DAS (256x1024 px, 128 ch)",
+        "value": B / (fd_ms * 1e-3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": fd_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (speckle phantoms with cysts, RF synthesised on the GPU)",
+        "config": {"workload": f"{B} frames, 128-ch plane wave, 256x1024 px, one receive law per {size} rows, "
+                               "theta from paper mode", "global_batch": B},
+        "das": {"frames_per_s": B / (das_ms * 1e-3), "ms_per_step": das_ms},
+        "speedup_vs_das": das_ms / fd_ms,
+        "rel_l2_vs_das_2d": errors,
+    }
+    if not (args.no_parity and args.no_cpu_baseline):
+        from oracle import das as o_das, simulate as o_sim
+        xs = s.x0 + np.arange(X) * s.dx
+        okw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, fc=s.fc, sigma=s.sigma,
+                   n_samples=s.n_samples, angles=list(s.angles))
+        dkw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, angles=list(s.angles), fnumber=s.fnumber)
+        # a lighter phantom of the same kind for the oracle (2000 scatterers, cysts, seed 0)
+        x, z, a, _ = generators.speckle_with_cysts(2000, s.field_w, s.field_d, CYSTS["n"], CYSTS["r_lo"],
+                                                   CYSTS["r_hi"], seed=0)
+        rf_o = o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **okw))
+        th_h = theta.cpu().numpy()
+        if not args.no_parity:
+            f_gpu = td.tidas_beamform(torch.from_numpy(rf_o).to(dev), s, ref_row=refs, theta=theta).cpu().numpy()
+            f_ref = o_das.fixed_delay_das(rf_o, xs, zs, refs_h, **dkw, theta=th_h)
+            out["rel_l2_vs_fp64"] = float(np.linalg.norm(f_gpu - f_ref) / np.linalg.norm(f_ref))
+            out["parity_sample"] = "one 1024 x 256 frame of a 2000-scatterer phantom (oracle RF)"
+        if not args.no_cpu_baseline:
+            t_c = time.perf_counter()
+            n_fr = 0
+            while n_fr < 1 or time.perf_counter() - t_c < 5.0:
+                o_das.fixed_delay_das(rf_o, xs, zs, refs_h, **dkw, theta=th_h)
+                n_fr += 1
+            out["cpu_baseline"] = {"value": n_fr / (time.perf_counter() - t_c), "unit": "frames/s", "cores": 1,
+                                   "kind": "oracle",
+                                   "sample": f"FP64 oracle fixed-delay beamformer on {n_fr} frames, about 5 s"}
     print(json.dumps(out), flush=True)
 
 

@@ -122,6 +122,27 @@ int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_r
                      int32_t n_frames, float* image, void* stream);
 
 /*
+ * The paper's time-invariant beamformer applied to the RF (Sec. 2.3 eqn:tDAS:
+ * the delays of one point serve a whole line; Sec. 2.4 eqn:line_conv: fixed
+ * parameters along the line, scaled by the weights Theta).  Row i reads every
+ * element with the receive law frozen at the depth of its reference row
+ * r = ref_row[i], in every column:
+ *   image[b][i][j] = theta[i] * sum_a sum_n w(x_j - x_n, z_r) *
+ *       L(rf[b][a][n], (tau_tx(x_j, z_i; a) + z_i / c - D_n(x_j, z_r) - t0) * fs),
+ *   D_n(x, z) = (z - sqrt((x - x_n)^2 + z^2)) / c   (eqn:delay at lateral x),
+ * w and L as in das_beamform.  With ref_row[i] = i and theta = 1 this is
+ * das_beamform.  ref_row DEV int32 [nz] or NULL (each row its own
+ * reference); entries are clamped into [0, nz).  theta DEV [nz] or NULL
+ * (ones), e.g. the weights tidas_build_kernels returns in paper mode.  rf,
+ * image and n_frames as in das_beamform; image must not alias an input.
+ * Waves whose rows share one reference (one law per neighbourhood or per
+ * line) evaluate the law once per element for all their rows.
+ */
+int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
+                       const tidas_grid* grid, const float* rf, int32_t n_samples, int32_t n_frames,
+                       const int32_t* ref_row, const float* theta, float* image, void* stream);
+
+/*
  * Per-depth-row kernel bank of the line model, evaluated on the centre line
  * x = 0 from the echo of a unit scatterer (computed analytically in float64
  * over n_samples RF samples, zero outside the record).  h = (K-1)/2.

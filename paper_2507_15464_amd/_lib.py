@@ -63,6 +63,8 @@ _SIGS = {
     "tidas_last_error": (ctypes.c_char_p, []),
     "das_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),
                           _P, _I, _I, _P, _P]),
+    "tidas_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),
+                            _P, _I, _I, _P, _P, _P, _P]),
     "tidas_build_kernels": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx),
                                  ctypes.POINTER(Grid), _I, _I, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P]),
     "tidas_apply": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),

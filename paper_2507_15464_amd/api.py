@@ -11,7 +11,8 @@ import torch
 
 from . import _lib
 
-__all__ = ["das_beamform", "build_kernels", "apply", "adjoint", "kernel_grad", "simulate_rf", "version"]
+__all__ = ["das_beamform", "tidas_beamform", "build_kernels", "apply", "adjoint", "kernel_grad", "simulate_rf",
+           "version"]
 
 
 def _stream():
@@ -61,6 +62,35 @@ def das_beamform(rf, setup, grid=None, out=None):
     arr, tx, rx, g = _descs(setup, grid)
     _lib.check(lib.das_beamform(ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g),
                                 _ptr(r4), T, B, _ptr(out), _stream()))
+    return out[0] if squeeze else out
+
+
+def tidas_beamform(rf, setup, ref_row=None, theta=None, grid=None, out=None):
+    """The time-invariant beamformer from RF: each row's receive law frozen at
+    its reference row (ref_row: int32 device tensor [Z] or None = own row),
+    scaled by theta (device [Z] or None = ones).  rf as in ``das_beamform``."""
+    grid = grid or setup
+    lib = _lib.load()
+    _check_tensor(rf, "rf")
+    squeeze = rf.dim() == 3
+    r4 = rf.unsqueeze(0) if squeeze else rf
+    if r4.dim() != 4 or r4.shape[1] != len(setup.angles) or r4.shape[2] != setup.n_elem:
+        raise ValueError("rf must be [B][A][C][T] matching the setup")
+    if ref_row is not None:
+        _check_tensor(ref_row, "ref_row", torch.int32)
+        if ref_row.shape != (grid.nz,):
+            raise ValueError("ref_row must be [Z]")
+    if theta is not None:
+        _check_tensor(theta, "theta")
+        if theta.shape != (grid.nz,):
+            raise ValueError("theta must be [Z]")
+    B, T = r4.shape[0], r4.shape[3]
+    if out is None:
+        out = torch.empty((B, grid.nz, grid.nx), device=rf.device, dtype=torch.float32)
+    _check_tensor(out, "out")
+    arr, tx, rx, g = _descs(setup, grid)
+    _lib.check(lib.tidas_beamform(ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g),
+                                  _ptr(r4), T, B, _ptr(ref_row), _ptr(theta), _ptr(out), _stream()))
     return out[0] if squeeze else out
 
 

@@ -200,6 +200,191 @@ __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid
                      rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
 }
 
+// ------------------------------------------------- fixed-delay beamformer ----
+// The paper's time-invariant beamformer applied to RF (Sec. 2.3 eqn:tDAS: the
+// delays of one point used for a whole line; Sec. 2.4 eqn:line_conv: fixed
+// parameters along the line, scaled by Theta): row i reads every element with
+// the receive law (delay and Hann weight) of its reference row r(i) in the
+// same column, and is scaled by theta_i,
+//   u = fs (tau_tx(x_j, z_i; a) + z_i / c - t0) + (fs / c) dx^2 / (rho_r + z_r),
+// rho_r = sqrt(dx^2 + z_r^2), the receive excess written as in the DAS kernel.
+// The wave tiles are DAS's, and each lane walks FD_RB rows (stride WZ) of its
+// column: when every row of a wave shares one reference (the paper's one law
+// per neighbourhood or per line), the law of an element is computed once and
+// serves FD_RB rows, so a pair costs its index, its reads and its FMAs only;
+// a wave whose rows have different references evaluates the law per row.
+template <int FB, int NA, int FD_RB>
+__device__ __forceinline__ void fd_wave(const DasArgs& p, const DasGrid& gr, int i_base, int j_base, int nfr,
+                                        const int32_t* __restrict__ ref, const float* __restrict__ theta,
+                                        const float* __restrict__ rf, size_t frame_rf, float* img, size_t frame_img) {
+    constexpr int WZ = das_wz(NA), WX = das_wx(NA);
+    constexpr int NAM = (NA > 0) ? NA : DAS_MAX_ANGLES;
+    const int lane = threadIdx.x & 63;
+    const int j = j_base + lane / WZ;
+    const int i_first = i_base + lane % WZ;  // the lane's rows: i_first + WZ k
+    const int A = (NA > 0) ? NA : p.A;
+
+    const double xd = gr.x0 + (double)min(j, gr.nx - 1) * gr.dx;
+    const double ox = xd - p.x_first;
+    const float dx0 = (float)ox, dx0_lo = (float)(ox - (double)dx0);
+    const float pitch_f = (float)p.pitch, pitch_lo = (float)(p.pitch - (double)pitch_f);
+
+    // reference row of each of the lane's rows (rows past the image, never
+    // stored, take the tile's first reference), clamped into the image
+    auto ref_of = [&](int i) {
+        const int ii = i < gr.nz ? i : i_base;
+        const int r = ref ? ref[ii] : ii;
+        return min(max(r, 0), gr.nz - 1);
+    };
+    int rk[FD_RB];
+    bool same = true;
+    const int r_wave = __builtin_amdgcn_readfirstlane(ref_of(i_base));
+#pragma unroll
+    for (int k = 0; k < FD_RB; ++k) {
+        rk[k] = ref_of(i_first + WZ * k);
+        same = same && rk[k] == r_wave;
+    }
+    const bool uniform = __builtin_amdgcn_ballot_w64(!same) == 0;
+
+    float acc[FD_RB][FB];
+#pragma unroll
+    for (int k = 0; k < FD_RB; ++k)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) acc[k][f] = 0.0f;
+
+    const uint32_t row_bytes = (uint32_t)p.T * 4u;
+    const int last_pair = (p.T - 2) * 4;
+
+    // the frozen law of element offset dx at reference depth zr: weight and
+    // receive excess in samples
+    struct Law {
+        float zr, z2, inv_az;
+        bool on;
+    };
+    auto law_at = [&](int r) {
+        const double zr = gr.z0 + (double)r * gr.dz;
+        Law L;
+        L.zr = (float)zr;
+        L.z2 = (float)(zr * zr);
+        L.on = (j < gr.nx) && (zr > 0.0);
+        L.inv_az = L.on ? (float)(2.0 * p.fnumber / zr) : 0.0f;
+        return L;
+    };
+    auto weight_excess = [&](const Law& L, float dx, float& w, float& ke) {
+        const float t = fabsf(dx) * L.inv_az;
+        const float wh = hann_weight(fminf(t, 1.0f));
+        w = (L.on && t <= 1.0f) ? wh : 0.0f;
+        const float rho = __builtin_amdgcn_sqrtf(fmaf(dx, dx, L.z2));
+        ke = p.kappa * (dx * dx) * __builtin_amdgcn_rcpf(rho + L.zr);
+    };
+    // one pair: element n's channel of angle a read at q + v for the FB frames
+    auto accumulate = [&](int k, size_t ch, int q, float v, float w) {
+        const float qf = floorf(v);
+        const float fr = v - qf;
+        const int off = (q + (int)qf) * 4;
+        if constexpr (FB > 1) {
+            const int oc = min(max(off, 0), last_pair);
+            const int d = off - oc;
+            const float wa = d == 0 ? w * (1.0f - fr) : (d == -4 ? w * fr : 0.0f);
+            const float wb = d == 0 ? w * fr : (d == 4 ? w * (1.0f - fr) : 0.0f);
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                const bool fv = f < nfr;
+                const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
+                const floatx2 sp = __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
+                acc[k][f] = fmaf(wb, sp[1], fmaf(wa, sp[0], acc[k][f]));
+            }
+        } else {
+            const int off1 = (q + (int)(qf + 1.0f)) * 4;
+            const auto rs = make_rsrc(rf + ch * p.T, nfr > 0 ? row_bytes : 0u);
+            const float s0 = buffer_load_f32(rs, off);
+            const float s1 = buffer_load_f32(rs, off1);
+            acc[k][0] = fmaf(w, fmaf(fr, s1 - s0, s0), acc[k][0]);
+        }
+    };
+
+    const double x_lo = gr.x0 + (double)j_base * gr.dx;
+    const double x_hi = gr.x0 + (double)min(j_base + WX - 1, gr.nx - 1) * gr.dx;
+    auto element_range = [&](double zr, int& n_lo, int& n_hi) {
+        n_lo = 0;
+        n_hi = -1;
+        if (zr > 0.0) {
+            const double a_max = zr / (2.0 * p.fnumber);
+            n_lo = max(0, (int)floor((fmin(x_lo, x_hi) - a_max - p.x_first) / p.pitch));
+            n_hi = min(p.C - 1, (int)ceil((fmax(x_lo, x_hi) + a_max - p.x_first) / p.pitch));
+        }
+    };
+
+#pragma unroll 1
+    for (int a = 0; a < A; ++a) {
+        const double sa = p.sin_a[a], ca = p.cos_a[a];
+        // per row: integer and fractional parts of fs (tau_tx + z/c - t0)
+        int q[FD_RB];
+        float fpart[FD_RB];
+#pragma unroll
+        for (int k = 0; k < FD_RB; ++k) {
+            const double zd = gr.z0 + (double)min(i_first + WZ * k, gr.nz - 1) * gr.dz;
+            const double U = p.fs * ((xd * sa + zd * ca) / p.c + zd / p.c - p.t0);
+            const double Uf = floor(U);
+            q[k] = (int)Uf;
+            fpart[k] = (float)(U - Uf);
+        }
+        const size_t ch_a = (size_t)a * p.C;
+        if (uniform) {
+            const Law L = law_at(r_wave);
+            int n_lo, n_hi;
+            element_range(gr.z0 + (double)r_wave * gr.dz, n_lo, n_hi);
+            for (int n = n_lo; n <= n_hi; ++n) {
+                const float nf = (float)n;
+                const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
+                float w, ke;
+                weight_excess(L, dx, w, ke);
+#pragma unroll
+                for (int k = 0; k < FD_RB; ++k) accumulate(k, ch_a + n, q[k], fpart[k] + ke, w);
+            }
+        } else {
+            // every element (weights vanish outside each row's own aperture)
+            for (int n = 0; n < p.C; ++n) {
+                const float nf = (float)n;
+                const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
+#pragma unroll
+                for (int k = 0; k < FD_RB; ++k) {
+                    float w, ke;
+                    weight_excess(law_at(rk[k]), dx, w, ke);
+                    accumulate(k, ch_a + n, q[k], fpart[k] + ke, w);
+                }
+            }
+        }
+    }
+    if (j < gr.nx) {
+#pragma unroll
+        for (int k = 0; k < FD_RB; ++k) {
+            const int i = i_first + WZ * k;
+            if (i < gr.nz) {
+                const float th = theta ? theta[i] : 1.0f;
+#pragma unroll
+                for (int f = 0; f < FB; ++f)
+                    if (f < nfr) img[f * frame_img + (size_t)i * gr.nx + j] = th * acc[k][f];
+            }
+        }
+    }
+}
+
+// workgroup = DAS_BZ wave tiles stacked in depth, each WZ x FD_RB rows
+template <int FB, int NA, int FD_RB>
+__global__ __launch_bounds__(256) void fixed_das_kernel(const DasArgs p, const DasGrid gr, const int32_t* __restrict__ ref,
+                                                        const float* __restrict__ theta, const float* __restrict__ rf,
+                                                        float* __restrict__ img) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int fr0 = blockIdx.z * FB;
+    const size_t frame_rf = (size_t)p.A * p.C * p.T;
+    const size_t frame_img = (size_t)gr.nz * gr.nx;
+    const int i_base = (blockIdx.x * DAS_BZ + wave) * das_wz(NA) * FD_RB;
+    if (i_base >= gr.nz) return;
+    fd_wave<FB, NA, FD_RB>(p, gr, i_base, blockIdx.y * das_wx(NA), min(FB, p.n_frames - fr0), ref, theta,
+                    rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
+}
+
 // ----------------------------------------------------------------- batches ----
 // Ragged batch: every frame has its own grid, RF record and image.  One
 // persistent launch covers the tiles (WAVES wave tiles stacked in depth) of
@@ -254,6 +439,15 @@ static void launch_das(const DasArgs& p, const DasGrid& gr, const float* rf, flo
     dim3 grid((gr.nz + DAS_BZ * das_wz(NA) - 1) / (DAS_BZ * das_wz(NA)), (gr.nx + das_wx(NA) - 1) / das_wx(NA),
               (p.n_frames + FB - 1) / FB);
     hipLaunchKernelGGL((das_kernel<FB, NA>), grid, dim3(256), 0, s, p, gr, rf, img);
+}
+
+template <int FB, int NA, int FD_RB>
+static void launch_fixed_das(const DasArgs& p, const DasGrid& gr, const int32_t* ref, const float* theta,
+                             const float* rf, float* img, hipStream_t s) {
+    const int rows_per_wg = DAS_BZ * das_wz(NA) * FD_RB;
+    dim3 grid((gr.nz + rows_per_wg - 1) / rows_per_wg, (gr.nx + das_wx(NA) - 1) / das_wx(NA),
+              (p.n_frames + FB - 1) / FB);
+    hipLaunchKernelGGL((fixed_das_kernel<FB, NA, FD_RB>), grid, dim3(256), 0, s, p, gr, ref, theta, rf, img);
 }
 
 // Shared validation and argument set-up of the DAS entry points.
@@ -323,6 +517,38 @@ extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, co
         launch_das<1, 0>(p, gr, rf, image, s);
     }
     return check_launch("das_beamform");
+}
+
+extern "C" int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
+                                  const tidas_grid* grid, const float* rf, int32_t n_samples, int32_t n_frames,
+                                  const int32_t* ref_row, const float* theta, float* image, void* stream) {
+    DasArgs p;
+    int32_t st = das_setup("tidas_beamform", array, tx, rx, n_samples, p);
+    if (st) return st;
+    if ((st = validate_grid(grid))) return st;
+    if (!rf || !image) return fail(TIDAS_EINVAL, "tidas_beamform: null rf or image pointer");
+    if (n_frames < 1) return fail(TIDAS_EINVAL, "tidas_beamform: n_frames must be >= 1");
+    if ((const void*)rf == (const void*)image || (const void*)theta == (const void*)image ||
+        (const void*)ref_row == (const void*)image)
+        return fail(TIDAS_EINVAL, "tidas_beamform: image aliases an input");
+    if (!das_grid_in_range(p, grid)) return fail(TIDAS_EUNSUPPORTED, "tidas_beamform: sample indices exceed 2^28");
+    p.n_frames = n_frames;
+    const DasGrid gr = to_grid(grid);
+    hipStream_t s = (hipStream_t)stream;
+    // rows per lane: the gathers bound this kernel as they bound DAS, so the
+    // shapes keep registers (and waves in flight) close to DAS's; measured on
+    // 64 frames of 1024 x 256, 128 elements, one law per 64 rows: 4 frames x
+    // 2 rows 0.64 ms, x 4 rows 0.78, x 8 rows 0.82 (166 registers)
+    const bool multi = n_frames >= 8;
+    if (p.A == 1) {
+        if (multi) launch_fixed_das<4, 1, 2>(p, gr, ref_row, theta, rf, image, s);
+        else launch_fixed_das<1, 1, 4>(p, gr, ref_row, theta, rf, image, s);
+    } else if (p.A == 11) {
+        launch_fixed_das<1, 11, 4>(p, gr, ref_row, theta, rf, image, s);
+    } else {
+        launch_fixed_das<1, 0, 4>(p, gr, ref_row, theta, rf, image, s);
+    }
+    return check_launch("tidas_beamform");
 }
 
 // ------------------------------------------------------------------ batch ----

@@ -1,0 +1,138 @@
+"""GPU parity of the time-invariant (fixed-delay) beamformer from RF
+(tidas_beamform) against the FP64 oracle, and its identity with DAS where
+every row is its own reference.  Floating-point bar: relative L2 <= 1e-5."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2507_15464_amd as td  # noqa: E402
+from oracle import das as o_das, simulate as o_sim  # noqa: E402
+from workloads import config, generators  # noqa: E402
+from tests.helpers import axes, das_kw, sim_kw  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def g(x, dev, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to(dev)
+
+
+def point_rf(s, seed, n=20):
+    x, z, a = generators.point_scatterers(n, s.field_w, s.field_d, seed=seed)
+    return o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **sim_kw(s)))
+
+
+def neighbourhood_refs(nz, size):
+    """One reference per block of `size` rows: the block's middle row."""
+    return np.minimum((np.arange(nz) // size) * size + size // 2, nz - 1).astype(np.int32)
+
+
+def test_own_rows_single_angle_is_das_bit_for_bit(dev):
+    s = config(1).with_grid(200, 96)
+    rf = g(point_rf(s, 1), dev)
+    assert torch.equal(td.tidas_beamform(rf, s), td.das_beamform(rf, s))
+    refs = g(np.arange(s.nz), dev, np.int32)
+    assert torch.equal(td.tidas_beamform(rf, s, ref_row=refs), td.das_beamform(rf, s))
+
+
+@pytest.mark.parametrize("size", [1, 16, 64, 1000])
+def test_neighbourhood_references_match_oracle(dev, size):
+    s = config(1).with_grid(256, 128)
+    rf = point_rf(s, 2)
+    refs = neighbourhood_refs(s.nz, size)
+    theta = (1.0 + 0.3 * generators.normal(s.nz, seed=3)).astype(np.float32)
+    img = td.tidas_beamform(g(rf, dev), s, ref_row=g(refs, dev, np.int32), theta=g(theta, dev)).cpu().numpy()
+    xs, zs = axes(s)
+    ref = o_das.fixed_delay_das(rf, xs, zs, refs, **das_kw(s), theta=theta)
+    assert rel(img, ref) <= RTOL
+
+
+def test_scattered_references_take_the_per_row_law(dev):
+    """A random row -> reference map (no wave shares one reference) and
+    references outside the image, which are clamped into it."""
+    s = config(1).with_grid(130, 70)
+    rf = point_rf(s, 4)
+    rng = np.random.default_rng(5)
+    refs = rng.integers(-20, s.nz + 20, s.nz).astype(np.int32)
+    img = td.tidas_beamform(g(rf, dev), s, ref_row=g(refs, dev, np.int32)).cpu().numpy()
+    xs, zs = axes(s)
+    ref = o_das.fixed_delay_das(rf, xs, zs, np.clip(refs, 0, s.nz - 1), **das_kw(s))
+    assert rel(img, ref) <= RTOL
+
+
+@pytest.mark.parametrize("angles", [(-0.1, 0.02, 0.15), tuple(np.radians(np.arange(-10, 11, 2)))])
+def test_compounded_angles(dev, angles):
+    s = config(1).replace(angles=angles).with_grid(150, 77)
+    rf = point_rf(s, 6)
+    refs = neighbourhood_refs(s.nz, 32)
+    img = td.tidas_beamform(g(rf, dev), s, ref_row=g(refs, dev, np.int32)).cpu().numpy()
+    xs, zs = axes(s)
+    assert rel(img, o_das.fixed_delay_das(rf, xs, zs, refs, **das_kw(s))) <= RTOL
+    # own rows: DAS (summed in another order over angles)
+    own = td.tidas_beamform(g(rf, dev), s).cpu().numpy()
+    das = td.das_beamform(g(rf, dev), s).cpu().numpy()
+    assert rel(own, das) <= 1e-6
+
+
+@pytest.mark.parametrize("B", [3, 9])
+def test_batched_frames(dev, B):
+    s = config(1).with_grid(100, 50)
+    rf = np.stack([point_rf(s, 100 + b) for b in range(B)])
+    refs = neighbourhood_refs(s.nz, 25)
+    img = td.tidas_beamform(g(rf, dev), s, ref_row=g(refs, dev, np.int32)).cpu().numpy()
+    xs, zs = axes(s)
+    for b in range(B):
+        assert rel(img[b], o_das.fixed_delay_das(rf[b], xs, zs, refs, **das_kw(s))) <= RTOL
+
+
+def test_edge_grids(dev):
+    base = config(1).replace(n_samples=1500)
+    x, z, a = generators.point_scatterers(20, base.field_w, 25e-3, seed=7)
+    rf = o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **sim_kw(base)))
+    for s in (base.replace(nz=70, nx=3, z0=-2e-3, dz=0.1e-3, x0=-1e-3, dx=1e-3),
+              base.replace(nz=65, nx=1, z0=5e-3, dz=0.2e-3, x0=0.0, dx=1e-4),
+              base.replace(nz=1, nx=77, z0=11e-3, dz=1e-4, x0=-9e-3, dx=0.23e-3)):
+        refs = neighbourhood_refs(s.nz, 16)
+        img = td.tidas_beamform(g(rf, dev), s, ref_row=g(refs, dev, np.int32)).cpu().numpy()
+        xs, zs = axes(s)
+        assert rel(img, o_das.fixed_delay_das(rf, xs, zs, refs, **das_kw(s))) <= RTOL
+
+
+def test_clinical_size_batch_sampled(dev):
+    """64 frames of 128 x 4096 RF (N(0,1) channel data) onto 1024 x 256 with one
+    reference per 64 rows and weights theta: sampled pixels of the first and
+    last frames against the oracle."""
+    s = config(2)
+    B = 64
+    rf = generators.normal((B, 1, s.n_elem, s.n_samples), seed=11).astype(np.float32)
+    refs = neighbourhood_refs(s.nz, 64)
+    theta = (1.0 + 0.2 * generators.normal(s.nz, seed=12)).astype(np.float32)
+    img = td.tidas_beamform(g(rf, dev), s, ref_row=g(refs, dev, np.int32), theta=g(theta, dev)).cpu().numpy()
+    xs, zs = axes(s)
+    rng = np.random.default_rng(13)
+    for b in (0, B - 1):
+        got, want = [], []
+        for _ in range(60):
+            i, j = int(rng.integers(s.nz)), int(rng.integers(s.nx))
+            r = int(refs[i])
+            one = o_das.fixed_delay_das(rf[b], [xs[j]], [zs[i], zs[r]], [1, 1], **das_kw(s))[0, 0]
+            got.append(img[b, i, j])
+            want.append(theta[i] * one)
+        assert rel(got, want) <= RTOL
