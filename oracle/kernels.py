@@ -26,6 +26,13 @@ scatterer of amplitude 1 before its FP32 rounding.
   theta_i = sum_B a_i b_i / sum_B a_i^2 (its time-domain form, Plancherel);
   finally K[i] = theta_i * h_{r(i)}.
 
+* lateral mode (the separable 2-D extension the conclusion, Sec. 4, leaves
+  for future work): row i's lateral kernel is the DAS response of the same
+  unit scatterer at (0, z_i) along its own row, normalised by its centre,
+      Kx[i][m+h] = DAS(RF1_i)(m dx, z_i) / DAS(RF1_i)(0, z_i)   (0 if the centre is 0),
+  so that a depth pass with exact kernels followed by a lateral pass with
+  these kernels reproduces DAS along an on-axis scatterer's own row.
+
 * line mode (Sec. 2.4, eqn:line_conv taken literally): the line model is
   Theta times the fixed-delay beamformer of the RF.  By Born linearity its
   exact form on a reflectivity map has, for output row i and source row
@@ -143,6 +150,17 @@ def theta_frequency(a, b):
     num = np.sum(np.conj(A) * B + A * np.conj(B)).real
     den = 2.0 * np.sum(np.abs(A) ** 2)
     return float(num / den) if den > 0 else 0.0
+
+
+def lateral_kernels(z_rows, dx, K, **setup):
+    """Lateral-mode kernel bank [Z][K]: Kx[i][m+h] = DAS(RF1_i)(m dx, z_i) / DAS(RF1_i)(0, z_i)."""
+    h = (K - 1) // 2
+    z = np.asarray(z_rows, np.float64)[:, None]
+    m = np.arange(-h, h + 1, dtype=np.float64)[None, :]
+    prof = unit_das(m * dx, z, 0.0, z, **setup)
+    centre = prof[:, h:h + 1]
+    safe = np.where(centre != 0.0, centre, 1.0)
+    return np.where(centre != 0.0, prof / safe, 0.0)
 
 
 def fine_half_length(fs, sigma):

@@ -21,6 +21,11 @@ learnable):
     Kbar[i][m+h] = sum_b sum_j Ybar[b][i][j] * R[b][i-m][j],   R = 0 outside [0, Z).
 
 All three are written as plain loops over the tap index m.
+
+The lateral pass of the separable 2-D extension (future work in Sec. 4)
+convolves each depth row along the lateral axis with that row's kernel:
+
+    Y2[b][i][j] = sum_{m=-h..h} Kx[i][m+h] * Y[b][i][j-m],   Y = 0 outside [0, X).
 """
 import numpy as np
 
@@ -87,6 +92,24 @@ def kernel_grad(R, Yb, K):
             if 0 <= s < Z:
                 G[i, m + h] = np.sum(Y3[:, i, :] * R3[:, s, :])
     return G
+
+
+def apply_lateral(Kx, Y):
+    """Y2 = lateral pass of Y ([Z][X] or [B][Z][X]) with the row kernels Kx [Z][K]."""
+    Kx, h = _check(Kx)
+    Y = np.asarray(Y, np.float64)
+    squeeze = Y.ndim == 2
+    Y3 = Y[None] if squeeze else Y
+    B, Z, X = Y3.shape
+    if Kx.shape[0] != Z:
+        raise ValueError("kernel bank rows must equal image rows")
+    out = np.zeros_like(Y3)
+    for m in range(-h, h + 1):
+        for j in range(X):
+            s = j - m
+            if 0 <= s < X:
+                out[:, :, j] += Kx[None, :, m + h] * Y3[:, :, s]
+    return out[0] if squeeze else out
 
 
 def matrix(K):

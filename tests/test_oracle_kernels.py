@@ -1,10 +1,11 @@
 """Pins of the oracle's kernel construction: exact DAS PSF kernels
-(Sec. 2.2 eq:PSF) and paper-mode fixed-delay + theta kernels (Sec. 2.3
-eqn:tDAS, eqn:theta; Sec. 3.1-3.2 FWHM window)."""
+(Sec. 2.2 eq:PSF), paper-mode fixed-delay + theta kernels (Sec. 2.3
+eqn:tDAS, eqn:theta; Sec. 3.1-3.2 FWHM window) and the lateral kernels of the
+separable 2-D extension, with its lateral pass."""
 import numpy as np
 import pytest
 
-from oracle import das, kernels, pulse, simulate
+from oracle import das, kernels, pulse, simulate, tidas
 from workloads import config
 from tests.helpers import das_kw, sim_kw, oracle_kw
 
@@ -203,3 +204,70 @@ def test_line_mode_single_element_equals_exact():
     ref = kernels.exact_kernels(zr, s.dz, 33, **oracle_kw(s))
     assert np.allclose(th, 1.0, rtol=0, atol=1e-12)
     assert np.max(np.abs(kb - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_lateral_kernel_rows_equal_das_row_of_materialised_echo():
+    """Lateral kernels equal RF synthesis (FP64) followed by DAS along the
+    scatterer's own row, divided by the value at the scatterer; unsteered,
+    they are symmetric (lateral symmetry of DAS for an on-axis scatterer)."""
+    s = C1.replace(n_samples=1500)
+    K = 15
+    h = 7
+    zr = np.array([5.3e-3, 12.0e-3, 18.4e-3])
+    kx = kernels.lateral_kernels(zr, s.dx, K, **oracle_kw(s))
+    for i, z in enumerate(zr):
+        rf = simulate.simulate_rf([0.0], [z], [1.0], **sim_kw(s))
+        row = das.das(rf, np.arange(-h, h + 1) * s.dx, [z], **das_kw(s))[0]
+        assert np.max(np.abs(kx[i] - row / row[h])) <= 1e-12 * np.max(np.abs(row / row[h]))
+        assert kx[i, h] == 1.0
+        assert np.max(np.abs(kx[i] - kx[i, ::-1])) <= 1e-13
+    # steered transmits break the symmetry
+    st = s.replace(angles=(0.15,))
+    ks = kernels.lateral_kernels(zr, s.dx, K, **oracle_kw(st))
+    assert np.max(np.abs(ks - ks[:, ::-1])) > 1e-3
+
+
+@pytest.mark.parametrize("Z,X,K", [(1, 1, 1), (4, 9, 3), (6, 20, 7), (3, 5, 11)])
+def test_lateral_pass_equals_row_matrices_and_numpy_convolve(Z, X, K):
+    from workloads import generators
+    kx = generators.normal((Z, K), seed=Z + K)
+    Y = generators.normal((2, Z, X), seed=X)
+    out = tidas.apply_lateral(kx, Y)
+    h = (K - 1) // 2
+    for i in range(Z):
+        M = np.zeros((X, X))
+        for j in range(X):
+            for m in range(-h, h + 1):
+                if 0 <= j - m < X:
+                    M[j, j - m] = kx[i, m + h]
+        for b in range(2):
+            assert np.max(np.abs(out[b, i] - M @ Y[b, i])) <= 1e-12
+            full = np.convolve(Y[b, i], kx[i])          # length X + K - 1, offset h
+            assert np.max(np.abs(out[b, i] - full[h:h + X])) <= 1e-12
+
+
+def test_separable_model_reproduces_das_along_the_scatterers_row():
+    """Depth pass with exact kernels, then lateral pass with lateral kernels,
+    on the reflectivity of one on-grid scatterer at (0, z_s): the scatterer's
+    row equals DAS's row, and its column is the depth pass's column (the
+    lateral centre tap is 1)."""
+    s = C1.replace(n_samples=1500, nz=40, nx=15, dz=0.05e-3, dx=0.15e-3, z0=10e-3, x0=-7 * 0.15e-3)
+    xs = s.x0 + np.arange(s.nx) * s.dx
+    zs = s.z0 + np.arange(s.nz) * s.dz
+    j0, i0 = 7, 20
+    assert abs(xs[j0]) < 1e-15
+    kz = kernels.exact_kernels(zs, s.dz, 41, **oracle_kw(s))
+    kx = kernels.lateral_kernels(zs, s.dx, 15, **oracle_kw(s))
+    R = np.zeros((s.nz, s.nx))
+    R[i0, j0] = 1.0
+    Y2 = tidas.apply_lateral(kx, tidas.apply(kz, R))
+    rf = simulate.simulate_rf([0.0], [zs[i0]], [1.0], **sim_kw(s))
+    D = das.das(rf, xs, zs, **das_kw(s))
+    scale = np.max(np.abs(D))
+    assert scale > 0.1
+    assert np.max(np.abs(Y2[i0] - D[i0])) <= 1e-12 * scale
+    Y1 = tidas.apply(kz, R)
+    assert np.array_equal(Y2[:, j0], Y1[:, j0])
+    assert abs(Y1[i0, j0] - D[i0, j0]) <= 1e-12 * scale
+    # elsewhere it is an approximation, and a better one than the depth pass alone
+    assert np.linalg.norm(Y2 - D) < 0.5 * np.linalg.norm(Y1 - D)
