@@ -29,6 +29,10 @@ Other workloads (one JSON line each, not the headline):
                         receive law frozen per neighbourhood of rows, theta from paper
                         mode) vs exact DAS on the benchmark's 64 speckle frames: frames/s,
                         rel-L2 vs the oracle, 2-D error against DAS
+    --workload separable  the separable 2-D extension: the line model's depth pass
+                        followed by a lateral per-row pass (tidas_apply_lateral) on the
+                        benchmark's 64 frames: time, HBM roofline of the lateral pass,
+                        2-D error against DAS with and without the lateral pass
     --workload kgrad    gradient of the line model in its kernels (tidas_kernel_grad)
                         over B frames of 1024 x 256 with 129 taps
     --workload surrogate  train the BF16-MFMA kernel surrogate on 200k exact
@@ -58,7 +62,8 @@ DAS_FLOPS_PER_TERM = 14
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["main", "batch", "deconv", "beamform", "kgrad", "surrogate", "approx"],
+    ap.add_argument("--workload", choices=["main", "batch", "deconv", "beamform", "separable", "kgrad", "surrogate",
+                                           "approx"],
                     default="main")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate workload: Adam steps")
     ap.add_argument("--train-rows", type=int, default=200_000, help="surrogate workload: training kernels")
@@ -108,7 +113,8 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
-    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "beamform": run_beamform, "kgrad": run_kgrad,
+    {"main": run_main, "batch": run_batch, "deconv": run_deconv, "beamform": run_beamform,
+     "separable": run_separable, "kgrad": run_kgrad,
      "surrogate": run_surrogate,
      "approx": run_approx}[args.workload](args)
 
@@ -576,6 +582,87 @@ def run_beamform(args):
             out["cpu_baseline"] = {"value": n_fr / (time.perf_counter() - t_c), "unit": "frames/s", "cores": 1,
                                    "kind": "oracle",
                                    "sample": f"FP64 oracle fixed-delay beamformer on {n_fr} frames, about 5 s"}
+    print(json.dumps(out), flush=True)
+
+
+def run_separable(args):
+    """Depth pass + lateral pass on 64 speckle maps of 1024 x 256: time, roofline, 2-D error against DAS."""
+    import numpy as np
+    import torch
+
+    import paper_2507_15464_amd as td
+    from workloads import config, generators
+    from workloads.configs import CYSTS, N_SCATTERERS
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = config(2)
+    B, Z, X, K = args.batch, s.nz, s.nx, s.K
+    KX = 33
+    R = torch.empty((B, Z, X), device=dev, dtype=torch.float32)
+    phantoms = []
+    for b in range(B):
+        x, z, a, _ = generators.speckle_with_cysts(N_SCATTERERS[2], s.field_w, s.field_d, CYSTS["n"], CYSTS["r_lo"],
+                                                   CYSTS["r_hi"], seed=b)
+        phantoms.append((x, z, a))
+        i, j, _, _ = generators.snap_to_grid(x, z, s.x0, s.dx, X, s.z0, s.dz, Z)
+        R[b] = torch.from_numpy(generators.reflectivity_map(i, j, a, Z, X).astype(np.float32))
+    kz = td.build_kernels(s, mode="exact")
+    prep = td.prepare(kz)
+    kx = td.build_kernels(s, K=KX, mode="lateral")
+    Y1 = torch.empty_like(R)
+    Y2 = torch.empty_like(R)
+    td.apply(prep, R, out=Y1)
+    lat_ms = _events_ms(lambda: td.apply_lateral(kx, Y1, out=Y2), args.steps, args.warmup)
+    both_ms = _events_ms(lambda: (td.apply(prep, R, out=Y1), td.apply_lateral(kx, Y1, out=Y2)), args.steps,
+                         args.warmup)
+    lat_bytes = 8.0 * B * Z * X + 4.0 * Z * KX
+    lat_gbs = lat_bytes / (lat_ms * 1e-3) / 1e9
+    # 2-D error against DAS on frame 0 (phantom snapped to the grid, RF of the snapped scatterers)
+    x, z, a = phantoms[0]
+    _, _, zs_, xs_ = generators.snap_to_grid(x, z, s.x0, s.dx, X, s.z0, s.dz, Z)
+    scat = torch.tensor(np.stack([xs_, zs_, a], 1), dtype=torch.float64, device=dev)
+    d0 = td.das_beamform(td.simulate_rf(s, scat), s)
+    y1 = td.apply(prep, R[0])
+    nd = torch.linalg.norm(d0)
+    errors = {"depth_pass_only": float(torch.linalg.norm(y1 - d0) / nd)}
+    for kxn in (17, 33, 65):
+        kk = td.build_kernels(s, K=kxn, mode="lateral")
+        errors[f"with_lateral_{kxn}_taps"] = float(torch.linalg.norm(td.apply_lateral(kk, y1) - d0) / nd)
+    out = {
+        "metric": "frames/s, separable 2-D model (depth pass + lateral pass) at 256x1024 px",
+        "value": B / (both_ms * 1e-3), "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": both_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (speckle phantoms with cysts snapped to the grid)",
+        "config": {"workload": f"{B} frames of 1024 x 256 px, 129-tap exact depth kernels, {KX}-tap lateral kernels",
+                   "global_batch": B},
+        "lateral_pass": {"ms_per_step": lat_ms, "frames_per_s": B / (lat_ms * 1e-3)},
+        "roofline": {"bound": "hbm", "achieved": lat_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": lat_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "lateral_pass_kernel",
+                     "bytes_per_launch": lat_bytes},
+        "rel_l2_vs_das_2d": errors,
+    }
+    if not (args.no_parity and args.no_cpu_baseline):
+        from oracle import kernels as o_k, tidas as o_t
+        zs = s.z0 + np.arange(Z) * s.dz
+        okw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, fc=s.fc, sigma=s.sigma,
+                   n_samples=s.n_samples, angles=list(s.angles), fnumber=s.fnumber)
+        kz_o = o_k.exact_kernels(zs, s.dz, K, **okw)
+        kx_o = o_k.lateral_kernels(zs, s.dx, KX, **okw)
+        x, z, a = phantoms[0]
+        i, j, _, _ = generators.snap_to_grid(x, z, s.x0, s.dx, X, s.z0, s.dz, Z)
+        R_host = generators.reflectivity_map(i, j, a, Z, X).astype(np.float32)
+        t_c = time.perf_counter()
+        y_ref = o_t.apply_lateral(kx_o, o_t.apply(kz_o, R_host))
+        cpu_s = time.perf_counter() - t_c
+        if not args.no_parity:
+            assert torch.equal(R[0].cpu(), torch.from_numpy(R_host))
+            y_gpu = Y2[0].cpu().numpy()
+            out["rel_l2_vs_fp64"] = float(np.linalg.norm(y_gpu - y_ref) / np.linalg.norm(y_ref))
+            out["parity_sample"] = "frame 0 of the timed launch (kernels built by each side)"
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {"value": 1.0 / cpu_s, "unit": "frames/s", "cores": 1, "kind": "oracle",
+                                   "sample": "FP64 oracle depth + lateral pass on one frame"}
     print(json.dumps(out), flush=True)
 
 

@@ -66,6 +66,7 @@ extern "C" {
 #define TIDAS_MODE_EXACT 0 /* kernel = DAS PSF of a unit scatterer (Sec. 2.2 eq:PSF)        */
 #define TIDAS_MODE_PAPER 1 /* kernel = theta x fixed-delay response (Sec. 2.3, eqn:theta)  */
 #define TIDAS_MODE_LINE 2  /* kernel = theta x fixed-delay line on the RF (Sec. 2.4)       */
+#define TIDAS_MODE_LATERAL 3 /* lateral profile of the row's PSF (separable 2-D extension) */
 
 /* Linear array: element count C >= 1, pitch > 0, speed of sound c > 0 (Sec. 2.1). */
 typedef struct tidas_array {
@@ -169,7 +170,12 @@ int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, const tidas
  *   beamformer of the RF, expressed on the reflectivity by Born linearity):
  *   theta_i, r and W_r as in paper mode, and
  *     kernels[i][m+h] = theta_i * F_r[unit echo at z_i - m dz](z_i).
- * kernels DEV [nz][K]; theta DEV [nz] or NULL (exact mode writes 1).
+ * mode TIDAS_MODE_LATERAL (the separable 2-D extension; a 2-D model is future
+ *   work in the conclusion, Sec. 4): the lateral profile through the scatterer
+ *   of the same unit echo, normalised at the scatterer,
+ *     kernels[i][m+h] = DAS(unit echo at (0, z_i)) at (m dx, z_i) / its value at (0, z_i)
+ *   (0 when that value is 0), for tidas_apply_lateral.
+ * kernels DEV [nz][K]; theta DEV [nz] or NULL (exact and lateral modes write 1).
  * ref_row HOST [nz] with 0 <= ref_row[i] < nz, or NULL.  K odd, >= 1.
  * Paper and line modes allocate and free a small temporary device buffer,
  * stream-ordered (TIDAS_ENOMEM possible), uploads the row -> reference map,
@@ -211,6 +217,18 @@ int32_t tidas_apply_ex(const float* kernels, int32_t K, const float* refl, int32
                        float alpha, float beta, const float* base, float* image, void* stream);
 int32_t tidas_adjoint_ex(const float* kernels, int32_t K, const float* image_bar, int32_t B, int32_t Z, int32_t X,
                          float alpha, float beta, const float* base, float* refl_bar, void* stream);
+
+/*
+ * Lateral pass of the separable 2-D extension: after the line model's depth
+ * pass, each depth row is convolved along the lateral axis with its own
+ * kernel (tidas_build_kernels, TIDAS_MODE_LATERAL):
+ *   out[b][i][j] = sum_{m=-h..h} kernels_x[i][m+h] * in[b][i][j-m],
+ * in taken as zero outside [0, X).  kernels_x DEV [Z][K], K odd, 1 <= K <= 1535;
+ * in, out DEV [B][Z][X], out must not alias an input.  With exact depth
+ * kernels the two passes reproduce DAS along an on-axis scatterer's own row.
+ */
+int32_t tidas_apply_lateral(const float* kernels_x, int32_t K, const float* in, int32_t B, int32_t Z, int32_t X,
+                            float* out, void* stream);
 
 /*
  * Gradient of the line model in its kernels.  The model (Sec. 2.4,

@@ -19,6 +19,7 @@ TIDAS_EUNSUPPORTED = -4
 MODE_EXACT = 0
 MODE_PAPER = 1
 MODE_LINE = 2
+MODE_LATERAL = 3
 LINE_FOUR_BLOCK, LINE_TWO_BLOCK, LINE_FP32_MATRIX, LINE_VECTOR = 1, 2, 3, 4
 
 
@@ -79,6 +80,7 @@ _SIGS = {
     "tidas_adjoint_prepared": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_deconvolve": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _I, _P, _P, _P]),
     "tidas_kernel_grad": (_I, [_I, _P, _P, _I, _I, _I, _P, _P]),
+    "tidas_apply_lateral": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
     "tidas_operator_norm_sq": (_I, [_P, _I, _I, _I, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "tidas_batch_workspace_bytes": (ctypes.c_size_t, [_I]),
     "das_beamform_batch": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), _I,

@@ -11,8 +11,8 @@ import torch
 
 from . import _lib
 
-__all__ = ["das_beamform", "tidas_beamform", "build_kernels", "apply", "adjoint", "kernel_grad", "simulate_rf",
-           "version"]
+__all__ = ["das_beamform", "tidas_beamform", "build_kernels", "apply", "adjoint", "apply_lateral", "kernel_grad",
+           "simulate_rf", "version"]
 
 
 def _stream():
@@ -100,7 +100,8 @@ def build_kernels(setup, grid=None, K=None, mode="exact", ref_row=None, n_sample
     lib = _lib.load()
     K = int(K if K is not None else setup.K)
     T = int(n_samples if n_samples is not None else setup.n_samples)
-    m = {"exact": _lib.MODE_EXACT, "paper": _lib.MODE_PAPER, "line": _lib.MODE_LINE}[mode]
+    m = {"exact": _lib.MODE_EXACT, "paper": _lib.MODE_PAPER, "line": _lib.MODE_LINE,
+         "lateral": _lib.MODE_LATERAL}[mode]
     dev = torch.device("cuda", torch.cuda.current_device())
     kb = torch.empty((grid.nz, K), device=dev, dtype=torch.float32)
     th = torch.empty(grid.nz, device=dev, dtype=torch.float32) if with_theta else None
@@ -207,6 +208,14 @@ def apply(kernels, refl, out=None):
 def adjoint(kernels, image_bar, out=None):
     """Transpose of ``apply``."""
     return _conv("tidas_adjoint", kernels, image_bar, out)
+
+
+def apply_lateral(kernels_x, x, out=None):
+    """Lateral pass of the separable 2-D model: each row of x ([B][Z][X] or
+    [Z][X]) convolved along X with its kernel kernels_x [Z][K]."""
+    if isinstance(kernels_x, Prepared):
+        raise TypeError("the lateral pass takes a kernel bank, not a prepared line-model bank")
+    return _conv("tidas_apply_lateral", kernels_x, x, out)
 
 
 def kernel_grad(refl, image_bar, K, out=None):

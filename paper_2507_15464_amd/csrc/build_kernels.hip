@@ -7,6 +7,11 @@
 // analytically where DAS reads it: RF1[a][n][k] = p(t0 + k/fs - tau_n) for
 // 0 <= k < T, zero outside the record.
 //
+// Lateral mode (the separable 2-D extension; the conclusion, Sec. 4, leaves a
+// 2-D model for future work): Kx[i][m+h] = DAS, at pixel (m dx, z_i), of the
+// same unit echo, divided by its value at (0, z_i): the lateral profile of row
+// i's PSF through the scatterer, for tidas_apply_lateral.
+//
 // Paper mode (Sec. 2.3 eqn:tDAS / eqn:theta; Sec. 3.1-3.2): receive delays and
 // apodization frozen at a reference depth z_r; the kernel is the fixed-delay
 // response h_r scaled by the least-squares weight theta_i fitted inside a
@@ -65,15 +70,15 @@ __device__ __forceinline__ double arrival(const Setup64& s, int a, double x, dou
     return (x * s.sin_a[a] + z * s.cos_a[a]) / s.c + sqrt(dx * dx + z * z) / s.c;
 }
 
-// DAS at pixel (0, z) of a unit scatterer at (0, zs).
-__device__ double unit_das(const Setup64& s, double z, double zs) {
+// DAS at pixel (x, z) of a unit scatterer at (0, zs).
+__device__ double unit_das(const Setup64& s, double x, double z, double zs) {
     double acc = 0.0;
     for (int a = 0; a < s.A; ++a) {
         for (int n = 0; n < s.C; ++n) {
             const double xn = s.x_first + (double)n * s.pitch;
-            const double w = hann_d(-xn, z, s.fnumber);
+            const double w = hann_d(x - xn, z, s.fnumber);
             if (w == 0.0) continue;
-            const double u = (arrival(s, a, 0.0, z, xn) - s.t0) * s.fs;
+            const double u = (arrival(s, a, x, z, xn) - s.t0) * s.fs;
             acc += w * unit_echo_read(s, u, arrival(s, a, 0.0, zs, xn));
         }
     }
@@ -106,7 +111,23 @@ __global__ __launch_bounds__(256) void exact_kernel(const Setup64 s, int32_t Z, 
     const int t = (int)(idx % K);
     const int h = (K - 1) / 2;
     const double zi = z0 + (double)i * dz;
-    kb[idx] = (float)unit_das(s, zi + (double)(t - h) * dz, zi);
+    kb[idx] = (float)unit_das(s, 0.0, zi + (double)(t - h) * dz, zi);
+    if (theta && t == 0) theta[i] = 1.0f;
+}
+
+// ---------------------------------------------------------- lateral mode ----
+// Row i's lateral kernel: the DAS response of the unit scatterer at (0, z_i)
+// along its own row, divided by its value at the scatterer (0 if that is 0).
+__global__ __launch_bounds__(256) void lateral_kernel(const Setup64 s, int32_t Z, int32_t K, double z0, double dz,
+                                                      double dx, float* __restrict__ kb, float* __restrict__ theta) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)Z * K) return;
+    const int i = (int)(idx / K);
+    const int t = (int)(idx % K);
+    const int h = (K - 1) / 2;
+    const double zi = z0 + (double)i * dz;
+    const double centre = unit_das(s, 0.0, zi, zi);
+    kb[idx] = centre != 0.0 ? (float)(unit_das(s, (double)(t - h) * dx, zi, zi) / centre) : 0.0f;
     if (theta && t == 0) theta[i] = 1.0f;
 }
 
@@ -153,7 +174,7 @@ __global__ __launch_bounds__(PAPER_THREADS) void paper_ref_kernel(const Setup64 
 
     for (int t = threadIdx.x; t < K; t += PAPER_THREADS)
         h_ref[(size_t)u * K + t] = fixed_delay(s, zr + (double)(t - h) * dz, zr, zr);
-    for (int q = threadIdx.x; q < L; q += PAPER_THREADS) b[q] = unit_das(s, zr + (double)(q - Qf) * dzf, zr);
+    for (int q = threadIdx.x; q < L; q += PAPER_THREADS) b[q] = unit_das(s, 0.0, zr + (double)(q - Qf) * dzf, zr);
     __syncthreads();
     // DFT of the zero-padded sequence at k = 0 .. N/2 (the analytic signal
     // keeps only those bins: weight 1 at 0 and N/2, 2 in between)
@@ -219,7 +240,7 @@ __global__ __launch_bounds__(PAPER_THREADS) void paper_row_kernel(const Setup64 
     for (int q = -qmax + (int)threadIdx.x; q <= qmax; q += PAPER_THREADS) {
         const double z = zi + (double)q * dzf;
         const double a = fixed_delay(s, z, zr, zi);
-        const double bb = unit_das(s, z, zi);
+        const double bb = unit_das(s, 0.0, z, zi);
         ab += a * bb;
         aa += a * a;
     }
@@ -353,8 +374,8 @@ extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx*
     if (!kernels) return fail(TIDAS_EINVAL, "tidas_build_kernels: null kernels pointer");
     if (n_samples < 2) return fail(TIDAS_EINVAL, "tidas_build_kernels: n_samples must be >= 2");
     if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_build_kernels: K must be odd and >= 1");
-    if (mode != TIDAS_MODE_EXACT && mode != TIDAS_MODE_PAPER && mode != TIDAS_MODE_LINE)
-        return fail(TIDAS_EINVAL, "tidas_build_kernels: mode must be 0 (exact), 1 (paper) or 2 (line)");
+    if (mode != TIDAS_MODE_EXACT && mode != TIDAS_MODE_PAPER && mode != TIDAS_MODE_LINE && mode != TIDAS_MODE_LATERAL)
+        return fail(TIDAS_EINVAL, "tidas_build_kernels: mode must be 0 (exact), 1 (paper), 2 (line) or 3 (lateral)");
     if ((void*)kernels == (void*)theta) return fail(TIDAS_EINVAL, "tidas_build_kernels: theta aliases kernels");
     const int Z = grid->nz;
     if (ref_row)
@@ -370,6 +391,12 @@ extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx*
         hipLaunchKernelGGL(exact_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, s, Z, K, grid->z0,
                            grid->dz, kernels, theta);
         return check_launch("tidas_build_kernels(exact)");
+    }
+    if (mode == TIDAS_MODE_LATERAL) {
+        const int64_t n = (int64_t)Z * K;
+        hipLaunchKernelGGL(lateral_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, s, Z, K, grid->z0,
+                           grid->dz, grid->dx, kernels, theta);
+        return check_launch("tidas_build_kernels(lateral)");
     }
 
     // paper and line modes: distinct reference rows and the row -> reference map

@@ -56,6 +56,17 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
 NUL = ctypes.c_void_p(0)
 
 
+def test_lateral_pass_rejects_invalid_arguments(lib):
+    out = ctypes.c_void_p(0x2000)
+    f = lib.tidas_apply_lateral
+    assert f(NUL, 33, FAKE, 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL            # null kernels
+    assert f(FAKE, 32, ctypes.c_void_p(0x3000), 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL  # even K
+    assert f(FAKE, 33, ctypes.c_void_p(0x3000), 0, 16, 16, out, NUL) == _lib.TIDAS_EINVAL  # B = 0
+    assert f(FAKE, 33, ctypes.c_void_p(0x3000), 1, 16, 16, ctypes.c_void_p(0x3000), NUL) == _lib.TIDAS_EINVAL
+    assert f(FAKE, 1537, ctypes.c_void_p(0x3000), 1, 16, 16, out, NUL) == _lib.TIDAS_EUNSUPPORTED
+    assert lib.tidas_last_error()
+
+
 @pytest.mark.parametrize("args", [
     (NUL, 65, FAKE, 1, 16, 16, FAKE),       # null kernels
     (FAKE, 64, FAKE, 1, 16, 16, ctypes.c_void_p(0x2000)),  # even K
