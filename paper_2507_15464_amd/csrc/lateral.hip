@@ -23,7 +23,7 @@ namespace {
 constexpr int LAT_SEG = 256;  // columns per wave
 constexpr int LAT_PER_LANE = 4;
 constexpr int LAT_STAGE = 8;  // staging loads per lane issued together (segments of up to 512 samples)
-constexpr int LAT_WAVES = 1;  // waves per workgroup (measured: 4 independent waves per group ran 1.2-1.4x slower)
+constexpr int LAT_WAVES = 1;  // waves per workgroup (4 independent waves per group measured 1.2-1.4x slower)
 
 // LDS floats of one wave's segment (and taps), a multiple of 4
 __host__ __device__ constexpr int lat_wave_floats(int K, bool taps_in_lds) {
