@@ -223,6 +223,9 @@ def run_main(args):
     if args.only is None:
         res["tidas_unprepared"] = timed(run_tidas_unprepared)
         log(f"tidas (bank converted in the call): {res['tidas_unprepared'][0]:.4f} ms/step")
+        # the adjoint (transpose) over the same frames, prepared bank
+        res["adjoint"] = timed(lambda: td.adjoint(prep, R, out=Y))
+        log(f"adjoint: {res['adjoint'][0]:.4f} ms/step")
     if args.only in (None, "das"):
         res["das"] = timed(run_das)
         log(f"das: {res['das'][0]:.4f} ms/step ({B} frames)")
@@ -282,6 +285,8 @@ def run_main(args):
                 "ms_per_step": das_ms},
         "tidas_speedup_vs_das": das_ms / tid_ms,
         "kernel_build_s": build_s,
+        "adjoint": ({"ms_per_step": res["adjoint"][0], "frames_per_s": B / (res["adjoint"][0] * 1e-3),
+                     "achieved_gbs": hbm_bytes / (res["adjoint"][0] * 1e-3) / 1e9} if "adjoint" in res else None),
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(B),
                      "kernel": kernel, "bytes_per_launch": hbm_bytes,
@@ -311,6 +316,17 @@ def run_main(args):
     d_snap = td.das_beamform(rf_snap, s)
     y_snap = td.apply(kb, R[0])
     out["approx_rel_l2_2d"] = float(torch.linalg.norm(y_snap - d_snap) / torch.linalg.norm(d_snap))
+    # kernel-bank builds (once per geometry): exact mode, and paper mode with one
+    # receive law per 64 rows
+    t_b = time.perf_counter()
+    td.build_kernels(s, mode="exact")
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t_b
+    refs64 = [min((i // 64) * 64 + 32, Z - 1) for i in range(Z)]
+    t_b = time.perf_counter()
+    td.build_kernels(s, mode="paper", ref_row=refs64, with_theta=True)
+    torch.cuda.synchronize()
+    out["kernel_build_times_s"] = {"exact": t_exact, "paper_one_law_per_64_rows": time.perf_counter() - t_b}
     # the paper-style 1-D error on the centre line (single scatterers at every row, exact kernels)
     e1d = line_errors(s, K, dev)["exact"]
     out["approx_1d"] = {"single_local_sq_median": e1d["single_local_sq_median"],
