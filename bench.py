@@ -707,9 +707,15 @@ def run_kgrad(args):
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (N(0,1) reflectivity maps and output gradients, seeded)",
         "config": {"workload": f"{B} frames of 1024 x 256 px, 129 taps (kernel gradient)", "global_batch": B},
+        # the arithmetic is float32-exact (split-bfloat16 parts, float32 sums):
+        # priced against the float32 matrix peak; the issued bf16 work (six
+        # products per term, 160 source rows for 129 taps) beside it
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / FP32_MFMA_TFLOPS, "traffic": None, "flops_per_launch": flops,
-                     "kernel": "kgrad_kernel + kgrad_reduce_kernel (whole call)"},
+                     "kernel": "kgrad_bf16_kernel + kgrad_reduce_kernel (whole call)",
+                     "mfma_bf16_tflops_issued": 6.0 * flops * (32 * ((K + 62) // 32)) / K / (ms * 1e-3) / 1e12,
+                     "mfma_bf16_frac": 6.0 * flops * (32 * ((K + 62) // 32)) / K / (ms * 1e-3) / 1e12
+                     / BF16_MFMA_TFLOPS},
     }
     if not args.no_parity:
         # sampled entries against FP64 dot products over all frames and columns

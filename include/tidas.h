@@ -238,8 +238,10 @@ int32_t tidas_apply_lateral(const float* kernels_x, int32_t K, const float* in, 
  * refl taken as zero outside [0, Z) (those taps get 0).  refl, image_bar DEV
  * [B][Z][X]; kernels_bar DEV [Z][K], overwritten, must not alias an input.
  * K odd >= 1; B, Z, X >= 1; EUNSUPPORTED when (Z + 2 K + 512) X 4 bytes
- * reach 2^31.  Float32 products on the matrix cores, partial sums over fixed
- * ranges of (frame, column) added in double in a fixed order (bit-
+ * reach 2^31.  Matrix-core products: split-bfloat16 (each value cut exactly
+ * into three bfloat16 parts, six products, float32 sums) when X % 4 == 0 and
+ * both inputs are 16-byte aligned, float32 otherwise; partial sums over
+ * fixed ranges of (frame, column) added in double in a fixed order (bit-
  * reproducible on one device type); a stream-ordered temporary buffer holds
  * the partial sums (about 2 x compute units x 128 Z K / ceil(Z / 128) bytes).
  */
