@@ -21,7 +21,7 @@ scatterer of amplitude 1 before its FP32 rounding.
   depth axis of spacing dzf = c / (2 fs) (one sample of two-way time)
   a_i = F_r[RF1 at z_i] and b_i = DAS(RF1 at z_i) along x = 0; the window B_i
   is centred on z_i and as wide as the FWHM W_r of the envelope of b_r
-  (Sec. 3.1: the FWHM of the PSF at the focal point); the weight is the least
+  (Sec. 3.1-3.2: the width of the reference PSF at half its maximum); the weight is the least
   squares solution of the first line of eqn:theta,
   theta_i = sum_B a_i b_i / sum_B a_i^2 (its time-domain form, Plancherel);
   finally K[i] = theta_i * h_{r(i)}.

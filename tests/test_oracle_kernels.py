@@ -271,3 +271,68 @@ def test_separable_model_reproduces_das_along_the_scatterers_row():
     assert abs(Y1[i0, j0] - D[i0, j0]) <= 1e-12 * scale
     # elsewhere it is an approximation, and a better one than the depth pass alone
     assert np.linalg.norm(Y2 - D) < 0.5 * np.linalg.norm(Y1 - D)
+
+
+def hand_theta_setup():
+    """Two elements at x = +-300 l (l = c / fs, fs = 200 MHz so that linear
+    interpolation is nearly exact), reference depth z_r = 400 l with receive
+    distance 500 l (a Pythagorean triple), scatterer at z_i = 430 l, F/0.05
+    (a nearly flat Hann aperture)."""
+    s = C1.replace(n_elem=2, n_samples=6000, fnumber=0.05, fs=200e6)
+    ell = s.c / s.fs
+    return s.replace(pitch=600 * ell), ell
+
+
+def hand_theta(s, ell, z_r, z_i, centre, half):
+    """eqn:theta (first line, time domain) on the explicitly listed window
+    {centre + q dzf : |q dzf| <= half}, dzf = l / 2, with a_i and b_i written
+    out by hand:
+      a_i(z) = sum_n w(x_n, z_r) p((2z - z_r + rho_n(z_r) - z_i - rho_n(z_i)) / c)
+    (the fixed-delay read index (2z - z_r + rho_n(z_r)) / l is an integer on
+    this axis, so the read is the echo sample itself), and b_i(z) the DAS
+    value at (0, z): per element numpy.interp of the sampled unit echo at
+    (z + rho_n(z)) / l, weighted by the Hann weight of depth z."""
+    import math
+    dzf = ell / 2
+    qmax = math.floor(half / dzf)
+    z = centre + np.arange(-qmax, qmax + 1) * dzf
+    k = np.arange(s.n_samples)
+    a = np.zeros_like(z)
+    b = np.zeros_like(z)
+    for xn in (-0.5 * s.pitch, 0.5 * s.pitch):
+        r_r, r_i = math.hypot(xn, z_r), math.hypot(xn, z_i)
+        w_r = 0.5 * (1 + math.cos(math.pi * abs(xn) / (z_r / (2 * s.fnumber))))
+        a += w_r * pulse.pulse((2 * z - z_r + r_r - z_i - r_i) / s.c, s.fc, s.sigma)
+        w_z = 0.5 * (1 + np.cos(np.pi * abs(xn) / (z / (2 * s.fnumber))))
+        echo = pulse.pulse(k / s.fs - (z_i + r_i) / s.c, s.fc, s.sigma)
+        b += w_z * np.interp((z + np.hypot(xn, z)) / ell, k, echo)
+    return float(np.dot(a, b) / np.dot(a, a))
+
+
+def test_paper_theta_window_centre_and_width_by_hand():
+    """The weight window B (Sec. 2.3 eqn:tDAS, eqn:theta; Sec. 3.1-3.2: its
+    width is the FWHM of the reference depth's PSF) is centred on the
+    scatterer's own depth z_i and is W_r wide.  W_r is pinned to the closed
+    form: the envelope FWHM of the pulse in time (cycles / fc) mapped to depth
+    by the two-way travel time's slope d(z + rho)/dz / c = (1 + z_r / rho_r) / c.
+    theta_i is then recomputed by hand on that window; a window centred on
+    z_r, or twice as wide, gives a different weight."""
+    import math
+    s, ell = hand_theta_setup()
+    z_r, z_i = 400 * ell, 430 * ell
+    kb, th, W = kernels.paper_kernels(np.array([z_r, z_i]), ell, 5, ref_rows=np.array([0, 0]), **oracle_kw(s))
+    w_closed = (s.cycles / s.fc) * s.c / (1 + 400 / 500)
+    assert np.all(np.abs(W - w_closed) < 5e-3 * w_closed)
+    # the FWHM is the reference depth's: the scatterer depth's slope differs by 1.1 %
+    w_at_zi = (s.cycles / s.fc) * s.c / (1 + z_i / math.hypot(0.5 * s.pitch, z_i))
+    assert abs(W[1] - w_closed) < 0.3 * abs(w_at_zi - w_closed)
+    # the closed-form and the measured width select the same discrete window
+    assert math.floor(W[1] / ell) == math.floor(w_closed / ell)
+    t_hand = hand_theta(s, ell, z_r, z_i, z_i, 0.5 * w_closed)
+    assert abs(th[1] - t_hand) <= 1e-12 * abs(t_hand)
+    assert abs(th[0] - hand_theta(s, ell, z_r, z_r, z_r, 0.5 * w_closed)) <= 1e-12
+    # centre and width both matter at this tolerance
+    assert abs(hand_theta(s, ell, z_r, z_i, z_r, 0.5 * w_closed) - t_hand) > 1e-3
+    assert abs(hand_theta(s, ell, z_r, z_i, z_i, w_closed) - t_hand) > 1e-3
+    # the kernel row is theta_i times the reference response h_r
+    assert np.max(np.abs(kb[1] - th[1] / th[0] * kb[0])) <= 1e-13 * np.max(np.abs(kb[1]))
