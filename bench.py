@@ -707,7 +707,8 @@ def run_kgrad(args):
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (N(0,1) reflectivity maps and output gradients, seeded)",
         "config": {"workload": f"{B} frames of 1024 x 256 px, 129 taps (kernel gradient)", "global_batch": B},
-        # the arithmetic is float32-exact (split-bfloat16 parts, float32 sums):
+        # the arithmetic is float32-level (split-bfloat16 parts, float32 sums, the
+        # dropped cross terms below 2^-20 |ab|):
         # priced against the float32 matrix peak; the issued bf16 work (six
         # products per term, 160 source rows for 129 taps) beside it
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_TFLOPS, "unit": "TFLOP/s",

@@ -244,9 +244,22 @@ int32_t tidas_apply_lateral(const float* kernels_x, int32_t K, const float* in, 
  * fixed ranges of (frame, column) added in double in a fixed order (bit-
  * reproducible on one device type); a stream-ordered temporary buffer holds
  * the partial sums (about 2 x compute units x 128 Z K / ceil(Z / 128) bytes).
+ * Non-finite inputs: the float32 kernel propagates Inf and NaN as float32
+ * arithmetic does; on the split-bfloat16 path an infinite input gives NaN
+ * (its parts are Inf - Inf).
  */
 int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* image_bar, int32_t B, int32_t Z, int32_t X,
                           float* kernels_bar, void* stream);
+
+/*
+ * Which kernel tidas_kernel_grad runs for X columns and the two input
+ * pointers (a diagnostic, enqueues nothing, pointers are not dereferenced):
+ * TIDAS_KGRAD_SPLIT_BF16 when X % 4 == 0 and both pointers are 16-byte
+ * aligned, TIDAS_KGRAD_FP32 otherwise; TIDAS_EINVAL for X < 1.
+ */
+#define TIDAS_KGRAD_SPLIT_BF16 1
+#define TIDAS_KGRAD_FP32 2
+int32_t tidas_kernel_grad_kernel(int32_t X, const void* refl, const void* image_bar);
 
 /*
  * Which line-model kernel tidas_apply / tidas_adjoint (and their fused and

@@ -21,6 +21,7 @@ MODE_PAPER = 1
 MODE_LINE = 2
 MODE_LATERAL = 3
 LINE_FOUR_BLOCK, LINE_TWO_BLOCK, LINE_FP32_MATRIX, LINE_VECTOR = 1, 2, 3, 4
+KGRAD_SPLIT_BF16, KGRAD_FP32 = 1, 2
 
 
 class TidasError(RuntimeError):
@@ -80,6 +81,7 @@ _SIGS = {
     "tidas_adjoint_prepared": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_deconvolve": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _I, _P, _P, _P]),
     "tidas_kernel_grad": (_I, [_I, _P, _P, _I, _I, _I, _P, _P]),
+    "tidas_kernel_grad_kernel": (_I, [_I, _P, _P]),
     "tidas_apply_lateral": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
     "tidas_operator_norm_sq": (_I, [_P, _I, _I, _I, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "tidas_batch_workspace_bytes": (ctypes.c_size_t, [_I]),

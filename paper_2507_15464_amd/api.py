@@ -11,7 +11,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["das_beamform", "tidas_beamform", "build_kernels", "apply", "adjoint", "apply_lateral", "kernel_grad",
+__all__ = ["das_beamform", "tidas_beamform", "build_kernels", "apply", "adjoint", "apply_lateral", "kernel_grad", "kernel_grad_kernel",
            "simulate_rf", "version"]
 
 
@@ -142,6 +142,14 @@ def line_kernel(K, B, Z, X):
     """Which line-model kernel a launch of B frames of Z x X with K taps runs
     (``_lib.LINE_FOUR_BLOCK`` … ``_lib.LINE_VECTOR``)."""
     r = _lib.load().tidas_line_kernel(int(K), int(B), int(Z), int(X))
+    _lib.check(r if r < 0 else 0)
+    return r
+
+
+def kernel_grad_kernel(refl, image_bar):
+    """Which kernel ``kernel_grad`` runs for these inputs
+    (``_lib.KGRAD_SPLIT_BF16`` or ``_lib.KGRAD_FP32``)."""
+    r = _lib.load().tidas_kernel_grad_kernel(int(refl.shape[-1]), _ptr(refl), _ptr(image_bar))
     _lib.check(r if r < 0 else 0)
     return r
 

@@ -401,6 +401,15 @@ static KgGeom kgrad_geometry(int32_t K, int32_t B, int32_t Z, int32_t X, int chu
 
 using namespace tidas;
 
+static bool kgrad_split_path(int32_t X, const void* refl, const void* image_bar) {
+    return (X % 4) == 0 && ((uintptr_t)refl % 16) == 0 && ((uintptr_t)image_bar % 16) == 0;
+}
+
+extern "C" int32_t tidas_kernel_grad_kernel(int32_t X, const void* refl, const void* image_bar) {
+    if (X < 1) return fail(TIDAS_EINVAL, "tidas_kernel_grad_kernel: X must be >= 1");
+    return kgrad_split_path(X, refl, image_bar) ? TIDAS_KGRAD_SPLIT_BF16 : TIDAS_KGRAD_FP32;
+}
+
 extern "C" int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* image_bar, int32_t B, int32_t Z,
                                      int32_t X, float* kernels_bar, void* stream) {
     if (!refl || !image_bar || !kernels_bar) return fail(TIDAS_EINVAL, "tidas_kernel_grad: null pointer");
@@ -412,7 +421,7 @@ extern "C" int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* 
     if (((int64_t)Z + 2 * (int64_t)K + 512) * X * 4 >= INT32_MAX)
         return fail(TIDAS_EUNSUPPORTED, "tidas_kernel_grad: frame too large for 32-bit offsets");
     int nt = 1;
-    const bool vec = (X % 4) == 0 && ((uintptr_t)refl % 16) == 0 && ((uintptr_t)image_bar % 16) == 0;
+    const bool vec = kgrad_split_path(X, refl, image_bar);
     const KgGeom g = kgrad_geometry(K, B, Z, X, vec ? KB_CW : KG_CW, &nt);
     if ((int64_t)g.n_rt * g.n_pass * g.n_split > INT32_MAX)
         return fail(TIDAS_EUNSUPPORTED, "tidas_kernel_grad: grid too large");

@@ -220,6 +220,15 @@ def test_kernel_grad_rejects_invalid_arguments(lib):
     assert lib.tidas_last_error()
 
 
+def test_kernel_grad_path_choice(lib):
+    k = lib.tidas_kernel_grad_kernel
+    assert k(16, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)) == _lib.KGRAD_SPLIT_BF16
+    assert k(16, ctypes.c_void_p(0x1004), ctypes.c_void_p(0x2000)) == _lib.KGRAD_FP32   # refl not 16-byte aligned
+    assert k(16, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2008)) == _lib.KGRAD_FP32   # image_bar not aligned
+    assert k(18, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)) == _lib.KGRAD_FP32   # X % 4 != 0
+    assert k(0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)) == _lib.TIDAS_EINVAL
+
+
 def test_line_kernel_rejects_invalid_sizes(lib):
     assert lib.tidas_line_kernel(64, 1, 64, 64) == _lib.TIDAS_EINVAL   # even K
     assert lib.tidas_line_kernel(0, 1, 64, 64) == _lib.TIDAS_EINVAL

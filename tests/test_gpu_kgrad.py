@@ -38,7 +38,10 @@ def g(x, dev):
 # 257), taps reaching past the image (K > 2 Z - 1), many frames
 KGRAD_SHAPES = [(1, 1, 1, 1), (1, 1, 5, 3), (1, 40, 7, 5), (2, 130, 33, 65), (3, 257, 65, 129),
                 (2, 300, 50, 161), (1, 200, 40, 193), (1, 150, 9, 257), (1, 64, 3, 321), (4, 128, 256, 129),
-                (17, 96, 31, 33)]
+                (17, 96, 31, 33),
+                # X % 4 == 0 (the split-bfloat16 kernel): one band tile (K = 1), the largest
+                # band rows of one pass (K = 161, six tiles), taps past the image (K > 2 Z - 1)
+                (1, 64, 8, 161), (1, 40, 4, 1), (1, 32, 12, 129)]
 
 
 @pytest.mark.parametrize("B,Z,X,K", KGRAD_SHAPES)
@@ -55,6 +58,29 @@ def test_kernel_grad_matches_oracle(dev, B, Z, X, K):
         for m in range(-h, h + 1):
             if not 0 <= i - m < Z:
                 assert G[i, m + h] == 0.0
+
+
+def test_kernel_grad_path_choice_and_float32_fallback(dev):
+    """Frames readable 16 bytes at a time run the split-bfloat16 kernel; a view
+    one float into its storage (rows not 16-byte aligned) runs the float32
+    kernel, and both agree with the oracle."""
+    B, Z, X, K = 2, 96, 32, 65
+    R = generators.normal((B, Z, X), seed=60).astype(np.float32)
+    Yb = generators.normal((B, Z, X), seed=61).astype(np.float32)
+    ref = o_t.kernel_grad(R, Yb, K)
+    Rd, Yd = g(R, dev), g(Yb, dev)
+    assert td.kernel_grad_kernel(Rd, Yd) == td._lib.KGRAD_SPLIT_BF16
+    G_split = td.kernel_grad(Rd, Yd, K).cpu().numpy()
+    assert rel(G_split, ref) <= RTOL
+    flat = torch.zeros(B * Z * X + 1, device=dev, dtype=torch.float32)
+    Ro = flat[1:].view(B, Z, X)
+    Ro.copy_(Rd)
+    assert Ro.data_ptr() % 16 != 0
+    assert td.kernel_grad_kernel(Ro, Yd) == td._lib.KGRAD_FP32
+    G_f32 = td.kernel_grad(Ro, Yd, K).cpu().numpy()
+    assert rel(G_f32, ref) <= RTOL
+    # X not a multiple of 4 also takes the float32 kernel
+    assert td.kernel_grad_kernel(Rd[..., :30].contiguous(), Yd[..., :30].contiguous()) == td._lib.KGRAD_FP32
 
 
 def test_kernel_grad_two_dimensional_input(dev):
