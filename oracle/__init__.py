@@ -22,6 +22,10 @@ Every function is a direct, slow, readable transcription of a definition:
 * ``mlp``       the kernel-surrogate MLP in FP64 and with BF16 rounding
                 emulated at the GPU's rounding points.
 * ``metrics``   relative errors and the paper's local / global error.
+* ``point_study`` the paper's single-point study (Sec. 3.1-3.3): focused
+                transmit with a Kossoff aperture, the Theta matrix and the
+                local / global error maps of every (delay curve, scatterer)
+                pair, and the DAS / tiDAS peak and FWHM along the line.
 
 All arithmetic is float64 (numpy).  Nothing is blocked, fused or reordered
 beyond what the definitions state.
