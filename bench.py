@@ -35,6 +35,11 @@ Other workloads (one JSON line each, not the headline):
                         2-D error against DAS with and without the lateral pass
     --workload kgrad    gradient of the line model in its kernels (tidas_kernel_grad)
                         over B frames of 1024 x 256 with 129 taps
+    --workload study    the paper's single-point study (tidas_point_study): 600 points
+                        from 2 to 42 mm, focused transmit with a Kossoff aperture at
+                        15 / 25 / 35 mm, 3-9 MHz; Theta matrix and local / global error
+                        maps of all 360k (delay curve, scatterer) pairs per setting,
+                        DAS / tiDAS peak ratios and FWHM differences
     --workload surrogate  train the BF16-MFMA kernel surrogate on 200k exact
                         kernels (depth, F# 1-3, angle +-15 deg, fc 3-10 MHz), then
                         surrogate-kernel vs exact-kernel line model on 512 x 2048
@@ -63,7 +68,7 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["main", "batch", "deconv", "beamform", "separable", "kgrad", "surrogate",
-                                           "approx"],
+                                           "approx", "study"],
                     default="main")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate workload: Adam steps")
     ap.add_argument("--train-rows", type=int, default=200_000, help="surrogate workload: training kernels")
@@ -116,7 +121,7 @@ def main():
     {"main": run_main, "batch": run_batch, "deconv": run_deconv, "beamform": run_beamform,
      "separable": run_separable, "kgrad": run_kgrad,
      "surrogate": run_surrogate,
-     "approx": run_approx}[args.workload](args)
+     "approx": run_approx, "study": run_study}[args.workload](args)
 
 
 def _oracle_apply_frames(task):
@@ -938,6 +943,82 @@ def run_approx(args):
            "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
            "data": "synthetic on-axis scatterers", "config": {"workload": "configs 1 and 2 geometry, x = 0 column"},
            "errors": res, "paper_threshold": 0.05}
+    print(json.dumps(out), flush=True)
+
+
+def run_study(args):
+    """The single-point study for every (centre frequency, focal depth) of the
+    workload; sampled pairs of one setting against the oracle."""
+    import numpy as np
+    import torch
+
+    import paper_2507_15464_amd as td
+    from workloads.configs import STUDY, study_focal_index, study_line_half, study_setup
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    settings = []
+    parity = None
+    cpu = None
+    for fc in STUDY["fcs"]:
+        s = study_setup(fc)
+        P = s.nz
+        Ql = study_line_half(s)
+        Qh = min(511, 4 * int(np.ceil(8 * s.sigma * s.fs)))
+        for zf in STUDY["foci"]:
+            f = study_focal_index(s, zf)
+            n_tx = td.kossoff_tx_count(s, s.z0 + f * s.dz, STUDY["kossoff"])
+            run = lambda: td.point_study(s, n_tx, P, s.z0, s.dz, f, Ql, stats_half=Qh)  # noqa: E731
+            ms = _events_ms(run, 1, 1)
+            out = run()
+            torch.cuda.synchronize()
+            th = out["theta"].cpu().numpy()
+            lo = out["err_local"].cpu().numpy()
+            gl = out["err_global"].cpu().numpy()
+            st = out["stats"].cpu().numpy()
+            d_fwhm = np.abs(st[:, 3] - st[:, 2])
+            q = lambda v: [float(x) for x in np.percentile(v, [25, 50, 75])]  # noqa: E731
+            rec = {"fc_mhz": fc / 1e6, "focus_mm": (s.z0 + f * s.dz) * 1e3, "focal_index": f, "n_tx": n_tx,
+                   "window_mm": out["window"].item() * 1e3, "ms": ms, "pairs_per_s": P * P / (ms * 1e-3),
+                   "local_below_5pct": float(np.mean(lo < 0.05)), "global_below_5pct": float(np.mean(gl < 0.05)),
+                   "curves_covering_all_points_local_5pct": int(np.sum(np.all(lo < 0.05, axis=1))),
+                   "focal_curve_local_below_5pct": float(np.mean(lo[f] < 0.05)),
+                   "theta_range": [float(th.min()), float(th.max())],
+                   "theta_diag_range": [float(np.diag(th).min()), float(np.diag(th).max())],
+                   "abs_dfwhm_um_quartiles": [1e6 * v for v in q(d_fwhm)],
+                   "peak_ratio_tidas_over_das_quartiles": q(st[:, 1] / st[:, 0]),
+                   "das_peak_over_focal_peak_range": [float((st[:, 0] / st[f, 0]).min()),
+                                                      float((st[:, 0] / st[f, 0]).max())]}
+            settings.append(rec)
+            log(f"study fc {fc / 1e6} MHz focus {rec['focus_mm']:.2f} mm: {ms:.1f} ms, "
+                f"local<5% {rec['local_below_5pct']:.3f}")
+            if parity is None and not args.no_parity:
+                from oracle import point_study as ps
+                o = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, fc=s.fc, sigma=s.sigma,
+                         n_samples=s.n_samples, fnumber=s.fnumber, n_tx=n_tx)
+                pts, refs = [0, f, P // 2, P - 1], [0, f, P - 1]
+                t0 = time.perf_counter()
+                tho, loo, glo, W, _ = ps.study(o, P, s.z0, s.dz, f, Ql, refs=refs, points=pts)
+                cpu_s = time.perf_counter() - t0
+                sub = np.ix_(refs, pts)
+                parity = {"pairs": len(refs) * len(pts), "setting": f"{fc / 1e6} MHz, focus {zf * 1e3:.0f} mm",
+                          "theta_max_rel": float(np.max(np.abs(th[sub] - tho) / np.abs(tho))),
+                          "err_local_max_abs": float(np.max(np.abs(lo[sub] - loo))),
+                          "err_global_max_abs": float(np.max(np.abs(gl[sub] - glo))),
+                          "window_rel": abs(out["window"].item() - W) / W}
+                if not args.no_cpu_baseline:
+                    # the oracle's time per pair (an echo per point, lines per pair)
+                    cpu = {"value": len(refs) * len(pts) / cpu_s, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                           "sample": f"{len(refs)} x {len(pts)} pairs of the {P}-point study"}
+    total_ms = sum(r["ms"] for r in settings)
+    pairs = len(settings) * STUDY["n_points"] ** 2
+    out = {"metric": "single-point study (Sec. 3.1-3.3): (delay curve, scatterer) pairs per second",
+           "value": pairs / (total_ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": total_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (unit scatterers on the probe axis)",
+           "config": {"workload": "192 elements, 0.3 mm pitch, 50 MHz, F/1, 600 points 2-42 mm, focused transmit "
+                                  "with a Kossoff aperture, 4 frequencies x 3 focal depths"},
+           "settings": settings, "parity": parity, "cpu_baseline": cpu, "paper_threshold": 0.05}
     print(json.dumps(out), flush=True)
 
 

@@ -452,6 +452,58 @@ int32_t tidas_sq_norms(const float* a, const float* b, int64_t n, double* work, 
 int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* tx, const double* scat,
                           int32_t n_scat, int32_t n_samples, float* rf, void* stream);
 
+/*
+ * The paper's single-point study (Sec. 3.1-3.3), float64 throughout.  An
+ * unsteered beam focused on the probe axis (Sec. 2.1) at the depth of point
+ * focal_index of the axial points z_s = z_first + s z_step (s < P =
+ * n_points, Sec. 3.1: one point is the transmit focus): the n_tx centremost
+ * elements fire at T_m = (z_f - sqrt(x_m^2 + z_f^2)) / c, unit weights (see
+ * tidas_kossoff_tx_count for the aperture of Sec. 3.1).  For a unit
+ * scatterer at every point s its echo, sampled on the record of n_samples
+ * samples (tx: fs, t0, fc, cycles; its angle list must be the single angle
+ * 0), is beamformed on the probe axis at the depths z_s + q dzf, dzf =
+ * c / (2 fs), |q| <= line_half: by DAS (transmit arrival z / c, dynamic
+ * receive law, Hann aperture of F-number rx->fnumber) giving b_s, and, for
+ * the delay curve of every point r, by the time-invariant line (receive
+ * delays D_n(z_r) of eqn:delay and the aperture of depth z_r for every
+ * depth, Sec. 2.3 eqn:tDAS) giving a_rs.  Outputs, DEV float64 [P][P] with
+ * entry [r][s]:
+ *   theta      = sum_B a b / sum_B a^2 (0 when sum_B a^2 = 0)  (eqn:theta, line 1)
+ *   err_local  = ||theta a - b||^2 over B / ||b||^2 over B    (Sec. 3.3, near the peak)
+ *   err_global = ||theta a - b||^2 / ||b||^2 over the line     (Sec. 3.3, whole signal)
+ * (errors 0 where ||b|| = 0), with the window B: |q| <= floor(W / (2 dzf)),
+ * W the FWHM of the envelope of the focal point's DAS line measured on
+ * |q| <= ceil(8 sigma fs) (Sec. 3.1-3.2); window DEV double [1] receives W in
+ * metres (or NULL).  stats DEV float64 [P][4] (or NULL): per point s the
+ * envelope peak of b_s, that of theta[focal][s] a_{focal,s}, and the two
+ * envelopes' FWHMs in metres, all on |q| <= stats_half <= 511 (Sec. 3.2).
+ * workspace DEV of at least tidas_point_study_workspace_bytes(C, P,
+ * n_samples, line_half) bytes (echoes [P][C][n_samples] float64, their
+ * supports, the DAS lines).  EINVAL: invalid descriptors, a steered or
+ * multi-angle tx, n_tx outside [1, C] or with C - n_tx odd, n_samples < 2,
+ * P < 1, z_first <= 0, z_step <= 0 when P > 1, focal_index outside [0, P),
+ * line_half < 0, stats_half outside [0, 511] with stats, null or overlapping
+ * outputs, a null or short workspace.  EUNSUPPORTED: C > 512, P > 65535, or
+ * a pulse longer than the 1023-sample FWHM axis.
+ */
+size_t tidas_point_study_workspace_bytes(int32_t n_elem, int32_t n_points, int32_t n_samples, int32_t line_half);
+int32_t tidas_point_study(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx, int32_t n_tx,
+                          int32_t n_samples, int32_t n_points, double z_first, double z_step, int32_t focal_index,
+                          int32_t line_half, int32_t stats_half, double* theta, double* err_local,
+                          double* err_global, double* stats, double* window, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/*
+ * Transmit aperture of the single-point study (Sec. 3.1: Kossoff's
+ * criterion with parameter `ratio`, 0.6 in the paper), read as the width D
+ * whose near-field length D^2 / (4 lambda) puts the focus z_focus at `ratio`
+ * of it: D = sqrt(4 lambda z_focus / ratio), lambda = c / fc.  Returns the
+ * element count nearest D / pitch with the parity of n_elem (a set symmetric
+ * about the probe centre), clamped to [1 (odd n_elem) or 2, n_elem]; or
+ * TIDAS_EINVAL.  Host arithmetic only.
+ */
+int32_t tidas_kossoff_tx_count(const tidas_array* array, double fc, double z_focus, double ratio);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,11 @@ _SIGS = {
     "tidas_deconvolve": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _I, _P, _P, _P]),
     "tidas_kernel_grad": (_I, [_I, _P, _P, _I, _I, _I, _P, _P]),
     "tidas_kernel_grad_kernel": (_I, [_I, _P, _P]),
+    "tidas_point_study_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I, _I]),
+    "tidas_point_study": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), _I, _I, _I,
+                               ctypes.c_double, ctypes.c_double, _I, _I, _I, _P, _P, _P, _P, _P, _P,
+                               ctypes.c_size_t, _P]),
+    "tidas_kossoff_tx_count": (_I, [ctypes.POINTER(Array), ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "tidas_apply_lateral": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
     "tidas_operator_norm_sq": (_I, [_P, _I, _I, _I, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "tidas_batch_workspace_bytes": (ctypes.c_size_t, [_I]),

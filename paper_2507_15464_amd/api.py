@@ -11,7 +11,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["das_beamform", "tidas_beamform", "build_kernels", "apply", "adjoint", "apply_lateral", "kernel_grad", "kernel_grad_kernel",
+__all__ = ["das_beamform", "tidas_beamform", "build_kernels", "apply", "adjoint", "apply_lateral", "kernel_grad", "kernel_grad_kernel", "point_study", "kossoff_tx_count",
            "simulate_rf", "version"]
 
 
@@ -256,4 +256,39 @@ def simulate_rf(setup, scat, n_samples=None, out=None):
     arr, tx, _, _ = _descs(setup)
     _lib.check(lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), _ptr(scat), scat.shape[0], T, _ptr(out),
                                      _stream()))
+    return out
+
+
+def kossoff_tx_count(setup, z_focus, ratio=0.6):
+    """Transmit elements of the single-point study's focused beam (Kossoff's criterion)."""
+    arr = _lib.make_array(setup.n_elem, setup.pitch, setup.c)
+    r = _lib.load().tidas_kossoff_tx_count(ctypes.byref(arr), float(setup.fc), float(z_focus), float(ratio))
+    _lib.check(r if r < 0 else 0)
+    return r
+
+
+def point_study(setup, n_tx, n_points, z_first, z_step, focal_index, line_half, stats_half=None):
+    """The single-point study (``tidas_point_study``) on the current device.
+
+    ``setup`` needs n_elem, pitch, c, fs, t0, fc, cycles, fnumber, n_samples
+    and angles == (0.0,).  Returns a dict of float64 device tensors: theta,
+    err_local, err_global ([P][P], entry [r][s]), stats ([P][4] or None) and
+    window (W in metres, a 1-element tensor)."""
+    lib = _lib.load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    P = int(n_points)
+    nbytes = int(lib.tidas_point_study_workspace_bytes(int(setup.n_elem), P, int(setup.n_samples), int(line_half)))
+    if nbytes == 0:
+        raise ValueError("invalid study sizes")
+    ws = torch.empty(nbytes, device=dev, dtype=torch.uint8)
+    out = {k: torch.empty((P, P), device=dev, dtype=torch.float64) for k in ("theta", "err_local", "err_global")}
+    out["stats"] = torch.empty((P, 4), device=dev, dtype=torch.float64) if stats_half is not None else None
+    out["window"] = torch.empty(1, device=dev, dtype=torch.float64)
+    arr, tx, rx, _ = _descs(setup)
+    _lib.check(lib.tidas_point_study(ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), int(n_tx),
+                                     int(setup.n_samples), P, float(z_first), float(z_step), int(focal_index),
+                                     int(line_half), int(stats_half or 0), _ptr(out["theta"]),
+                                     _ptr(out["err_local"]), _ptr(out["err_global"]), _ptr(out["stats"]),
+                                     _ptr(out["window"]), _ptr(ws), nbytes, _stream()))
+    out["_workspace"] = ws  # kept alive until the caller synchronises
     return out

@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "envelope.hpp"
 
 namespace tidas {
 
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void lateral_kernel(const Setup64 s, int32_t Z
 
 // ------------------------------------------------------------ paper mode ----
 constexpr int PAPER_THREADS = 256;
-constexpr int FINE_MAX = 1024;  // max fine-axis length 2 Qf + 1 (DFT length <= 2 FINE_MAX)
+constexpr int FINE_MAX = ENV_MAX;  // max fine-axis length 2 Qf + 1 (DFT length <= 2 FINE_MAX)
 
 __device__ double block_sum(double v, double* red) {
     // wave reduction then LDS across the 4 waves
@@ -169,55 +170,13 @@ __global__ __launch_bounds__(PAPER_THREADS) void paper_ref_kernel(const Setup64 
     const int h = (K - 1) / 2;
     const double dzf = s.c / (2.0 * s.fs);
     const int L = 2 * Qf + 1;
-    int N = 1;
-    while (N < 2 * L) N *= 2;
 
     for (int t = threadIdx.x; t < K; t += PAPER_THREADS)
         h_ref[(size_t)u * K + t] = fixed_delay(s, zr + (double)(t - h) * dz, zr, zr);
     for (int q = threadIdx.x; q < L; q += PAPER_THREADS) b[q] = unit_das(s, 0.0, zr + (double)(q - Qf) * dzf, zr);
     __syncthreads();
-    // DFT of the zero-padded sequence at k = 0 .. N/2 (the analytic signal
-    // keeps only those bins: weight 1 at 0 and N/2, 2 in between)
-    for (int k = threadIdx.x; k <= N / 2; k += PAPER_THREADS) {
-        double re = 0.0, im = 0.0;
-        for (int n = 0; n < L; ++n) {
-            const int m = (int)(((int64_t)k * n) & (N - 1));
-            double sn, cs;
-            sincospi(2.0 * (double)m / (double)N, &sn, &cs);
-            re += b[n] * cs;
-            im -= b[n] * sn;
-        }
-        const double wgt = (k == 0 || k == N / 2) ? 1.0 : 2.0;
-        Xr[k] = wgt * re;
-        Xi[k] = wgt * im;
-    }
-    __syncthreads();
-    for (int n = threadIdx.x; n < L; n += PAPER_THREADS) {
-        double re = 0.0, im = 0.0;
-        for (int k = 0; k <= N / 2; ++k) {
-            const int m = (int)(((int64_t)k * n) & (N - 1));
-            double sn, cs;
-            sincospi(2.0 * (double)m / (double)N, &sn, &cs);
-            re += Xr[k] * cs - Xi[k] * sn;
-            im += Xr[k] * sn + Xi[k] * cs;
-        }
-        env[n] = sqrt(re * re + im * im) / (double)N;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // FWHM: first maximum, walk outwards to the half-maximum crossings
-        int p = 0;
-        for (int n = 1; n < L; ++n)
-            if (env[n] > env[p]) p = n;
-        const double half = 0.5 * env[p];
-        int lo = p;
-        while (lo > 0 && env[lo - 1] >= half) --lo;
-        const double xl = (lo == 0) ? 0.0 : (lo - 1) + (half - env[lo - 1]) / (env[lo] - env[lo - 1]);
-        int hi = p;
-        while (hi < L - 1 && env[hi + 1] >= half) ++hi;
-        const double xr = (hi == L - 1) ? (double)(L - 1) : hi + (env[hi] - half) / (env[hi] - env[hi + 1]);
-        width[u] = (xr - xl) * dzf;
-    }
+    block_envelope<PAPER_THREADS>(b, L, env, Xr, Xi);
+    if (threadIdx.x == 0) width[u] = env_fwhm(env, L) * dzf;
 }
 
 // One workgroup per row i.

@@ -268,3 +268,48 @@ def test_prepared_bank_size_and_invalid_arguments(lib):
         assert fn(FAKE, 128, FAKE, 1, 64, 64, f1, f0, NUL, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EINVAL
         assert fn(FAKE, 129, FAKE, 1, 64, 64, f1, f0, NUL, FAKE, NUL) == _lib.TIDAS_EINVAL  # out aliases input
         assert fn(FAKE, 401, FAKE, 1, 64, 64, f1, f0, NUL, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EUNSUPPORTED
+
+
+def test_point_study_rejects_invalid_arguments(lib):
+    arr = _lib.make_array(33, 0.3e-3, 1540.0)
+    tx = _lib.make_tx([0.0], 40e6, 0.0, 5e6, 2.0)
+    rx = _lib.make_rx(1.0)
+    f = lib.tidas_point_study
+    need = lib.tidas_point_study_workspace_bytes(33, 10, 1400, 1000)
+    assert need > 10 * 33 * 1400 * 8
+    assert lib.tidas_point_study_workspace_bytes(33, 0, 1400, 1000) == 0
+    T, Th, L, G, S, W, WS = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000, 0x5000, 0x6000, 0x7000))
+
+    def call(arr_=arr, tx_=tx, rx_=rx, n_tx=9, ns=1400, P=10, z1=6e-3, dz=2e-3, fi=4, lh=1000, sh=100,
+             th=Th, lo=L, gl=G, st=S, ws=WS, nb=need):
+        return f(ctypes.byref(arr_), ctypes.byref(tx_), ctypes.byref(rx_), n_tx, ns, P, z1, dz, fi, lh, sh, th, lo,
+                 gl, st, W, ws, nb, NUL)
+    E = _lib.TIDAS_EINVAL
+    assert call(n_tx=8) == E                                   # C - n_tx odd
+    assert call(n_tx=0) == E and call(n_tx=35) == E
+    assert call(tx_=_lib.make_tx([0.1], 40e6, 0.0, 5e6, 2.0)) == E      # steered
+    assert call(tx_=_lib.make_tx([0.0, 0.0], 40e6, 0.0, 5e6, 2.0)) == E  # several angles
+    assert call(ns=1) == E and call(P=0) == E
+    assert call(z1=0.0) == E and call(dz=0.0) == E
+    assert call(fi=10) == E and call(fi=-1) == E and call(lh=-1) == E
+    assert call(sh=512) == E                                   # stats axis over 1023 samples
+    assert call(th=NUL) == E and call(ws=NUL) == E
+    assert call(lo=Th) == E and call(st=G) == E                 # overlapping outputs
+    assert call(nb=need - 1) == E                               # short workspace
+    big = _lib.make_array(514, 0.3e-3, 1540.0)
+    assert call(arr_=big, n_tx=10) == _lib.TIDAS_EUNSUPPORTED
+    assert call(tx_=_lib.make_tx([0.0], 40e6, 0.0, 0.2e6, 2.0)) == _lib.TIDAS_EUNSUPPORTED  # pulse too long
+    assert lib.tidas_last_error()
+
+
+def test_kossoff_count_matches_the_oracle_on_the_host(lib):
+    from oracle import point_study as ps
+    for C in (16, 17, 64, 127, 128, 192):
+        for fc in (3e6, 5e6, 7e6, 9e6):
+            for zf in (2e-3, 15e-3, 25e-3, 35e-3, 1.0):
+                arr = _lib.make_array(C, 0.3e-3, 1540.0)
+                assert lib.tidas_kossoff_tx_count(ctypes.byref(arr), fc, zf, 0.6) == \
+                    ps.kossoff_tx_count(C, 0.3e-3, 1540.0, fc, zf)
+    arr = _lib.make_array(16, 0.3e-3, 1540.0)
+    assert lib.tidas_kossoff_tx_count(ctypes.byref(arr), 0.0, 25e-3, 0.6) == _lib.TIDAS_EINVAL
+    assert lib.tidas_kossoff_tx_count(ctypes.byref(arr), 5e6, 25e-3, 0.0) == _lib.TIDAS_EINVAL

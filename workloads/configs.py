@@ -13,6 +13,12 @@
 5. learned kernels: array of case 2, rows of a 512 x 2048 image over
    38 x 60 mm, 129 taps; draws of depth, F-number in [1, 3], angle in
    [-15, 15] degrees, centre frequency in [3, 10] MHz.
+
+The single-point study (the paper's Sec. 3.1-3.3 set-up, its open
+parameters read as stated here): 192 elements at 0.3 mm pitch, 50 MHz
+sampling, 3200 samples, 2-cycle pulse, receive F-number 1, 600 points
+from 2 to 42 mm on the axis, transmit focus at 15, 25 or 35 mm with a
+Kossoff aperture (parameter 0.6), centre frequencies 3 to 9 MHz.
 """
 from dataclasses import dataclass, replace
 import math
@@ -87,3 +93,29 @@ SURROGATE = dict(n_train=200_000, fnumber=(1.0, 3.0), angle_deg=(-15.0, 15.0), f
 
 def config(k):
     return CONFIGS[int(k)]
+
+
+STUDY = dict(n_elem=192, pitch=0.3e-3, fs=50e6, n_samples=3200, fnumber=1.0, n_points=600, z_first=2e-3,
+             z_last=42e-3, foci=(15e-3, 25e-3, 35e-3), fcs=(3e6, 5e6, 7e6, 9e6), kossoff=0.6)
+
+
+def study_setup(fc, **over):
+    """Setup of the single-point study at centre frequency fc (one 0-degree
+    angle: the focused beam is unsteered; the grid fields describe the
+    axial line of points)."""
+    p = dict(STUDY, **over)
+    n = p["n_points"]
+    dz = (p["z_last"] - p["z_first"]) / (n - 1)
+    return Setup(n_elem=p["n_elem"], pitch=p["pitch"], c=1540.0, fs=p["fs"], t0=0.0, fc=fc, cycles=2.0,
+                 n_samples=p["n_samples"], angles=(0.0,), fnumber=p["fnumber"], nz=n, nx=1, z0=p["z_first"], dz=dz,
+                 x0=0.0, dx=p["pitch"], K=1, field_w=p["n_elem"] * p["pitch"], field_d=p["z_last"])
+
+
+def study_line_half(setup):
+    """Half length of the whole line in fine samples: the span of the points."""
+    return int(math.ceil((setup.nz - 1) * setup.dz / (setup.c / (2.0 * setup.fs))))
+
+
+def study_focal_index(setup, z_focus):
+    """The point nearest the requested focal depth."""
+    return int(round((z_focus - setup.z0) / setup.dz))
