@@ -262,6 +262,25 @@ int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* image_bar, 
 int32_t tidas_kernel_grad_kernel(int32_t X, const void* refl, const void* image_bar);
 
 /*
+ * tidas_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operator, kernels and results (bit for bit) as tidas_apply, with the
+ * band images the split-bfloat16 kernels read prepared in a library-owned
+ * device array of TIDAS_NOALLOC_SCRATCH_BYTES (8 MiB) on each GPU, held until
+ * the process ends, instead of a temporary allocation; no call allocates or
+ * frees anything.  The array belongs to the current device (which must be
+ * the stream's device); every call on one GPU shares it, so calls that
+ * overlap on one GPU (concurrent streams or threads) race and must be
+ * serialised by the caller.  A bank whose band images exceed the array (one
+ * operator mode at K taps and Z rows: about 1.1 MB per 1024 rows at K = 129)
+ * returns TIDAS_EUNSUPPORTED before anything is enqueued; other arguments
+ * as tidas_apply.
+ */
+#define TIDAS_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+int32_t tidas_apply_noalloc(const float* kernels, int32_t K, const float* refl, int32_t B, int32_t Z, int32_t X,
+                            float* image, void* stream);
+
+/*
  * Which line-model kernel tidas_apply / tidas_adjoint (and their fused and
  * prepared forms) run for K taps, B frames of Z x X (16-byte aligned
  * buffers): a diagnostic for callers and tests, enqueues nothing.

@@ -71,6 +71,7 @@ _SIGS = {
                                  ctypes.POINTER(Grid), _I, _I, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P]),
     "tidas_apply": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
     "tidas_adjoint": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
+    "tidas_apply_noalloc": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
     "tidas_simulate_rf": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), _P, _I, _I, _P, _P]),
     "tidas_apply_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_adjoint_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),

@@ -37,6 +37,7 @@
 // halo rows in that XCD's L2.
 #include <algorithm>
 #include <climits>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -1385,20 +1386,28 @@ static bool vec_ok(int32_t X, const float* in, const float* out, const float* ba
 
 // Validate, pick the matrix-core or the VALU kernel, launch.  Enqueues nothing
 // when it returns TIDAS_EINVAL / TIDAS_EUNSUPPORTED.  The split-bfloat16 path
-// prepares the band images it needs in a stream-ordered temporary buffer.
+// prepares the band images it needs in a stream-ordered temporary buffer, or,
+// when `band` is given, in that device buffer of `band_bytes` bytes (too
+// small: TIDAS_EUNSUPPORTED before anything is enqueued).
 static int32_t conv_launch(bool adj, const char* name, const float* kernels, int32_t K, const float* in, int32_t B,
                            int32_t Z, int32_t X, float alpha, float beta, const float* base, float* out,
-                           hipStream_t stream) {
+                           hipStream_t stream, void* band = nullptr, size_t band_bytes = 0) {
     int32_t st = conv_validate(name, kernels, K, in, B, Z, X, alpha, beta, base, out);
     if (st) return st;
     const bool vec = vec_ok(X, in, out, base);
     const bool four = b4_path(K, B, Z, X);
     if (four || bx_path(K, B, Z, X)) {
         // the band images of this one mode, in the layout of the chosen tile
-        void* buf = nullptr;
-        if ((st = check_hip(hipMallocAsync(&buf, four ? b4_bytes(K, Z, 1) : prepared_bytes(K, Z, 1), stream),
-                            "band buffer")))
+        const size_t need = four ? b4_bytes(K, Z, 1) : prepared_bytes(K, Z, 1);
+        void* buf = band;
+        if (band) {
+            if (need > band_bytes)
+                return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": the band images (" + std::to_string(need) +
+                                                    " bytes) exceed the " + std::to_string(band_bytes) +
+                                                    "-byte scratch buffer");
+        } else if ((st = check_hip(hipMallocAsync(&buf, need, stream), "band buffer"))) {
             return st;
+        }
         if (four) launch_b4_prepare(kernels, K, Z, adj ? 1 : 0, 1, (uint16_t*)buf, stream);
         else launch_prepare(kernels, K, Z, adj ? 1 : 0, 1, (uint16_t*)buf, stream);
         st = check_launch(name);
@@ -1407,6 +1416,7 @@ static int32_t conv_launch(bool adj, const char* name, const float* kernels, int
             else launch_bx6(adj, vec, (const uint16_t*)buf, K, in, B, Z, X, alpha, beta, base, out, stream);
             st = check_launch(name);
         }
+        if (band) return st;
         const int32_t st2 = check_hip(hipFreeAsync(buf, stream), "band buffer");
         return st ? st : st2;
     }
@@ -1493,9 +1503,49 @@ __global__ __launch_bounds__(1024) void normalize_kernel(float* __restrict__ v, 
     for (int i = threadIdx.x; i < n; i += 1024) v[i] *= inv;
 }
 
+// Band images of the allocation-free forward operator (tidas_apply_noalloc):
+// a file-scope device array, one copy on every GPU the library runs on, held
+// until the process ends and shared by every call on that GPU.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in): its device address is looked up once per device with
+// hipGetSymbolAddress, with that device current, and kept in g_scratch.
+constexpr size_t NOALLOC_SCRATCH_BYTES = TIDAS_NOALLOC_SCRATCH_BYTES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) uint8_t noalloc_scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mutex;
+static void* g_scratch[NOALLOC_MAX_DEVICES] = {};
+
+static int32_t noalloc_scratch_ptr(void** out) {
+    int dev = -1;
+    if (int32_t st = check_hip(hipGetDevice(&dev), "tidas_apply_noalloc: current device")) return st;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(TIDAS_EUNSUPPORTED, "tidas_apply_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        if (int32_t st = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)),
+                                   "tidas_apply_noalloc: scratch address"))
+            return st;
+        if (!p) return fail(TIDAS_EHIP, "tidas_apply_noalloc: scratch address is null");
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return TIDAS_OK;
+}
+
 }  // namespace tidas
 
 using namespace tidas;
+
+extern "C" int32_t tidas_apply_noalloc(const float* kernels, int32_t K, const float* refl, int32_t B, int32_t Z,
+                                       int32_t X, float* image, void* stream) {
+    if (int32_t st = conv_validate("tidas_apply_noalloc", kernels, K, refl, B, Z, X, 1.0f, 0.0f, nullptr, image))
+        return st;
+    void* scratch = nullptr;
+    if (int32_t st = noalloc_scratch_ptr(&scratch)) return st;
+    return conv_launch(false, "tidas_apply_noalloc", kernels, K, refl, B, Z, X, 1.0f, 0.0f, nullptr, image,
+                       (hipStream_t)stream, scratch, NOALLOC_SCRATCH_BYTES);
+}
 
 extern "C" int32_t tidas_apply(const float* kernels, int32_t K, const float* refl, int32_t B, int32_t Z,
                                int32_t X, float* image, void* stream) {
