@@ -334,9 +334,17 @@ int32_t tidas_adjoint_prepared(const void* prepared, int32_t K, const float* ima
  * Sec. 1, Sec. 4).  Minimises 1/2 ||A r - y||^2 + lam/2 ||r||^2 by `iters`
  * gradient steps from r_0 = 0:
  *   r_{t+1} = r_t - eta (A^T (A r_t - y) + lam r_t),
- * two fused launches per step.  y, r, work DEV [B][Z][X], pairwise distinct;
- * r receives the result, work is scratch.  lam >= 0, eta > 0 (for
- * convergence eta < 2 / (||A||^2 + lam); see tidas_operator_norm_sq).
+ * computed as r_{t+1} = N r_t + c with the step operator N = (1 - eta lam) I
+ * - eta A^T A (a bank of 2K - 1 taps built in float64) and c = eta A^T y,
+ * r_1 = c: one launch per step, or, when the bank of N^2 (4K - 3 taps) fits
+ * the split-bfloat16 tile (K <= 81), one launch per two steps
+ * (r_{t+2} = N^2 r_t + N c + c); kernels too long for the tile (K > 161)
+ * take two fused launches per step as written.  y, r, work DEV [B][Z][X],
+ * pairwise distinct; r receives the result, work is scratch.  lam >= 0,
+ * eta > 0 (for convergence eta < 2 / (||A||^2 + lam); see
+ * tidas_operator_norm_sq).  The step operators, their band images and c (and
+ * N c + c) live in one stream-ordered temporary buffer (about 2 frames plus
+ * 60 Z K bytes; TIDAS_ENOMEM possible).
  */
 int32_t tidas_deconvolve(const float* kernels, int32_t K, const float* y, int32_t B, int32_t Z, int32_t X,
                          float lam, float eta, int32_t iters, float* r, float* work, void* stream);

@@ -1360,6 +1360,8 @@ constexpr int CONV_RZ = 16;
 constexpr int CONV_WAVES = 4;
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 static int32_t conv_validate(const char* name, const void* kernels, int32_t K, const float* in, int32_t B, int32_t Z,
@@ -1477,6 +1479,53 @@ static int32_t conv_launch_images(bool adj, const char* name, const uint16_t* pr
     const uint16_t* img = prepared + (adj ? prepared_bytes(K, Z, 1) / 2 : 0);
     launch_bx6(adj, vec_ok(X, in, out, base), img, K, in, B, Z, X, alpha, beta, base, out, stream);
     return check_launch(name);
+}
+
+// Step operator of the Tikhonov gradient iteration, N = (1 - eta lam) I -
+// eta A^T A, as a line-model bank of 2K - 1 taps (offsets m = i - j from
+// -(K - 1) to K - 1): Nb[i][m + K - 1] = N[i][i - m], with
+//   (A^T A)[i][j] = sum_k A[k][i] A[k][j],  A[k][i] = K[k][k - i + h],
+// k over the rows both columns reach (|k - i| <= h, |k - j| <= h, 0 <= k < Z);
+// entries with j outside [0, Z) are 0.  Float64 sums; `nd` keeps the float64
+// bank for the squared operator, `nf` the float32 bank of N + shift I.
+__global__ __launch_bounds__(256) void normal_bank_kernel(const float* __restrict__ kb, int32_t K, int32_t Z,
+                                                          double eta, double lam, double shift,
+                                                          double* __restrict__ nd, float* __restrict__ nf) {
+    const int KN = 2 * K - 1, h = (K - 1) / 2;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)Z * KN) return;
+    const int i = (int)(idx / KN);
+    const int m = (int)(idx % KN) - (K - 1);
+    const int j = i - m;
+    double v = 0.0;
+    if (j >= 0 && j < Z) {
+        const int k0 = max(max(i, j) - h, 0), k1 = min(min(i, j) + h, Z - 1);
+        double acc = 0.0;
+        for (int k = k0; k <= k1; ++k)
+            acc += (double)kb[(size_t)k * K + (k - i + h)] * (double)kb[(size_t)k * K + (k - j + h)];
+        v = -eta * acc + (i == j ? 1.0 - eta * lam : 0.0);
+    }
+    if (nd) nd[idx] = v;
+    nf[idx] = (float)(v + (m == 0 && j < Z ? shift : 0.0));
+}
+
+// N^2 from the float64 bank of N (K1 = 2K - 1 taps, H1 = K1 / 2): a bank of
+// 2 K1 - 1 taps, N2[i][j] = sum_k N[i][k] N[k][j] in float64, rounded once.
+__global__ __launch_bounds__(256) void square_bank_kernel(const double* __restrict__ nd, int32_t K1, int32_t Z,
+                                                          float* __restrict__ n2) {
+    const int K2 = 2 * K1 - 1, H1 = (K1 - 1) / 2, H2 = (K2 - 1) / 2;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)Z * K2) return;
+    const int i = (int)(idx / K2);
+    const int m = (int)(idx % K2) - H2;
+    const int j = i - m;
+    double acc = 0.0;
+    if (j >= 0 && j < Z) {
+        const int k0 = max(max(i, j) - H1, 0), k1 = min(min(i, j) + H1, Z - 1);
+        for (int k = k0; k <= k1; ++k)
+            acc += nd[(size_t)i * K1 + (i - k) + H1] * nd[(size_t)k * K1 + (k - j) + H1];
+    }
+    n2[idx] = (float)acc;
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(float* __restrict__ p, int64_t n, float v) {
@@ -1628,35 +1677,92 @@ extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float
             if (ptrs[a] == ptrs[c]) return fail(TIDAS_EINVAL, "tidas_deconvolve: buffers must be distinct");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = (int64_t)B * Z * X;
-    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s, r, n,
-                       0.0f);
-    int32_t st = check_launch("tidas_deconvolve(zero)");
-    const float decay = 1.0f - eta * lam;
-    // the band images of both modes once for all iterations
-    void* imgs = nullptr;
-    const bool bx = bx_path(K, B, Z, X);
-    if (!st && bx && !(st = check_hip(hipMallocAsync(&imgs, full_prepared_bytes(K, Z), s), "tidas_deconvolve: bands"))) {
-        prepare_full(kernels, K, Z, (uint16_t*)imgs, s);
+    if (iters == 0) {
+        hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s, r,
+                           n, 0.0f);
+        return check_launch("tidas_deconvolve(zero)");
+    }
+    // r_{t+1} = N r_t + c with N = (1 - eta lam) I - eta A^T A and c = eta A^T y
+    // (the same step, regrouped), r_1 = c; with N^2 and c2 = N c + c two steps
+    // per launch: r_{t+2} = N^2 r_t + c2.  The step operator's bank has 2K - 1
+    // taps (N^2: 4K - 3); both run on the split-bfloat16 two-block tile.
+    const int KN = 2 * K - 1, KN2 = 2 * KN - 1;
+    const bool two = bx_path(KN2, B, Z, X) && bx_lds_bytes(KN2) <= 160 * 1024;
+    const bool one = bx_path(KN, B, Z, X) && bx_lds_bytes(KN) <= 160 * 1024;
+    if (!one) {
+        // large kernels: two fused launches per step (residual, update)
+        hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s, r,
+                           n, 0.0f);
+        int32_t st = check_launch("tidas_deconvolve(zero)");
+        const float decay = 1.0f - eta * lam;
+        for (int it = 0; it < iters && !st; ++it) {
+            st = conv_launch(false, "tidas_deconvolve(residual)", kernels, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
+            if (!st) st = conv_launch(true, "tidas_deconvolve(update)", kernels, K, work, B, Z, X, -eta, decay, r, r, s);
+        }
+        return st;
+    }
+    const int KP = two ? KN2 : KN;  // bank of one launch
+    const size_t frame_bytes = (size_t)n * sizeof(float);
+    const size_t off_nd = 0;
+    const size_t off_n1 = off_nd + (two ? align_up((size_t)Z * KN * sizeof(double), 256) : 0);
+    const size_t off_np = off_n1 + align_up((size_t)Z * KN * sizeof(float), 256);
+    const size_t off_img = off_np + (two ? align_up((size_t)Z * KP * sizeof(float), 256) : 0);
+    const size_t off_c = off_img + align_up(prepared_bytes(KP, Z, 1), 256);
+    const size_t off_c2 = off_c + align_up(frame_bytes, 256);
+    const size_t total = off_c2 + (two ? align_up(frame_bytes, 256) : 0);
+    char* tmp = nullptr;
+    int32_t st = check_hip(hipMallocAsync((void**)&tmp, total, s), "tidas_deconvolve: temporaries");
+    if (st) return st;
+    double* nd = two ? (double*)(tmp + off_nd) : nullptr;
+    float* n1 = (float*)(tmp + off_n1);  // N, or N + I with two steps per launch
+    float* np = two ? (float*)(tmp + off_np) : n1;
+    uint16_t* img = (uint16_t*)(tmp + off_img);
+    float* c = (float*)(tmp + off_c);
+    float* c2 = two ? (float*)(tmp + off_c2) : nullptr;
+    const int64_t e1 = (int64_t)Z * KN;
+    // with two steps per launch n1 is N + I (for c2 = (N + I) c), else N
+    hipLaunchKernelGGL(normal_bank_kernel, dim3((unsigned)((e1 + 255) / 256)), dim3(256), 0, s, kernels, K, Z,
+                       (double)eta, (double)lam, two ? 1.0 : 0.0, nd, n1);
+    st = check_launch("tidas_deconvolve(step operator)");
+    if (!st && two) {
+        const int64_t e2 = (int64_t)Z * KN2;
+        hipLaunchKernelGGL(square_bank_kernel, dim3((unsigned)((e2 + 255) / 256)), dim3(256), 0, s, nd, KN, Z, np);
+        st = check_launch("tidas_deconvolve(squared step operator)");
+    }
+    if (!st) {
+        launch_prepare(np, KP, Z, 0, 1, img, s);
         st = check_launch("tidas_deconvolve(prepare)");
     }
-    const uint16_t* prep = (const uint16_t*)imgs;
-    for (int it = 0; it < iters && !st; ++it) {
-        // work = A r - y ;  r = -eta A^T work + (1 - eta lam) r
-        if (bx) {
-            st = conv_launch_images(false, "tidas_deconvolve(residual)", prep, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
-            if (!st)
-                st = conv_launch_images(true, "tidas_deconvolve(update)", prep, K, work, B, Z, X, -eta, decay, r, r, s);
-        } else {
-            st = conv_launch(false, "tidas_deconvolve(residual)", kernels, K, r, B, Z, X, 1.0f, -1.0f, y, work, s);
-            if (!st)
-                st = conv_launch(true, "tidas_deconvolve(update)", kernels, K, work, B, Z, X, -eta, decay, r, r, s);
+    // c = eta A^T y
+    if (!st) st = conv_launch(true, "tidas_deconvolve(c)", kernels, K, y, B, Z, X, eta, 0.0f, nullptr, c, s);
+    // iterate from x = r_1 = c (or, two per launch with an even count, x = r_2 = c2)
+    const float* x = c;
+    int left = iters - 1;  // steps still to take
+    const float* base = c;
+    if (!st && two) {
+        st = conv_launch(false, "tidas_deconvolve(c2)", n1, KN, c, B, Z, X, 1.0f, 0.0f, nullptr, c2, s);
+        base = c2;
+        if (iters % 2 == 0) {
+            x = c2;
+            left = iters - 2;
         }
     }
-    if (imgs) {
-        const int32_t st2 = check_hip(hipFreeAsync(imgs, s), "tidas_deconvolve: bands");
-        if (!st) st = st2;
+    const int per = two ? 2 : 1;
+    int launches = left / per;
+    // the last launch writes r, so launches alternate between work and r backwards from it
+    float* bufs[2] = {r, work};
+    for (int q = 0; q < launches && !st; ++q) {
+        float* out = bufs[(launches - 1 - q) % 2];
+        launch_bx6(false, vec_ok(X, x, out, base), img, KP, x, B, Z, X, 1.0f, 1.0f, base, out, s);
+        st = check_launch("tidas_deconvolve(step)");
+        x = out;
     }
-    return st;
+    if (!st && launches == 0) {
+        // iters = 1 (r = c), or iters = 2 with two steps per launch (r = c2)
+        st = check_hip(hipMemcpyAsync(r, x, frame_bytes, hipMemcpyDeviceToDevice, s), "tidas_deconvolve: copy");
+    }
+    const int32_t st2 = check_hip(hipFreeAsync(tmp, s), "tidas_deconvolve: temporaries");
+    return st ? st : st2;
 }
 
 extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32_t Z, int32_t iters, float* work,

@@ -127,7 +127,9 @@ def test_deconvolution_200_iterations_matches_oracle(dev):
     M = o_t.matrix(kb.astype(np.float64))
     smax = np.linalg.svd(M, compute_uv=False)[0]
     eta = 1.0 / (smax ** 2 + lam)
-    checkpoints = (1, 10, 50, DECONV["iters"])
+    # 1 and 2: the first iterates (no operator launch); odd counts start from
+    # r_1 with two steps per launch, even ones from r_2
+    checkpoints = (1, 2, 7, 10, 51, DECONV["iters"])
     r_o, rec = o_dc.gradient_descent_matrix(M, y, lam, eta, DECONV["iters"], record_at=checkpoints)
     kd, yd = g(kb, dev), g(y, dev)
     for t in checkpoints:
@@ -138,6 +140,28 @@ def test_deconvolution_200_iterations_matches_oracle(dev):
     d0 = np.linalg.norm(rstar)
     assert np.linalg.norm(r_o - rstar) < d0
     assert rel(r_o, rtrue) < 1.0
+
+
+# K = 129: the step operator (257 taps) runs one step per launch; K = 201:
+# its 401 taps exceed the split tile, two fused launches per step
+@pytest.mark.parametrize("B,Z,X,K", [(1, 300, 40, 129), (2, 200, 24, 201), (3, 90, 20, 17)])
+def test_deconvolution_iterates_on_every_path(dev, B, Z, X, K):
+    kb = (generators.normal((Z, K), seed=K + 1) * 0.05).astype(np.float32)
+    y = generators.normal((B, Z, X), seed=Z + 2).astype(np.float32)
+    lam = 1e-2
+    M = o_t.matrix(kb.astype(np.float64))
+    eta = 1.0 / (np.linalg.svd(M, compute_uv=False)[0] ** 2 + lam)
+    checkpoints = (0, 1, 2, 3, 8, 25)
+    _, rec = o_dc.gradient_descent_matrix(M, np.moveaxis(y, 0, 1).reshape(Z, -1), lam, eta, 25,
+                                          record_at=checkpoints)
+    kd, yd = g(kb, dev), g(y, dev)
+    for t in checkpoints:
+        r_g = td.deconvolve(kd, yd, lam, eta=eta, iters=t).cpu().numpy()
+        want = np.moveaxis(rec[t].reshape(Z, B, X), 1, 0)
+        if t == 0:
+            assert not np.any(r_g)
+        else:
+            assert rel(r_g, want) <= RTOL, t
 
 
 def test_operator_norm_power_iteration(dev):
