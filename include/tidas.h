@@ -375,13 +375,29 @@ typedef struct tidas_frame {
 /* Launch-shape variants the batch entry points accept (chosen by an autotuner):
  *   DAS:        variant v -> 4 or 8 waves per workgroup (v & 1), and 2, 4 or 8
  *               workgroups per compute unit (v >> 1)
- *   line model: variant v -> prefetch depth 4, 8 or 16 steps (v % 3), and 2 or
- *               4 workgroups per compute unit (v / 3) */
+ *   line model: variants 0-5: persistent workgroups over the 64-row tiles of
+ *               all frames (split-bfloat16 two-block tile: 1, 2, 3, 4, 6 or 8
+ *               workgroups per compute unit; for K > 321 the float32 matrix
+ *               tile: prefetch depth 4, 8 or 16 steps (v % 3) and 2 or 4
+ *               workgroups per compute unit (v / 3));
+ *               variant 6 (TIDAS_APPLY_BATCH_FOUR_BLOCK, K <= 161): the band
+ *               images of every frame prepared once in the workspace, then
+ *               one workgroup per 128-row tile of every frame on the
+ *               four-block tile, walking the frame's 256-column tiles; it
+ *               needs tidas_apply_batch_workspace_bytes and a 256-byte
+ *               aligned workspace.  Every variant gives the same bits. */
 #define TIDAS_DAS_BATCH_VARIANTS 6
-#define TIDAS_APPLY_BATCH_VARIANTS 6
+#define TIDAS_APPLY_BATCH_VARIANTS 7
+#define TIDAS_APPLY_BATCH_FOUR_BLOCK 6
 
 /* Device workspace (bytes) a batch of n_frames needs: the frame table. */
 size_t tidas_batch_workspace_bytes(int32_t n_frames);
+
+/* Device workspace (bytes) tidas_apply_batch needs for these frames and K
+ * with any variant: the frame table and, when K <= 161, the four-block band
+ * images of every frame (one operator mode: about 1 MB per 1024 rows at
+ * K = 129, 0.8 MB at K = 65).  0 for invalid arguments. */
+size_t tidas_apply_batch_workspace_bytes(const tidas_frame* frames, int32_t n_frames, int32_t K);
 
 /*
  * DAS of a ragged batch: frames[f].out = DAS(frames[f].rf) on frames[f].grid
@@ -396,12 +412,31 @@ int32_t das_beamform_batch(const tidas_array* array, const tidas_tx* tx, const t
 
 /*
  * Line model of a ragged batch: frames[f].out = A_f(frames[f].in) with the
- * frame's own [nz][K] bank (definition of tidas_apply).  Workspace as above;
- * variant in [0, TIDAS_APPLY_BATCH_VARIANTS).  TIDAS_EUNSUPPORTED if a frame
+ * frame's own [nz][K] bank (definition of tidas_apply).  Workspace of
+ * tidas_apply_batch_workspace_bytes (variants 0-5 need only the table,
+ * tidas_batch_workspace_bytes); variant in [0, TIDAS_APPLY_BATCH_VARIANTS).  TIDAS_EUNSUPPORTED if a frame
  * exceeds the tile path's limits (then use tidas_apply per frame).
  */
 int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames, int32_t K, void* workspace,
                           size_t workspace_bytes, int32_t variant, void* stream);
+
+/*
+ * The four-block batch (variant TIDAS_APPLY_BATCH_FOUR_BLOCK) split in two,
+ * for a batch applied many times (the banks depend on the geometry only):
+ * tidas_apply_batch_prepare uploads the frame table and prepares every
+ * frame's band images in `workspace` (tidas_apply_batch_workspace_bytes
+ * bytes, 256-byte aligned); tidas_apply_batch_prepared then runs the line
+ * model of the batch with one launch and no upload.  The workspace then
+ * holds the frames' bank, input and output pointers: the prepared call must
+ * get the same frames (it recomputes only the launch size from them) and the
+ * banks must be unchanged since the prepare call; the outputs are the same
+ * bits as tidas_apply_batch.  EUNSUPPORTED for K > 161 or more than 65535
+ * tiles of 128 rows.
+ */
+int32_t tidas_apply_batch_prepare(const tidas_frame* frames, int32_t n_frames, int32_t K, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+int32_t tidas_apply_batch_prepared(const tidas_frame* frames, int32_t n_frames, int32_t K, const void* workspace,
+                                   size_t workspace_bytes, void* stream);
 
 /*
  * Exact-mode row kernels for independent draws (the surrogate's training data

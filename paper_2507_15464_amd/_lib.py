@@ -55,7 +55,8 @@ class Frame(ctypes.Structure):
 
 
 DAS_BATCH_VARIANTS = 6
-APPLY_BATCH_VARIANTS = 6
+APPLY_BATCH_VARIANTS = 7
+APPLY_BATCH_FOUR_BLOCK = 6
 
 
 _P = ctypes.c_void_p
@@ -94,6 +95,9 @@ _SIGS = {
     "das_beamform_batch": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), _I,
                                 ctypes.POINTER(Frame), _I, _P, ctypes.c_size_t, _I, _P]),
     "tidas_apply_batch": (_I, [ctypes.POINTER(Frame), _I, _I, _P, ctypes.c_size_t, _I, _P]),
+    "tidas_apply_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Frame), _I, _I]),
+    "tidas_apply_batch_prepare": (_I, [ctypes.POINTER(Frame), _I, _I, _P, ctypes.c_size_t, _P]),
+    "tidas_apply_batch_prepared": (_I, [ctypes.POINTER(Frame), _I, _I, _P, ctypes.c_size_t, _P]),
     "tidas_kernels_at": (_I, [ctypes.POINTER(Array), ctypes.c_double, ctypes.c_double, ctypes.c_double, _I,
                               ctypes.c_double, _P, _I, _I, _I, _P, _P, _P]),
     "tidas_mlp_param_count": (ctypes.c_int64, [ctypes.POINTER(ctypes.c_int32)]),

@@ -12,7 +12,7 @@ import torch
 from . import _lib
 from .api import _check_tensor, _descs, _stream
 
-__all__ = ["das_beamform_batch", "apply_batch"]
+__all__ = ["das_beamform_batch", "apply_batch", "PreparedBatch"]
 
 
 def _grid_of(g):
@@ -50,9 +50,7 @@ def das_beamform_batch(setup, grids, rfs, outs=None, variant=0):
     return outs
 
 
-def apply_batch(kernels, refls, outs=None, variant=0):
-    """Line model of ragged frames: outs[f] = A_f(refls[f]) with bank kernels[f] [Z_f][K]."""
-    lib = _lib.load()
+def _line_frames(kernels, refls, outs):
     n = len(kernels)
     if n < 1 or len(refls) != n:
         raise ValueError("need one reflectivity map per kernel bank")
@@ -67,6 +65,44 @@ def apply_batch(kernels, refls, outs=None, variant=0):
             raise ValueError("frame f needs kernels [Z][K] (common K), refl and out [Z][X]")
         g = _lib.make_grid(r.shape[0], r.shape[1], 0.0, 1.0, 0.0, 1.0)
         frames[f] = _lib.Frame(g, 0, kb.data_ptr(), r.data_ptr(), out.data_ptr())
-    ws, nbytes = _workspace(n, refls[0].device)
+    return frames, K, outs
+
+
+def _line_workspace(frames, n, K, device):
+    nbytes = _lib.load().tidas_apply_batch_workspace_bytes(frames, n, K)
+    if nbytes == 0:
+        raise ValueError("invalid batch")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def apply_batch(kernels, refls, outs=None, variant=0):
+    """Line model of ragged frames: outs[f] = A_f(refls[f]) with bank kernels[f] [Z_f][K]."""
+    lib = _lib.load()
+    frames, K, outs = _line_frames(kernels, refls, outs)
+    n = len(outs)
+    ws, nbytes = _line_workspace(frames, n, K, refls[0].device)
     _lib.check(lib.tidas_apply_batch(frames, n, K, ctypes.c_void_p(ws.data_ptr()), nbytes, int(variant), _stream()))
     return outs
+
+
+class PreparedBatch:
+    """A ragged batch of the line model prepared once (frame table and every
+    frame's band images, ``tidas_apply_batch_prepare``): ``apply()`` is then one
+    launch over the batch (``tidas_apply_batch_prepared``), writing ``outs``.
+    The banks, maps and outputs are held by reference; the banks must not
+    change while the batch is in use (the maps may: they are read at each
+    ``apply``)."""
+
+    def __init__(self, kernels, refls, outs=None):
+        self.lib = _lib.load()
+        self.kernels, self.refls = list(kernels), list(refls)
+        self.frames, self.K, self.outs = _line_frames(self.kernels, self.refls, outs)
+        self.n = len(self.outs)
+        self.ws, self.nbytes = _line_workspace(self.frames, self.n, self.K, self.refls[0].device)
+        _lib.check(self.lib.tidas_apply_batch_prepare(self.frames, self.n, self.K, ctypes.c_void_p(self.ws.data_ptr()),
+                                                      self.nbytes, _stream()))
+
+    def apply(self):
+        _lib.check(self.lib.tidas_apply_batch_prepared(self.frames, self.n, self.K,
+                                                       ctypes.c_void_p(self.ws.data_ptr()), self.nbytes, _stream()))
+        return self.outs

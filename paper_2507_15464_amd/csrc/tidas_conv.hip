@@ -404,6 +404,7 @@ struct ConvFrameDev {  // at most 128 bytes (the workspace holds 128 bytes per f
     int32_t vec;  // X % 4 == 0 and 16-byte aligned input and output
     int32_t pad;
     int64_t tile_start;
+    int64_t img_off;  // four-block batch: byte offset of the frame's band images in the workspace
 };
 
 static_assert(sizeof(ConvFrameDev) <= 128, "batch table entry too large");
@@ -486,11 +487,12 @@ __host__ __device__ constexpr size_t bx_lds_bytes(int K) { return (size_t)3 * BX
 
 // A wave-uniform pointer moved into scalar registers (a buffer descriptor
 // built from a pointer the compiler cannot prove uniform costs a loop per load).
-__device__ __forceinline__ const float* uniform_ptr(const float* p) {
+template <typename T>
+__device__ __forceinline__ const T* uniform_ptr(const T* p) {
     const uint64_t v = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return reinterpret_cast<const float*>(((uint64_t)hi << 32) | lo);
+    return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
 }
 
 // bfloat16 parts of the exact split, each as the top half of a 32-bit word
@@ -844,12 +846,11 @@ __host__ __device__ constexpr int b4_nsb(int K) {
 // Band image of the 128-row tile at i0 in the four-block layout
 // [block (stride b4_block_bytes)][plane][32][16 NSB + 8]: entry (b, r, c) = M[32 b + r][32 b + c] of
 // the tile (apply: K[i0 + 32b + r][r - c + 2h]; adjoint: K[i0 - h + 32b + c][c - r]).
-__global__ __launch_bounds__(256) void b4_prepare_kernel(const float* __restrict__ Kb, int32_t K, int32_t Z,
-                                                         int32_t n_rt, int32_t nsb, uint16_t* __restrict__ prepared,
-                                                         int32_t mode0) {
+// Entry e (over [block][row][column]) of the band image of 128-row tile rt,
+// written to the tile's image img (three planes per block).
+__device__ __forceinline__ void b4_prepare_entry(const float* __restrict__ Kb, int32_t K, int32_t Z, int32_t nsb,
+                                                 int rt, int adj, int e, uint16_t* __restrict__ img) {
     const int LS = b4_lstride(nsb);
-    const int rt = blockIdx.y, adj = mode0 + (int)blockIdx.z;
-    const int e = blockIdx.x * 256 + threadIdx.x;  // over [block][row][column]
     const int per_block = 32 * LS;
     if (e >= 4 * per_block) return;
     const int b = e / per_block, rc = e - b * per_block;
@@ -860,13 +861,37 @@ __global__ __launch_bounds__(256) void b4_prepare_kernel(const float* __restrict
     const int row = adj ? i0 - h + 32 * b + c : i0 + 32 * b + r;
     const bool ok = c < 16 * nsb && t >= 0 && t < K && row >= 0 && row < Z;
     const float v = ok ? Kb[(size_t)row * K + t] : 0.0f;
-    uint16_t* img =
-        prepared + (size_t)(blockIdx.z * n_rt + rt) * (b4_image_bytes(nsb) / 2) + (size_t)b * (b4_block_bytes(nsb) / 2);
+    uint16_t* blk = img + (size_t)b * (b4_block_bytes(nsb) / 2);
     uint32_t w0, w1, w2;
     split3(v, w0, w1, w2);
-    img[rc] = (uint16_t)(w0 >> 16);
-    img[per_block + rc] = (uint16_t)(w1 >> 16);
-    img[2 * per_block + rc] = (uint16_t)(w2 >> 16);
+    blk[rc] = (uint16_t)(w0 >> 16);
+    blk[per_block + rc] = (uint16_t)(w1 >> 16);
+    blk[2 * per_block + rc] = (uint16_t)(w2 >> 16);
+}
+
+__global__ __launch_bounds__(256) void b4_prepare_kernel(const float* __restrict__ Kb, int32_t K, int32_t Z,
+                                                         int32_t n_rt, int32_t nsb, uint16_t* __restrict__ prepared,
+                                                         int32_t mode0) {
+    const int rt = blockIdx.y, adj = mode0 + (int)blockIdx.z;
+    uint16_t* img = prepared + (size_t)(blockIdx.z * n_rt + rt) * (b4_image_bytes(nsb) / 2);
+    b4_prepare_entry(Kb, K, Z, nsb, rt, adj, blockIdx.x * 256 + threadIdx.x, img);
+}
+
+// Forward band images of every 128-row tile of every frame of a ragged batch
+// (grid.y = global tile index; frame f's images at byte offset img_off).
+__global__ __launch_bounds__(256) void b4_batch_prepare_kernel(const ConvFrameDev* __restrict__ tab, int32_t n_tab,
+                                                               int32_t K, int32_t nsb, uint16_t* __restrict__ images) {
+    const int t = blockIdx.y;
+    int a = 0, b = n_tab - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (tab[mid].tile_start <= t) a = mid;
+        else b = mid - 1;
+    }
+    const ConvFrameDev fr = tab[a];
+    const int rt = t - (int)fr.tile_start;
+    uint16_t* img = images + fr.img_off / 2 + (size_t)rt * (b4_image_bytes(nsb) / 2);
+    b4_prepare_entry(fr.kernels, K, fr.Z, nsb, rt, 0, blockIdx.x * 256 + threadIdx.x, img);
 }
 
 template <int N, typename F, int... I>
@@ -886,9 +911,17 @@ struct B4Geom {
     const float* base;
 };
 
-template <bool ADJ, int NSB>
+// BATCH: a ragged batch (tidas_apply_batch).  Workgroup lg takes 128-row
+// tile rt of the frame whose tile range holds lg (table `tab`, tile_start in
+// 128-row tiles), with that frame's prepared band image at byte offset
+// img_off from `images`; the frame's 256-column tiles take the place of the
+// frames of a plain launch (the ring runs on from one to the next), each
+// addressed from a base 256 columns further on, so rows past the image still
+// fall outside the range and read 0; columns past X are computed but not stored.
+template <bool ADJ, int NSB, bool BATCH>
 __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, const uint16_t* __restrict__ images,
-                                                              const float* __restrict__ In, float* Out) {
+                                                              const float* __restrict__ In, float* Out,
+                                                              const ConvFrameDev* __restrict__ tab, int32_t n_tab) {
     constexpr int NW = NSB + 6;   // window steps of the tile
     constexpr int LS = b4_lstride(NSB);
     constexpr int PB = 32 * LS;   // one plane of one block, in bf16
@@ -899,35 +932,71 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
     static_assert(NW % PD == 0, "ring slots must divide the window steps");
     extern __shared__ uint16_t b4_smem[];
     const int lg = xcd_remap(blockIdx.x, g.n_blocks);
-    const int rt = lg % g.n_rt;
-    const int ct = (lg / g.n_rt) % g.n_ct;
-    const int fg = lg / (g.n_rt * g.n_ct);
-    const int f0 = fg * g.nf;
-    const int nf = min(g.nf, g.B - f0);
-    const int K = g.K, Z = g.Z, X = g.X;
+    int rt, ct, nf, Z, X;
+    const float* In0;
+    float* Out0;
+    const float* Base0;
+    const uint16_t* img_tiles;  // band image of tile 0 of this workgroup's frame
+    size_t fstride;             // floats from one frame (batch: column tile) to the next
+    if constexpr (BATCH) {
+        int a = 0, b = n_tab - 1;  // largest frame with tile_start <= lg
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (tab[mid].tile_start <= lg) a = mid;
+            else b = mid - 1;
+        }
+        const ConvFrameDev fr = tab[__builtin_amdgcn_readfirstlane(a)];
+        Z = __builtin_amdgcn_readfirstlane(fr.Z);
+        X = __builtin_amdgcn_readfirstlane(fr.X);
+        rt = lg - __builtin_amdgcn_readfirstlane((int)fr.tile_start);
+        ct = 0;
+        nf = (X + B4_TN - 1) / B4_TN;
+        In0 = uniform_ptr(fr.in);
+        Out0 = const_cast<float*>(uniform_ptr(fr.out));
+        Base0 = nullptr;
+        img_tiles = uniform_ptr(images + fr.img_off / 2);
+        fstride = B4_TN;
+    } else {
+        rt = lg % g.n_rt;
+        ct = (lg / g.n_rt) % g.n_ct;
+        const int fg = lg / (g.n_rt * g.n_ct);
+        const int f0 = fg * g.nf;
+        nf = min(g.nf, g.B - f0);
+        Z = g.Z;
+        X = g.X;
+        fstride = (size_t)Z * X;
+        In0 = In + (size_t)f0 * fstride;
+        Out0 = Out + (size_t)f0 * fstride;
+        Base0 = g.base ? g.base + (size_t)f0 * fstride : nullptr;
+        img_tiles = images;
+    }
+    const int K = g.K;
     const int h = (K - 1) >> 1;
     const int i0 = rt * B4_TZ;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int j = lane & 31, gk = lane >> 5;
     const int col = ct * B4_TN + 32 * wave + j;
-    const size_t fstride = (size_t)Z * X;
-    const uint32_t frame_bytes = (uint32_t)(fstride * sizeof(float));
+    // bytes addressable from frame (column tile) f's base: up to the image's end
+    auto frame_bytes = [&](int f) {
+        return (uint32_t)(((size_t)Z * X - (BATCH ? (size_t)f * B4_TN : 0)) * sizeof(float));
+    };
     const int row_bytes = X * 4;
     // byte offset of window row 8 gk of step 0 at this lane's column; rows
     // above or below the image fall outside the frame and read 0
     const int off0 = ((i0 - h + 8 * gk) * X + col) * 4;
-    const float* In0 = In + (size_t)f0 * fstride;
-    float* Out0 = Out + (size_t)f0 * fstride;
-    const float* Base0 = g.base ? g.base + (size_t)f0 * fstride : nullptr;
 
     auto frame_rsrc = [&](int f) {
         const int fu = __builtin_amdgcn_readfirstlane(f < nf ? f : 0);
-        return make_rsrc(uniform_ptr(In0 + (size_t)fu * fstride), frame_bytes);
+        return make_rsrc(uniform_ptr(In0 + (size_t)fu * fstride), frame_bytes(fu));
     };
-    auto load8 = [&](__amdgpu_buffer_rsrc_t rs, int s, bool valid, float(&x)[8]) {
+    // rows of window step s of frame (batch: column tile) f; in a batch, lanes
+    // whose column lies past X in that column tile read nothing (their offset
+    // leaves the range), so the ragged edge costs no traffic
+    auto load8 = [&](__amdgpu_buffer_rsrc_t rs, int s, bool valid, float(&x)[8], int f) {
         const int so = __builtin_amdgcn_readfirstlane(valid ? s * 16 * row_bytes : INT32_MIN - off0);
-        const int o = off0 + so;
+        int o = off0 + so;
+        if constexpr (BATCH) o = f * B4_TN + col < X ? o : INT32_MIN;
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = buffer_load_f32(rs, o + e * row_bytes);
     };
@@ -959,7 +1028,7 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         float ring[PD][8];
         {
             const auto rs0 = frame_rsrc(0);
-            const uint16_t* img = images + (size_t)rt * (b4_image_bytes(NSB) / 2);
+            const uint16_t* img = img_tiles + (size_t)rt * (b4_image_bytes(NSB) / 2);
             const auto rs = make_rsrc(img, (uint32_t)b4_image_bytes(NSB));
             auto copy_block = [&](int k) {
 #pragma unroll
@@ -972,10 +1041,10 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
             };
             // what the first iteration needs goes first: its input rows and
             // the first block, then the other prefetched rows and blocks
-            load8(rs0, step_of(0), true, ring[0]);
+            load8(rs0, step_of(0), true, ring[0], 0);
             copy_block(0);
 #pragma unroll
-            for (int u = 1; u < PD - 1; ++u) load8(rs0, step_of(u), true, ring[u]);
+            for (int u = 1; u < PD - 1; ++u) load8(rs0, step_of(u), true, ring[u], 0);
 #pragma unroll
             for (int k = 1; k < 4; ++k) copy_block(k);
         }
@@ -1020,7 +1089,8 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         // D row 8 (i / 4) + 4 gk + i % 4 of block b is tile row 32 b + that.
         // Every store is issued: rows below the image lie past the frame's last
         // byte and columns past X start at INT32_MIN, so the range check drops both.
-        const int vstart = col < X ? ((i0 + 4 * gk) * X + col) * 4 : INT32_MIN;
+        const int vbase = ((i0 + 4 * gk) * X + col) * 4;
+        const int vstart = col < X ? vbase : INT32_MIN;
         const bool has_base = Base0 != nullptr;
         const bool plain = g.alpha == 1.0f && !has_base;  // results stored as accumulated
         // base values of the block to be stored two iterations on (two buffers:
@@ -1032,8 +1102,8 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
             for (int i = 0; i < 16; ++i) bv[u][i] = 0.0f;
         // offset of block b's first result row; rebuilt from opaque values at
         // each use, else the compiler hoists all 64 offsets out of the frame loop
-        auto block_offsets = [&](int b, int(&voff)[16]) {
-            int o = vstart, rb = row_bytes;
+        auto block_offsets = [&](int b, int f, int(&voff)[16]) {
+            int o = BATCH ? (f * B4_TN + col < X ? vbase : INT32_MIN) : vstart, rb = row_bytes;
             asm volatile("" : "+v"(o), "+s"(rb));
             o += 32 * b * rb;
 #pragma unroll
@@ -1045,13 +1115,13 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         auto frame_out = [&](int f, const float* P) {
             // frames before the first or past the last: no record, every access dropped
             const int fu = __builtin_amdgcn_readfirstlane(f >= 0 && f < nf ? f : 0);
-            return make_rsrc(uniform_ptr(P + (size_t)fu * fstride), f >= 0 && f < nf ? frame_bytes : 0u);
+            return make_rsrc(uniform_ptr(P + (size_t)fu * fstride), f >= 0 && f < nf ? frame_bytes(fu) : 0u);
         };
         auto load_base = [&](int b, int f, float(&dst)[16]) {
             if (has_base) {
                 const auto rs_b = frame_out(f, Base0);
                 int voff[16];
-                block_offsets(b, voff);
+                block_offsets(b, f, voff);
 #pragma unroll
                 for (int i = 0; i < 16; ++i) dst[i] = buffer_load_f32(rs_b, voff[i]);
             }
@@ -1059,7 +1129,7 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         auto store_block = [&](int b, int f, floatx16& a, const float(&bsrc)[16]) {
             const auto rs_o = frame_out(f, Out0);
             int voff[16];
-            block_offsets(b, voff);
+            block_offsets(b, f, voff);
             if (plain) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
@@ -1087,9 +1157,9 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
                     if (f == 0) band_ready(std::integral_constant<int, I / 2>{});
                 // prefetch the iteration PD - 1 ahead (of this frame or the next)
                 if constexpr (I + PD - 1 < NW)
-                    load8(rs_cur, step_of(I + PD - 1), true, ring[(I + PD - 1) % PD]);
+                    load8(rs_cur, step_of(I + PD - 1), true, ring[(I + PD - 1) % PD], f);
                 else
-                    load8(rs_nxt, step_of(I + PD - 1 - NW), nxt_valid, ring[(I + PD - 1) % PD]);
+                    load8(rs_nxt, step_of(I + PD - 1 - NW), nxt_valid, ring[(I + PD - 1) % PD], f + 1);
                 // the last block of the previous frame (none before the first)
                 if constexpr (I == 0) store_block(block_of(3), f - 1, acc[block_of(3)], bv[1]);
                 // the k-th block of this frame, its last iteration just done
@@ -1294,11 +1364,11 @@ static void launch_b4_mode(const B4Geom& g, int nsb, const uint16_t* images, con
     const dim3 grid(g.n_blocks), block(B4_THREADS);
     const size_t lds = b4_image_bytes(nsb);
     switch (nsb) {
-        case 4: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 4>), grid, block, lds, stream, g, images, in, out); break;
-        case 6: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 6>), grid, block, lds, stream, g, images, in, out); break;
-        case 8: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 8>), grid, block, lds, stream, g, images, in, out); break;
-        case 10: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 10>), grid, block, lds, stream, g, images, in, out); break;
-        default: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 12>), grid, block, lds, stream, g, images, in, out); break;
+        case 4: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 4, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        case 6: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 6, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        case 8: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 8, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        case 10: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 10, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        default: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 12, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
     }
 }
 // images: the four-block band images of the operator's mode, tile rt at
@@ -1810,6 +1880,118 @@ extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32
     return st;
 }
 
+// Four-block ragged batch: byte offset of every frame's forward band images
+// after the frame table, and the total (0 when K does not fit the tile or
+// there are too many 128-row tiles for one launch).
+static size_t b4_batch_layout(const tidas_frame* frames, int32_t n_frames, int32_t K, std::vector<int64_t>* offs,
+                              int64_t* tiles) {
+    if (!b4_image_ok(K) || n_frames < 1) return 0;
+    size_t off = tidas_batch_workspace_bytes(n_frames);
+    int64_t t = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const int Z = frames[f].grid.nz;
+        if (Z < 1 || frames[f].grid.nx < 1) return 0;
+        if (offs) offs->push_back((int64_t)off);
+        off += b4_bytes(K, Z, 1);
+        t += (Z + B4_TZ - 1) / B4_TZ;
+    }
+    if (t > 65535) return 0;
+    if (tiles) *tiles = t;
+    return off;
+}
+
+extern "C" size_t tidas_apply_batch_workspace_bytes(const tidas_frame* frames, int32_t n_frames, int32_t K) {
+    if (!frames || n_frames < 1 || K < 1 || (K % 2) == 0) return 0;
+    const size_t four = b4_batch_layout(frames, n_frames, K, nullptr, nullptr);
+    return std::max(four, tidas_batch_workspace_bytes(n_frames));
+}
+
+// Four-block batch, step 1: validate, upload the frame table (tile_start in
+// 128-row tiles, img_off the frame's band images) and prepare every frame's
+// forward band images in the workspace.  *tiles receives the tile count.
+static int32_t b4_batch_prepare(const char* name, const tidas_frame* frames, int32_t n_frames, int32_t K,
+                                void* workspace, size_t workspace_bytes, int64_t* tiles, hipStream_t s) {
+    std::vector<int64_t> offs;
+    const size_t need = b4_batch_layout(frames, n_frames, K, &offs, tiles);
+    if (need == 0)
+        return fail(TIDAS_EUNSUPPORTED,
+                    std::string(name) + ": the four-block batch needs K <= 161 and at most 65535 tiles of 128 rows");
+    if (workspace_bytes < need)
+        return fail(TIDAS_EINVAL, std::string(name) + ": workspace too small for the four-block batch "
+                                                      "(see tidas_apply_batch_workspace_bytes)");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(TIDAS_EINVAL, std::string(name) + ": the four-block batch needs a 256-byte aligned workspace");
+    std::vector<ConvFrameDev> tab(n_frames);
+    int64_t t0 = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const tidas_frame& fr = frames[f];
+        const int Z = fr.grid.nz, X = fr.grid.nx;
+        if (!b4_fits(K, Z, X)) return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": frame too large for the tile path");
+        if (fr.in == fr.out || (const void*)fr.kernels == (const void*)fr.out)
+            return fail(TIDAS_EINVAL, std::string(name) + ": output aliases an input");
+        tab[f] = ConvFrameDev{fr.kernels, fr.in, fr.out, Z, X, 0, 0, t0, offs[f]};
+        t0 += (Z + B4_TZ - 1) / B4_TZ;
+    }
+    // hipMemcpyAsync from pageable memory returns once the source is staged
+    int32_t st = check_hip(hipMemcpyAsync(workspace, tab.data(), sizeof(ConvFrameDev) * n_frames,
+                                          hipMemcpyHostToDevice, s),
+                           "four-block batch: table upload");
+    if (st) return st;
+    const int nsb = b4_nsb(K);
+    const int per_tile = 4 * 32 * b4_lstride(nsb);
+    hipLaunchKernelGGL(b4_batch_prepare_kernel, dim3((unsigned)((per_tile + 255) / 256), (unsigned)*tiles), dim3(256),
+                       0, s, (const ConvFrameDev*)workspace, n_frames, K, nsb, (uint16_t*)workspace);
+    return check_launch(name);
+}
+
+// Four-block batch, step 2: one workgroup per 128-row tile of every frame.
+static int32_t b4_batch_launch(const char* name, int32_t n_frames, int32_t K, const void* workspace, int64_t tiles,
+                               hipStream_t s) {
+    B4Geom g{};
+    g.K = K;
+    g.n_blocks = (int32_t)tiles;
+    g.alpha = 1.0f;
+    g.beta = 0.0f;
+    const dim3 grid((unsigned)tiles), block(B4_THREADS);
+    const int nsb = b4_nsb(K);
+    const size_t lds = b4_image_bytes(nsb);
+    const ConvFrameDev* d = (const ConvFrameDev*)workspace;
+    const uint16_t* img = (const uint16_t*)workspace;
+    switch (nsb) {
+        case 4: hipLaunchKernelGGL((tidas_b4_kernel<false, 4, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        case 6: hipLaunchKernelGGL((tidas_b4_kernel<false, 6, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        case 8: hipLaunchKernelGGL((tidas_b4_kernel<false, 8, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        case 10: hipLaunchKernelGGL((tidas_b4_kernel<false, 10, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        default: hipLaunchKernelGGL((tidas_b4_kernel<false, 12, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+    }
+    return check_launch(name);
+}
+
+extern "C" int32_t tidas_apply_batch_prepare(const tidas_frame* frames, int32_t n_frames, int32_t K, void* workspace,
+                                             size_t workspace_bytes, void* stream) {
+    int32_t st = validate_batch("tidas_apply_batch_prepare", frames, n_frames, workspace, workspace_bytes, false, true);
+    if (st) return st;
+    if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_apply_batch_prepare: K must be odd and >= 1");
+    int64_t tiles = 0;
+    return b4_batch_prepare("tidas_apply_batch_prepare", frames, n_frames, K, workspace, workspace_bytes, &tiles,
+                            (hipStream_t)stream);
+}
+
+extern "C" int32_t tidas_apply_batch_prepared(const tidas_frame* frames, int32_t n_frames, int32_t K,
+                                              const void* workspace, size_t workspace_bytes, void* stream) {
+    int32_t st = validate_batch("tidas_apply_batch_prepared", frames, n_frames, const_cast<void*>(workspace),
+                                workspace_bytes, false, true);
+    if (st) return st;
+    if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_apply_batch_prepared: K must be odd and >= 1");
+    int64_t tiles = 0;
+    const size_t need = b4_batch_layout(frames, n_frames, K, nullptr, &tiles);
+    if (need == 0)
+        return fail(TIDAS_EUNSUPPORTED, "tidas_apply_batch_prepared: the four-block batch needs K <= 161 and at "
+                                        "most 65535 tiles of 128 rows");
+    if (workspace_bytes < need) return fail(TIDAS_EINVAL, "tidas_apply_batch_prepared: workspace too small");
+    return b4_batch_launch("tidas_apply_batch_prepared", n_frames, K, workspace, tiles, (hipStream_t)stream);
+}
+
 extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames, int32_t K, void* workspace,
                                      size_t workspace_bytes, int32_t variant, void* stream) {
     int32_t st = validate_batch("tidas_apply_batch", frames, n_frames, workspace, workspace_bytes, false, true);
@@ -1817,6 +1999,13 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
     if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_apply_batch: K must be odd and >= 1");
     if (variant < 0 || variant >= TIDAS_APPLY_BATCH_VARIANTS)
         return fail(TIDAS_EINVAL, "tidas_apply_batch: variant out of range");
+    if (variant == TIDAS_APPLY_BATCH_FOUR_BLOCK) {
+        int64_t tiles = 0;
+        if ((st = b4_batch_prepare("tidas_apply_batch", frames, n_frames, K, workspace, workspace_bytes, &tiles,
+                                   (hipStream_t)stream)))
+            return st;
+        return b4_batch_launch("tidas_apply_batch", n_frames, K, workspace, tiles, (hipStream_t)stream);
+    }
     // the same arithmetic as tidas_apply on each frame: the split-bfloat16
     // tiles when the band fits (a visit = one 64-row tile, all its columns),
     // else the float32 matrix-core tiles
@@ -1839,6 +2028,7 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
         tab[f].vec = (X % 4) == 0 && aligned16(fr.in) && aligned16(fr.out);
         tab[f].pad = 0;
         tab[f].tile_start = total;
+        tab[f].img_off = 0;
         total += (int64_t)((Z + TZ - 1) / TZ) * ((X + TN - 1) / TN);
     }
     hipStream_t s = (hipStream_t)stream;
@@ -1850,7 +2040,7 @@ extern "C" int32_t tidas_apply_batch(const tidas_frame* frames, int32_t n_frames
     const ConvFrameDev* d = (const ConvFrameDev*)workspace;
     if (bx) {
         // variants: workgroups per compute unit
-        static const int bx_per_cu[TIDAS_APPLY_BATCH_VARIANTS] = {1, 2, 3, 4, 6, 8};
+        static const int bx_per_cu[TIDAS_APPLY_BATCH_FOUR_BLOCK] = {1, 2, 3, 4, 6, 8};
         auto grid_for = [&](int64_t t) {
             const int64_t nb = std::max<int64_t>(8, std::min<int64_t>(t, (int64_t)n_cu * bx_per_cu[variant]));
             return (unsigned)((nb + 7) / 8 * 8);

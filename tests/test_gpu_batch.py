@@ -106,6 +106,38 @@ def test_full_size_ragged_batch_sampled_pixels(dev):
         assert rel(img[np.ix_(rows, cols)], ref) <= RTOL
 
 
+def test_full_size_ragged_line_model_four_block_variant(dev):
+    """The line model's four-block batch variant (band images of every frame
+    prepared in the workspace, one workgroup per 128-row tile walking the
+    frame's column tiles) on frames at the batching workload's extreme sizes
+    and ragged ones: the same bits as the persistent two-block variant and as
+    single launches; sampled rows against the oracle."""
+    shapes = [(2048, 512), (512, 256), (1500, 333), (129, 300), (640, 257)]
+    K = 65
+    kbs = [generators.normal((Z, K), seed=30 + i).astype(np.float32) for i, (Z, X) in enumerate(shapes)]
+    Rs = [generators.normal((Z, X), seed=40 + i).astype(np.float32) for i, (Z, X) in enumerate(shapes)]
+    kd = [g(k, dev) for k in kbs]
+    rd = [g(r, dev) for r in Rs]
+    four = td.apply_batch(kd, rd, variant=_lib.APPLY_BATCH_FOUR_BLOCK)
+    two = td.apply_batch(kd, rd, variant=0)
+    # prepared once, applied twice (the maps change between the calls)
+    pb = td.PreparedBatch(kd, rd)
+    first = [o.clone() for o in pb.apply()]
+    for r in rd:
+        r.mul_(-2.0)
+    second = pb.apply()
+    rng = np.random.default_rng(5)
+    for f, (Z, X) in enumerate(shapes):
+        assert torch.equal(first[f], four[f]), f
+        assert torch.equal(second[f], td.apply(kd[f], rd[f])), f
+        rd[f].mul_(-0.5)
+        assert torch.equal(four[f], two[f]), f
+        assert torch.equal(four[f], td.apply(kd[f], rd[f])), f
+        rows = np.sort(rng.choice(Z, 16, replace=False))
+        full = o_t.apply(kbs[f], Rs[f])
+        assert rel(four[f].cpu().numpy()[rows], full[rows]) <= RTOL
+
+
 def test_autotuner_picks_and_caches_a_variant(dev, tmp_path, monkeypatch):
     monkeypatch.setenv("TIDAS_TUNE_CACHE", str(tmp_path / "tune.json"))
     shapes = [(256, 256), (512, 300)]
