@@ -506,10 +506,14 @@ int32_t tidas_sq_norms(const float* a, const float* b, int64_t n, double* work, 
 /*
  * Born-approximation RF synthesis, Sec. 2 eqn:SRX with linear superposition:
  *   rf[a][n][k] = sum_s amp[s] * p(t0 + k/fs - tau_n(x_s, z_s; a))
- * accumulated in float64 and rounded once to float32.  scat is DEV
- * [n_scat][3] float64 rows (x, z, amplitude); rf DEV [A][C][n_samples]
- * (overwritten).  n_scat >= 0.  Allocates and frees a float64 accumulation
- * buffer of A*C*n_samples values, stream-ordered (TIDAS_ENOMEM possible).
+ * evaluated in float64, accumulated exactly in 64-bit fixed point (2^e units
+ * per unit amplitude, n_scat max|amp| 2^e < 2^61: each term carries an
+ * absolute error below 2^-(e+1)) and rounded once to float32.  The integer sum
+ * does not depend on the order of the additions, so the record is the same
+ * bits on every call.  scat is DEV [n_scat][3] float64 rows (x, z,
+ * amplitude); rf DEV [A][C][n_samples] (overwritten).  n_scat >= 0.
+ * Allocates and frees an accumulation buffer of A*C*n_samples + 1 eight-byte
+ * values, stream-ordered (TIDAS_ENOMEM possible).
  */
 int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* tx, const double* scat,
                           int32_t n_scat, int32_t n_samples, float* rf, void* stream);

@@ -215,8 +215,34 @@ __global__ __launch_bounds__(PAPER_THREADS) void paper_row_kernel(const Setup64 
 }
 
 // ------------------------------------------------------------ RF synthesis ----
+// Order-independent accumulation: every contribution amp * p(t) is rounded
+// once to a fixed-point integer with 2^e units per unit of amplitude and the
+// integers are summed with 64-bit integer atomics.  Integer addition is exact
+// and associative, so the sum (and the float32 record) does not depend on the
+// order in which threads add.  e is the largest exponent with
+// n_scat * max|amp| * 2^e < 2^61 (no sum can overflow, since |p| <= 1), so
+// each contribution carries an absolute error below 2^-(e+1): relative to the
+// largest possible sample, under n_scat * 2^-62.
+__global__ __launch_bounds__(256) void amp_scale_kernel(const double* __restrict__ scat, int32_t S,
+                                                        double* __restrict__ scale) {
+    __shared__ double red[4];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < S; i += 256) m = fmax(m, fabs(scat[3 * (int64_t)i + 2]));
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double top = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * (double)max(S, 1);
+        // 2^e with top * 2^e < 2^61; amplitudes of 0 (or none): any scale
+        int e = 0;
+        if (top > 0.0 && isfinite(top)) e = 60 - ilogb(top);
+        scale[0] = ldexp(1.0, max(min(e, 1000), -1000));
+    }
+}
+
 __global__ __launch_bounds__(256) void simulate_kernel(const Setup64 s, const double* __restrict__ scat, int32_t S,
-                                                       int32_t width, double* __restrict__ acc) {
+                                                       int32_t width, const double* __restrict__ scale,
+                                                       unsigned long long* __restrict__ acc) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;  // over (a, n, scatterer)
     const int64_t total = (int64_t)s.A * s.C * S;
     if (idx >= total) return;
@@ -227,19 +253,23 @@ __global__ __launch_bounds__(256) void simulate_kernel(const Setup64 s, const do
     const double xn = s.x_first + (double)n * s.pitch;
     const double tau = arrival(s, a, x, z, xn);
     const double half = 4.0 * s.sigma;
+    const double sc_amp = amp * scale[0];
     const int64_t k_lo = (int64_t)ceil((tau - half - s.t0) * s.fs);
-    double* row = acc + ((int64_t)a * s.C + n) * s.T;
+    unsigned long long* row = acc + ((int64_t)a * s.C + n) * s.T;
     for (int w = 0; w < width; ++w) {
         const int64_t k = k_lo + w;
         if (k < 0 || k >= s.T) continue;
-        const double v = amp * pulse_d(s.t0 + (double)k / s.fs - tau, s.fc, s.sigma);
-        if (v != 0.0) unsafeAtomicAdd(row + k, v);
+        const long long v = __double2ll_rn(sc_amp * pulse_d(s.t0 + (double)k / s.fs - tau, s.fc, s.sigma));
+        // two's complement: adding the bit pattern of a negative value modulo
+        // 2^64 is adding the value
+        if (v != 0) atomicAdd(row + k, (unsigned long long)v);
     }
 }
 
-__global__ __launch_bounds__(256) void round_kernel(const double* __restrict__ acc, int64_t n, float* __restrict__ rf) {
+__global__ __launch_bounds__(256) void round_kernel(const unsigned long long* __restrict__ acc, int64_t n,
+                                                    const double* __restrict__ scale, float* __restrict__ rf) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx < n) rf[idx] = (float)acc[idx];
+    if (idx < n) rf[idx] = (float)((double)(long long)acc[idx] / scale[0]);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(double* __restrict__ p, int64_t n) {
@@ -416,19 +446,27 @@ extern "C" int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* t
     hipStream_t strm = (hipStream_t)stream;
     const int64_t n = (int64_t)s.A * s.C * s.T;
     void* buf = nullptr;
-    if ((st = check_hip(hipMallocAsync(&buf, sizeof(double) * n, strm), "tidas_simulate_rf: accumulator"))) return st;
-    double* acc = (double*)buf;
-    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, acc, n);
+    // [fixed-point accumulator n x 8 bytes | scale (8 bytes)]
+    if ((st = check_hip(hipMallocAsync(&buf, sizeof(double) * (n + 1), strm), "tidas_simulate_rf: accumulator")))
+        return st;
+    unsigned long long* acc = (unsigned long long*)buf;
+    double* scale = (double*)buf + n;
+    // the all-zero bit pattern is the integer 0
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, (double*)buf, n);
     st = check_launch("tidas_simulate_rf(zero)");
+    if (!st) {
+        hipLaunchKernelGGL(amp_scale_kernel, dim3(1), dim3(256), 0, strm, scat, n_scat, scale);
+        st = check_launch("tidas_simulate_rf(scale)");
+    }
     const int width = (int)std::ceil(2.0 * 4.0 * s.sigma * s.fs) + 2;
     const int64_t work = (int64_t)s.A * s.C * n_scat;
     if (!st && work > 0) {
         hipLaunchKernelGGL(simulate_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, strm, s, scat, n_scat,
-                           width, acc);
+                           width, scale, acc);
         st = check_launch("tidas_simulate_rf(accumulate)");
     }
     if (!st) {
-        hipLaunchKernelGGL(round_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, acc, n, rf);
+        hipLaunchKernelGGL(round_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, acc, n, scale, rf);
         st = check_launch("tidas_simulate_rf(round)");
     }
     hipError_t e = hipFreeAsync(buf, strm);
