@@ -30,6 +30,7 @@
 // apodization are computed once per (pixel, element) and reused.
 #include <algorithm>
 #include <climits>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -385,6 +386,265 @@ __global__ __launch_bounds__(256) void fixed_das_kernel(const DasArgs p, const D
                     rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
 }
 
+// --------------------------------- fixed-delay beamformer, staged windows ----
+// One plane wave and groups of FB frames.  The time-invariant law makes a
+// row's read position in element n's channel u_k = U_k + E(j, n): a per-row
+// term U_k = fs (tau_tx(x_j, z_k) + z_k / c - t0), which grows by
+// fs dz (1 + cos a) / c per row, plus the receive excess E of the row's
+// reference depth, the same for every row of a run that shares the
+// reference.  So a wave (64 columns, lane = column, FL_RW consecutive rows)
+// reads, for one element, a single window of the channel, from the run's
+// first row to its last, over the lanes inside the element's aperture.  A
+// superset of it (bounded from the columns' extent and the aperture, with a
+// margin of two samples) is copied into the wave's LDS by direct-to-LDS
+// loads, FL_LMAX / 64 loads of 64 consecutive samples per frame (samples
+// outside the record read 0), FL_DEPTH - 1 elements ahead of the one being
+// summed; every pair of the run then reads its two samples from LDS: no
+// per-pair gathers, and the law (square root, reciprocal, Hann weight) once
+// per (column, element, run).  The ring slots are distinct LDS arrays, so
+// the compiler sees that a read of one slot does not depend on the copies
+// still landing in the others, and the wait before each element's sum is
+// the explicit one (its loads done, the later ones in flight).  Runs of
+// equal reference inside a wave are walked one after the other (a wave
+// whose rows all differ stages one window per row).  A window longer than
+// FL_LMAX samples is read from global memory pair by pair instead.  The
+// index split, the law and the sum of each pair are those of the DAS kernel
+// with FB > 1, so self-referenced rows give DAS's bits.
+constexpr int FL_RW = 16;     // rows per wave
+constexpr int FL_LMAX = 256;  // samples per staged window (one frame, one slot)
+constexpr int FL_PIECES = FL_LMAX / 64;
+constexpr int FL_DEPTH = 4;   // ring slots: the element being summed and the next three
+constexpr int FL_WAVES = 4;   // waves per workgroup, stacked in depth
+
+template <int N, typename F, int... I>
+__device__ __forceinline__ void fl_static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void fl_static_for(F&& f) {
+    fl_static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+template <int FB>
+__global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasGrid gr, const int32_t* __restrict__ ref,
+                                                     const float* __restrict__ theta, const float* __restrict__ rf,
+                                                     float* __restrict__ img) {
+    static_assert(FL_DEPTH == 4, "four ring slots below");
+    // ring slots, one array each: [wave][frame][FL_LMAX]
+    __shared__ float fl_s0[FL_WAVES * FB * FL_LMAX];
+    __shared__ float fl_s1[FL_WAVES * FB * FL_LMAX];
+    __shared__ float fl_s2[FL_WAVES * FB * FL_LMAX];
+    __shared__ float fl_s3[FL_WAVES * FB * FL_LMAX];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int i_base = (blockIdx.x * FL_WAVES + wave) * FL_RW;
+    if (i_base >= gr.nz) return;  // wave-uniform: the kernel has no barrier
+    const int fr0 = blockIdx.z * FB;
+    const int nfr = min(FB, p.n_frames - fr0);
+    const size_t frame_rf = (size_t)p.C * p.T;
+    const size_t frame_img = (size_t)gr.nz * gr.nx;
+    const float* rf0 = rf + fr0 * frame_rf;
+    float* img0 = img + fr0 * frame_img;
+    const int wo = wave * FB * FL_LMAX;
+    auto slot = [&](auto D_) -> float* {
+        constexpr int d = decltype(D_)::value;
+        if constexpr (d == 0) return fl_s0 + wo;
+        else if constexpr (d == 1) return fl_s1 + wo;
+        else if constexpr (d == 2) return fl_s2 + wo;
+        else return fl_s3 + wo;
+    };
+    const int j_base = blockIdx.y * 64;
+    const int j = j_base + lane;
+
+    const double xd = gr.x0 + (double)min(j, gr.nx - 1) * gr.dx;
+    const double ox = xd - p.x_first;
+    const float dx0 = (float)ox, dx0_lo = (float)(ox - (double)dx0);
+    const float pitch_f = (float)p.pitch, pitch_lo = (float)(p.pitch - (double)pitch_f);
+    const double sa = p.sin_a[0], ca = p.cos_a[0];
+    int q[FL_RW];
+    float fp[FL_RW];
+#pragma unroll
+    for (int k = 0; k < FL_RW; ++k) {
+        const double zd = gr.z0 + (double)min(i_base + k, gr.nz - 1) * gr.dz;
+        const double U = p.fs * ((xd * sa + zd * ca) / p.c + zd / p.c - p.t0);
+        const double Uf = floor(U);
+        q[k] = (int)Uf;
+        fp[k] = (float)(U - Uf);
+    }
+    float acc[FL_RW][FB];
+#pragma unroll
+    for (int k = 0; k < FL_RW; ++k)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) acc[k][f] = 0.0f;
+
+    // reference row of row i (rows past the image take the wave's first
+    // row's), clamped into the image; wave-uniform
+    auto ref_of = [&](int i) {
+        const int ii = i < gr.nz ? i : i_base;
+        const int r = ref ? ref[ii] : ii;
+        return __builtin_amdgcn_readfirstlane(min(max(r, 0), gr.nz - 1));
+    };
+    const uint32_t row_bytes = (uint32_t)p.T * 4u;
+    auto chan = [&](int f, int n, bool live) {
+        const bool fv = live && f < nfr;
+        return make_rsrc(rf0 + (fv ? f : 0) * frame_rf + (size_t)(live ? n : 0) * p.T, fv ? row_bytes : 0u);
+    };
+    // the wave's columns, relative to element 0 (uniform)
+    const int j_end = min(j_base + 63, gr.nx - 1);
+    const float xl0 = (float)(gr.x0 + (double)j_base * gr.dx - p.x_first);
+    const float xh0 = (float)(gr.x0 + (double)j_end * gr.dx - p.x_first);
+    auto U_at = [&](double x, int k) {
+        const double zd = gr.z0 + (double)min(i_base + k, gr.nz - 1) * gr.dz;
+        return p.fs * ((x * sa + zd * ca) / p.c + zd / p.c - p.t0);
+    };
+    const double x_lo = gr.x0 + (double)j_base * gr.dx, x_hi = gr.x0 + (double)j_end * gr.dx;
+
+#pragma unroll 1
+    for (int k0 = 0; k0 < FL_RW;) {
+        const int r = ref_of(i_base + k0);
+        int k1 = k0;
+        while (k1 + 1 < FL_RW && ref_of(i_base + k1 + 1) == r) ++k1;
+        const double zr = gr.z0 + (double)r * gr.dz;
+        const float zrf = (float)zr, z2 = (float)(zr * zr);
+        const bool on = (j < gr.nx) && (zr > 0.0);
+        const float inv_az = on ? (float)(2.0 * p.fnumber / zr) : 0.0f;
+        const double a_ap = zr / (2.0 * p.fnumber);
+        const float a_f = (float)a_ap;
+        int n_lo = 0, n_hi = -1;
+        if (zr > 0.0) {
+            n_lo = max(0, (int)floor((x_lo - a_ap - p.x_first) / p.pitch));
+            n_hi = min(p.C - 1, (int)ceil((x_hi + a_ap - p.x_first) / p.pitch));
+        }
+        // lowest read position of the run's first row and highest of its last
+        // row over the wave's columns, before the receive excess
+        const float U_first = (float)fmin(U_at(x_lo, k0), U_at(x_hi, k0));
+        const float U_last = (float)fmax(U_at(x_lo, k1), U_at(x_hi, k1));
+        // receive excess at lateral distance d (float; the window keeps a
+        // margin of two samples for the rounding)
+        auto excess = [&](float d) { return p.kappa * (d * d) / (__builtin_amdgcn_sqrtf(fmaf(d, d, z2)) + zrf); };
+
+        struct Win {
+            float w, e;
+            int lo, len;  // len 0: no lane in the aperture (or n past the run); len > FL_LMAX: read pair by pair
+        };
+        // element n's law (per lane), window (uniform) and its copy into slot
+        // S: every call issues FL_PIECES loads per frame (dummy ones, which read
+        // nothing, for an element past the run, out of reach or not staged)
+        auto prep = [&](int n, auto S_) {
+            Win W{0.0f, 0.0f, 0, 0};
+            if (n <= n_hi) {
+                const float nf = (float)n;
+                const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
+                const float t = fabsf(dx) * inv_az;
+                const float wh = hann_weight(fminf(t, 1.0f));
+                W.w = (on && t <= 1.0f) ? wh : 0.0f;
+                const float rho = __builtin_amdgcn_sqrtf(fmaf(dx, dx, z2));
+                W.e = p.kappa * (dx * dx) * __builtin_amdgcn_rcpf(rho + zrf);
+                const float xn = nf * pitch_f;  // element n relative to element 0
+                const float dl = xl0 - xn, dh = xh0 - xn;
+                const float d_near = (dl <= 0.0f && dh >= 0.0f) ? 0.0f : fminf(fabsf(dl), fabsf(dh));
+                const float d_far = fminf(a_f, fmaxf(fabsf(dl), fabsf(dh)));
+                if (d_near <= a_f * 1.0001f + 1e-9f) {
+                    W.lo = __builtin_amdgcn_readfirstlane((int)floorf(U_first + excess(d_near)) - 2);
+                    const int hi = __builtin_amdgcn_readfirstlane((int)floorf(U_last + excess(d_far)) + 3);
+                    W.len = hi - W.lo + 1;
+                }
+            }
+            const bool staged = W.len > 0 && W.len <= FL_LMAX;
+            float* dst = slot(S_);
+#pragma unroll
+            for (int c = 0; c < FL_PIECES; ++c)
+#pragma unroll
+                for (int f = 0; f < FB; ++f)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        chan(f, n, staged), (__attribute__((address_space(3))) void*)(dst + f * FL_LMAX + 64 * c), 4,
+                        (W.lo + 64 * c + lane) * 4, 0, 0, 0);
+            return W;
+        };
+        // sum element n of the run from slot S (or pair by pair from the record)
+        auto sum = [&](int n, auto S_, const Win& W) {
+            if (W.len == 0) return;
+            const float w = W.w;
+            if (W.len <= FL_LMAX) {
+                const float* ws = slot(S_);
+#pragma unroll
+                for (int k = 0; k < FL_RW; ++k) {
+                    if (k < k0 || k > k1) continue;  // wave-uniform
+                    const float v = fp[k] + W.e;
+                    const float qf = floorf(v);
+                    const float fr = v - qf;
+                    const int idx = w != 0.0f ? q[k] + (int)qf - W.lo : 0;
+                    const float wa = w * (1.0f - fr), wbb = w * fr;
+#pragma unroll
+                    for (int f = 0; f < FB; ++f) {
+                        const float s0 = ws[f * FL_LMAX + idx];
+                        const float s1 = ws[f * FL_LMAX + idx + 1];
+                        acc[k][f] = fmaf(wbb, s1, fmaf(wa, s0, acc[k][f]));
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < FL_RW; ++k) {
+                    if (k < k0 || k > k1) continue;
+                    const float v = fp[k] + W.e;
+                    const float qf = floorf(v);
+                    const float fr = v - qf;
+                    const int off = (q[k] + (int)qf) * 4;
+                    const float wa = w * (1.0f - fr), wbb = w * fr;
+#pragma unroll
+                    for (int f = 0; f < FB; ++f) {
+                        const auto rs = chan(f, n, true);
+                        const float s0 = buffer_load_f32(rs, off);
+                        const float s1 = buffer_load_f32(rs, off + 4);
+                        acc[k][f] = fmaf(wbb, s1, fmaf(wa, s0, acc[k][f]));
+                    }
+                }
+            }
+        };
+        if (n_lo <= n_hi) {
+            Win ring[FL_DEPTH];
+            fl_static_for<FL_DEPTH - 1>([&](auto D_) {
+                constexpr int d = decltype(D_)::value;
+                ring[d] = prep(n_lo + d, D_);
+            });
+#pragma unroll 1
+            for (int n0 = n_lo; n0 <= n_hi; n0 += FL_DEPTH) {
+                fl_static_for<FL_DEPTH>([&](auto D_) {
+                    constexpr int d = decltype(D_)::value;
+                    constexpr int sl_next = (d + FL_DEPTH - 1) % FL_DEPTH;
+                    const int n = n0 + d;
+                    if (n <= n_hi) {
+                        // the reads of the slot about to be refilled (element n - 1) are done
+                        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+                        ring[sl_next] = prep(n + FL_DEPTH - 1, std::integral_constant<int, sl_next>{});
+                        // element n's copy has landed: only the FL_DEPTH - 1 later
+                        // elements' loads may still be outstanding
+                        constexpr int later = (FL_DEPTH - 1) * FL_PIECES * FB;
+                        static_assert(later <= 63, "vmcnt range");
+                        __builtin_amdgcn_s_waitcnt((later & 15) | ((later >> 4) << 14) | 0x70 | 0xF00);
+                        sum(n, D_, ring[d]);
+                    }
+                });
+            }
+            // the loads issued for elements past the run read nothing: drain them
+            __builtin_amdgcn_s_waitcnt(0x070);
+        }
+        k0 = k1 + 1;
+    }
+    if (j < gr.nx) {
+#pragma unroll
+        for (int k = 0; k < FL_RW; ++k) {
+            const int i = i_base + k;
+            if (i < gr.nz) {
+                const float th = theta ? theta[i] : 1.0f;
+#pragma unroll
+                for (int f = 0; f < FB; ++f)
+                    if (f < nfr) img0[f * frame_img + (size_t)i * gr.nx + j] = th * acc[k][f];
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------- batches ----
 // Ragged batch: every frame has its own grid, RF record and image.  One
 // persistent launch covers the tiles (WAVES wave tiles stacked in depth) of
@@ -541,8 +801,15 @@ extern "C" int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, 
     // 2 rows 0.64 ms, x 4 rows 0.78, x 8 rows 0.82 (166 registers)
     const bool multi = n_frames >= 8;
     if (p.A == 1) {
-        if (multi) launch_fixed_das<4, 1, 2>(p, gr, ref_row, theta, rf, image, s);
-        else launch_fixed_das<1, 1, 4>(p, gr, ref_row, theta, rf, image, s);
+        if (multi) {
+            // groups of four frames: the staged-window kernel
+            constexpr int FB = 4;
+            const dim3 grid((gr.nz + FL_WAVES * FL_RW - 1) / (FL_WAVES * FL_RW), (gr.nx + 63) / 64,
+                            (n_frames + FB - 1) / FB);
+            hipLaunchKernelGGL(fd_lds_kernel<FB>, grid, dim3(FL_WAVES * 64), 0, s, p, gr, ref_row, theta, rf, image);
+        } else {
+            launch_fixed_das<1, 1, 4>(p, gr, ref_row, theta, rf, image, s);
+        }
     } else if (p.A == 11) {
         launch_fixed_das<1, 11, 4>(p, gr, ref_row, theta, rf, image, s);
     } else {

@@ -136,3 +136,51 @@ def test_clinical_size_batch_sampled(dev):
             got.append(img[b, i, j])
             want.append(theta[i] * one)
         assert rel(got, want) <= RTOL
+
+
+def test_staged_window_kernel_own_rows_are_das_bits(dev):
+    """Eight or more frames of one plane wave take the staged-window kernel:
+    with every row its own reference (runs of one row) it gives DAS's bits."""
+    s = config(1).with_grid(200, 96)
+    rf = np.stack([point_rf(s, 200 + b) for b in range(8)])
+    rd = g(rf, dev)
+    assert torch.equal(td.tidas_beamform(rd, s), td.das_beamform(rd, s))
+
+
+@pytest.mark.parametrize("size", [1, 16, 64, 1000, -1])
+def test_staged_window_kernel_matches_oracle(dev, size):
+    """Neighbourhoods of 1 / 16 / 64 / all rows, and scattered references
+    (size -1: a random map with references outside the image, clamped), on 9
+    frames; theta applied."""
+    s = config(1).with_grid(300, 130)
+    B = 9
+    rf = np.stack([point_rf(s, 300 + b) for b in range(B)])
+    if size > 0:
+        refs = neighbourhood_refs(s.nz, size)
+    else:
+        refs = np.random.default_rng(8).integers(-20, s.nz + 20, s.nz).astype(np.int32)
+    theta = (1.0 + 0.3 * generators.normal(s.nz, seed=9)).astype(np.float32)
+    img = td.tidas_beamform(g(rf, dev), s, ref_row=g(refs, dev, np.int32), theta=g(theta, dev)).cpu().numpy()
+    xs, zs = axes(s)
+    for b in (0, 4, B - 1):
+        ref = o_das.fixed_delay_das(rf[b], xs, zs, np.clip(refs, 0, s.nz - 1), **das_kw(s), theta=theta)
+        assert rel(img[b], ref) <= RTOL
+        assert np.max(np.abs(img[b] - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def test_staged_window_kernel_edge_grids(dev):
+    base = config(1).replace(n_samples=1500)
+    frames = []
+    for b in range(8):
+        x, z, a = generators.point_scatterers(20, base.field_w, 25e-3, seed=70 + b)
+        frames.append(o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **sim_kw(base))))
+    rf = np.stack(frames)
+    for s in (base.replace(nz=70, nx=3, z0=-2e-3, dz=0.1e-3, x0=-1e-3, dx=1e-3),
+              base.replace(nz=65, nx=1, z0=5e-3, dz=0.2e-3, x0=0.0, dx=1e-4),
+              base.replace(nz=1, nx=77, z0=11e-3, dz=1e-4, x0=-9e-3, dx=0.23e-3),
+              base.replace(nz=37, nx=200, z0=30e-3, dz=0.3e-3, x0=-15e-3, dx=0.15e-3)):
+        refs = neighbourhood_refs(s.nz, 16)
+        img = td.tidas_beamform(g(rf, dev), s, ref_row=g(refs, dev, np.int32)).cpu().numpy()
+        xs, zs = axes(s)
+        for b in (0, 7):
+            assert rel(img[b], o_das.fixed_delay_das(rf[b], xs, zs, refs, **das_kw(s))) <= RTOL
