@@ -40,6 +40,18 @@
  * default stream) and is asynchronous: execution errors surface at the
  * caller's next synchronisation.  Outputs must not overlap inputs.
  *
+ * Device scratch.  Entry points that need scratch memory take (workspace,
+ * workspace_bytes) and have a size query named <entry point>_workspace_bytes:
+ * workspace DEV, 256-byte aligned, at least the queried size, owned by the
+ * caller and not retained; or workspace = NULL with workspace_bytes = 0, in
+ * which case the call allocates the scratch stream-ordered (hipMallocAsync /
+ * hipFreeAsync on `stream`; TIDAS_ENOMEM possible).  With a caller workspace
+ * no call below allocates device memory, except the unprepared line-model
+ * calls (tidas_apply, tidas_adjoint and their _ex forms), which keep their
+ * signatures and convert the bank into band images in a stream-ordered
+ * temporary; tidas_prepare with a caller buffer (tidas_prepared_bytes) and
+ * tidas_apply_noalloc are their allocation-free forms.
+ *
  * Return codes: 0 = OK; TIDAS_EINVAL (-1) invalid argument, checked before
  * any work is enqueued, in which case nothing is written; TIDAS_EHIP (-2) a
  * HIP runtime or launch error; TIDAS_ENOMEM (-3) a temporary device
@@ -177,13 +189,16 @@ int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, const tidas
  *   (0 when that value is 0), for tidas_apply_lateral.
  * kernels DEV [nz][K]; theta DEV [nz] or NULL (exact and lateral modes write 1).
  * ref_row HOST [nz] with 0 <= ref_row[i] < nz, or NULL.  K odd, >= 1.
- * Paper and line modes allocate and free a small temporary device buffer,
- * stream-ordered (TIDAS_ENOMEM possible), uploads the row -> reference map,
- * and returns only after the stream has drained (synchronous).
+ * Paper and line modes need scratch (reference responses and the row ->
+ * reference map, tidas_build_kernels_workspace_bytes; exact and lateral modes
+ * need none) and upload the map from a host copy that a host function queued
+ * on `stream` releases: the call does not wait for the stream.
  */
+size_t tidas_build_kernels_workspace_bytes(int32_t nz, int32_t K, int32_t mode);
 int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                             const tidas_grid* grid, int32_t n_samples, int32_t K, int32_t mode,
-                            const int32_t* ref_row, float* kernels, float* theta, void* stream);
+                            const int32_t* ref_row, float* kernels, float* theta, void* workspace,
+                            size_t workspace_bytes, void* stream);
 
 /*
  * The tiDAS line model, Sec. 2.4 eqn:line_conv, applied to a reflectivity
@@ -242,14 +257,16 @@ int32_t tidas_apply_lateral(const float* kernels_x, int32_t K, const float* in, 
  * into three bfloat16 parts, six products, float32 sums) when X % 4 == 0 and
  * both inputs are 16-byte aligned, float32 otherwise; partial sums over
  * fixed ranges of (frame, column) added in double in a fixed order (bit-
- * reproducible on one device type); a stream-ordered temporary buffer holds
- * the partial sums (about 2 x compute units x 128 Z K / ceil(Z / 128) bytes).
+ * reproducible on one device type); the workspace holds the partial sums
+ * (tidas_kernel_grad_workspace_bytes, for the current device: about 2 x
+ * compute units x 128 Z K / ceil(Z / 128) bytes).
  * Non-finite inputs: the float32 kernel propagates Inf and NaN as float32
  * arithmetic does; on the split-bfloat16 path an infinite input gives NaN
  * (its parts are Inf - Inf).
  */
+size_t tidas_kernel_grad_workspace_bytes(int32_t K, int32_t B, int32_t Z, int32_t X);
 int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* image_bar, int32_t B, int32_t Z, int32_t X,
-                          float* kernels_bar, void* stream);
+                          float* kernels_bar, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Which kernel tidas_kernel_grad runs for X columns and the two input
@@ -343,20 +360,25 @@ int32_t tidas_adjoint_prepared(const void* prepared, int32_t K, const float* ima
  * pairwise distinct; r receives the result, work is scratch.  lam >= 0,
  * eta > 0 (for convergence eta < 2 / (||A||^2 + lam); see
  * tidas_operator_norm_sq).  The step operators, their band images and c (and
- * N c + c) live in one stream-ordered temporary buffer (about 2 frames plus
- * 60 Z K bytes; TIDAS_ENOMEM possible).
+ * N c + c) live in the workspace (tidas_deconvolve_workspace_bytes: about 2
+ * frames plus 60 Z K bytes; 0 for kernels too long for the tile).
  */
+size_t tidas_deconvolve_workspace_bytes(int32_t K, int32_t B, int32_t Z, int32_t X);
 int32_t tidas_deconvolve(const float* kernels, int32_t K, const float* y, int32_t B, int32_t Z, int32_t X,
-                         float lam, float eta, int32_t iters, float* r, float* work, void* stream);
+                         float lam, float eta, int32_t iters, float* r, float* work, void* workspace,
+                         size_t workspace_bytes, void* stream);
 
 /*
  * Largest eigenvalue of A^T A for the Z x Z column operator of the line model
  * (= squared largest singular value), by `iters` steps of power iteration
- * from the all-ones vector.  work DEV with room for 3 Z + 4 floats; *out is a
- * HOST double, written after the call synchronises the stream.
+ * from the all-ones vector.  work DEV with room for 3 Z + 4 floats; the
+ * workspace holds the bank's band images (tidas_operator_norm_sq_workspace_bytes,
+ * 0 when the bank takes the float32 path); *out is a HOST double, written
+ * after the call synchronises the stream (the result is a host value).
  */
+size_t tidas_operator_norm_sq_workspace_bytes(int32_t K, int32_t Z);
 int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32_t Z, int32_t iters, float* work, double* out,
-                               void* stream);
+                               void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Ragged batches.  Each frame has its own image grid and buffers; the array,
@@ -511,12 +533,14 @@ int32_t tidas_sq_norms(const float* a, const float* b, int64_t n, double* work, 
  * absolute error below 2^-(e+1)) and rounded once to float32.  The integer sum
  * does not depend on the order of the additions, so the record is the same
  * bits on every call.  scat is DEV [n_scat][3] float64 rows (x, z,
- * amplitude); rf DEV [A][C][n_samples] (overwritten).  n_scat >= 0.
- * Allocates and frees an accumulation buffer of A*C*n_samples + 1 eight-byte
- * values, stream-ordered (TIDAS_ENOMEM possible).
+ * amplitude); rf DEV [A][C][n_samples] (overwritten).  n_scat >= 0.  The
+ * workspace holds the accumulator (tidas_simulate_rf_workspace_bytes:
+ * A*C*n_samples + 1 eight-byte values).
  */
+size_t tidas_simulate_rf_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_samples);
 int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* tx, const double* scat,
-                          int32_t n_scat, int32_t n_samples, float* rf, void* stream);
+                          int32_t n_scat, int32_t n_samples, float* rf, void* workspace, size_t workspace_bytes,
+                          void* stream);
 
 /*
  * The paper's single-point study (Sec. 3.1-3.3), float64 throughout.  An

@@ -61,6 +61,7 @@ APPLY_BATCH_FOUR_BLOCK = 6
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
+_Z = ctypes.c_size_t
 _SIGS = {
     "tidas_version": (ctypes.c_char_p, []),
     "tidas_last_error": (ctypes.c_char_p, []),
@@ -69,11 +70,14 @@ _SIGS = {
     "tidas_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),
                             _P, _I, _I, _P, _P, _P, _P]),
     "tidas_build_kernels": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx),
-                                 ctypes.POINTER(Grid), _I, _I, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P]),
+                                 ctypes.POINTER(Grid), _I, _I, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _Z,
+                                 _P]),
+    "tidas_build_kernels_workspace_bytes": (_Z, [_I, _I, _I]),
     "tidas_apply": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
     "tidas_adjoint": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
     "tidas_apply_noalloc": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
-    "tidas_simulate_rf": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), _P, _I, _I, _P, _P]),
+    "tidas_simulate_rf": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), _P, _I, _I, _P, _P, _Z, _P]),
+    "tidas_simulate_rf_workspace_bytes": (_Z, [_I, _I, _I]),
     "tidas_apply_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_adjoint_ex": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_line_kernel": (_I, [_I, _I, _I, _I]),
@@ -81,8 +85,10 @@ _SIGS = {
     "tidas_prepare": (_I, [_P, _I, _I, _P, ctypes.c_size_t, _P]),
     "tidas_apply_prepared": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "tidas_adjoint_prepared": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
-    "tidas_deconvolve": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _I, _P, _P, _P]),
-    "tidas_kernel_grad": (_I, [_I, _P, _P, _I, _I, _I, _P, _P]),
+    "tidas_deconvolve": (_I, [_P, _I, _P, _I, _I, _I, ctypes.c_float, ctypes.c_float, _I, _P, _P, _P, _Z, _P]),
+    "tidas_deconvolve_workspace_bytes": (_Z, [_I, _I, _I, _I]),
+    "tidas_kernel_grad": (_I, [_I, _P, _P, _I, _I, _I, _P, _P, _Z, _P]),
+    "tidas_kernel_grad_workspace_bytes": (_Z, [_I, _I, _I, _I]),
     "tidas_kernel_grad_kernel": (_I, [_I, _P, _P]),
     "tidas_point_study_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I, _I]),
     "tidas_point_study": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), _I, _I, _I,
@@ -90,7 +96,8 @@ _SIGS = {
                                ctypes.c_size_t, _P]),
     "tidas_kossoff_tx_count": (_I, [ctypes.POINTER(Array), ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "tidas_apply_lateral": (_I, [_P, _I, _P, _I, _I, _I, _P, _P]),
-    "tidas_operator_norm_sq": (_I, [_P, _I, _I, _I, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "tidas_operator_norm_sq": (_I, [_P, _I, _I, _I, _P, ctypes.POINTER(ctypes.c_double), _P, _Z, _P]),
+    "tidas_operator_norm_sq_workspace_bytes": (_Z, [_I, _I]),
     "tidas_batch_workspace_bytes": (ctypes.c_size_t, [_I]),
     "das_beamform_batch": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), _I,
                                 ctypes.POINTER(Frame), _I, _P, ctypes.c_size_t, _I, _P]),

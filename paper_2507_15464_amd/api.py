@@ -23,6 +23,15 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _workspace(nbytes, dev):
+    """Device scratch of a call and its size (None, 0 when it needs none), from
+    torch's caching allocator, so that the library itself allocates nothing."""
+    nbytes = int(nbytes)
+    if nbytes == 0:
+        return None, 0
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev), nbytes
+
+
 def _check_tensor(t, name, dtype=torch.float32):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
@@ -112,8 +121,9 @@ def build_kernels(setup, grid=None, K=None, mode="exact", ref_row=None, n_sample
             raise ValueError("ref_row must have one entry per depth row")
         ref = (ctypes.c_int32 * len(vals))(*vals)
     arr, tx, rx, g = _descs(setup, grid)
+    ws, nws = _workspace(lib.tidas_build_kernels_workspace_bytes(grid.nz, K, m), dev)
     _lib.check(lib.tidas_build_kernels(ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g), T, K,
-                                       m, ref, _ptr(kb), _ptr(th), _stream()))
+                                       m, ref, _ptr(kb), _ptr(th), _ptr(ws), nws, _stream()))
     return (kb, th) if with_theta else kb
 
 
@@ -239,7 +249,9 @@ def kernel_grad(refl, image_bar, K, out=None):
     _check_tensor(out, "out")
     if tuple(out.shape) != (Z, int(K)):
         raise ValueError("out must be [Z][K]")
-    _lib.check(lib.tidas_kernel_grad(int(K), _ptr(refl), _ptr(image_bar), B, Z, X, _ptr(out), _stream()))
+    ws, nws = _workspace(lib.tidas_kernel_grad_workspace_bytes(int(K), B, Z, X), refl.device)
+    _lib.check(lib.tidas_kernel_grad(int(K), _ptr(refl), _ptr(image_bar), B, Z, X, _ptr(out), _ptr(ws), nws,
+                                     _stream()))
     return out
 
 
@@ -254,8 +266,9 @@ def simulate_rf(setup, scat, n_samples=None, out=None):
         out = torch.empty((len(setup.angles), setup.n_elem, T), device=scat.device, dtype=torch.float32)
     _check_tensor(out, "out")
     arr, tx, _, _ = _descs(setup)
+    ws, nws = _workspace(lib.tidas_simulate_rf_workspace_bytes(len(setup.angles), setup.n_elem, T), scat.device)
     _lib.check(lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), _ptr(scat), scat.shape[0], T, _ptr(out),
-                                     _stream()))
+                                     _ptr(ws), nws, _stream()))
     return out
 
 

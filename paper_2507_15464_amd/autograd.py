@@ -16,7 +16,7 @@ import ctypes
 import torch
 
 from . import _lib
-from .api import Prepared, _check_tensor, _ptr, _stream, adjoint, apply, conv_ex, kernel_grad
+from .api import Prepared, _check_tensor, _ptr, _stream, _workspace, adjoint, apply, conv_ex, kernel_grad
 
 __all__ = ["TiDASFunction", "tidas", "apply_ex", "adjoint_ex", "deconvolve", "operator_norm_sq", "step_size"]
 
@@ -68,7 +68,9 @@ def operator_norm_sq(kernels, iters=100):
     Z, K = kernels.shape
     work = torch.empty(3 * Z + 4, device=kernels.device, dtype=torch.float32)
     out = ctypes.c_double(0.0)
-    _lib.check(lib.tidas_operator_norm_sq(_ptr(kernels), K, Z, int(iters), _ptr(work), ctypes.byref(out), _stream()))
+    ws, nws = _workspace(lib.tidas_operator_norm_sq_workspace_bytes(K, Z), kernels.device)
+    _lib.check(lib.tidas_operator_norm_sq(_ptr(kernels), K, Z, int(iters), _ptr(work), ctypes.byref(out), _ptr(ws),
+                                          nws, _stream()))
     return out.value
 
 
@@ -90,6 +92,7 @@ def deconvolve(kernels, y, lam, eta=None, iters=200, out=None, work=None):
     w = torch.empty_like(y3) if work is None else work
     _check_tensor(r, "out")
     _check_tensor(w, "work")
+    ws, nws = _workspace(lib.tidas_deconvolve_workspace_bytes(kernels.shape[1], B, Z, X), y.device)
     _lib.check(lib.tidas_deconvolve(_ptr(kernels), kernels.shape[1], _ptr(y3), B, Z, X, ctypes.c_float(lam),
-                                    ctypes.c_float(eta), int(iters), _ptr(r), _ptr(w), _stream()))
+                                    ctypes.c_float(eta), int(iters), _ptr(r), _ptr(w), _ptr(ws), nws, _stream()))
     return r.view(y.shape)

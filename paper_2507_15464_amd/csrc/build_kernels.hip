@@ -353,9 +353,24 @@ static int32_t fill_setup(const tidas_array* array, const tidas_tx* tx, const ti
 
 using namespace tidas;
 
+// Paper and line modes: [reference responses nref x K doubles | widths nref
+// doubles | row -> slot map Z ints | reference rows nref ints], sized for
+// nref = Z (every row its own reference).
+static size_t paper_workspace_bytes(int64_t Z, int64_t K) {
+    return (size_t)(8 * Z * K + 8 * Z + 4 * Z + 4 * Z + 16);
+}
+
+extern "C" size_t tidas_build_kernels_workspace_bytes(int32_t nz, int32_t K, int32_t mode) {
+    if (nz < 1 || K < 1 || (mode != TIDAS_MODE_PAPER && mode != TIDAS_MODE_LINE)) return 0;
+    return paper_workspace_bytes(nz, K);
+}
+
+static void free_staging(void* p) { delete static_cast<std::vector<int32_t>*>(p); }
+
 extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                                        const tidas_grid* grid, int32_t n_samples, int32_t K, int32_t mode,
-                                       const int32_t* ref_row, float* kernels, float* theta, void* stream) {
+                                       const int32_t* ref_row, float* kernels, float* theta, void* workspace,
+                                       size_t workspace_bytes, void* stream) {
     int32_t st;
     if ((st = validate_array(array)) || (st = validate_tx(tx, true)) || (st = validate_rx(rx)) ||
         (st = validate_grid(grid)))
@@ -367,6 +382,10 @@ extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx*
         return fail(TIDAS_EINVAL, "tidas_build_kernels: mode must be 0 (exact), 1 (paper), 2 (line) or 3 (lateral)");
     if ((void*)kernels == (void*)theta) return fail(TIDAS_EINVAL, "tidas_build_kernels: theta aliases kernels");
     const int Z = grid->nz;
+    const bool paper = mode == TIDAS_MODE_PAPER || mode == TIDAS_MODE_LINE;
+    if ((st = workspace_check("tidas_build_kernels", workspace, workspace_bytes,
+                              paper ? paper_workspace_bytes(Z, K) : 0)))
+        return st;
     if (ref_row)
         for (int i = 0; i < Z; ++i)
             if (ref_row[i] < 0 || ref_row[i] >= Z)
@@ -406,16 +425,25 @@ extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx*
     }
     const size_t nref = refs.size();
     const size_t bytes = sizeof(int32_t) * (Z + nref) + sizeof(double) * (nref * (K + 1)) + 16;
-    void* buf = nullptr;
-    if ((st = check_hip(hipMallocAsync(&buf, bytes, strm), "tidas_build_kernels: temporary buffer"))) return st;
-    double* h_ref = (double*)buf;
+    Workspace ws;
+    if ((st = workspace_acquire("tidas_build_kernels: temporary buffer", workspace, bytes, strm, ws))) return st;
+    double* h_ref = (double*)ws.ptr;
     double* width = h_ref + nref * K;
     int32_t* d_map = (int32_t*)(width + nref);
     int32_t* d_refs = d_map + Z;
-    std::vector<int32_t> host_ints(map);
-    host_ints.insert(host_ints.end(), refs.begin(), refs.end());
-    st = check_hip(hipMemcpyAsync(d_map, host_ints.data(), sizeof(int32_t) * host_ints.size(), hipMemcpyHostToDevice, strm),
+    // host staging of the map, released by a host function queued after the
+    // copy (the call does not wait for the stream)
+    auto* host_ints = new std::vector<int32_t>(map);
+    host_ints->insert(host_ints->end(), refs.begin(), refs.end());
+    st = check_hip(hipMemcpyAsync(d_map, host_ints->data(), sizeof(int32_t) * host_ints->size(), hipMemcpyHostToDevice,
+                                  strm),
                    "tidas_build_kernels: upload");
+    if (check_hip(hipLaunchHostFunc(strm, free_staging, host_ints), "tidas_build_kernels: staging release")) {
+        // the host function could not be queued: wait for the copy instead
+        const hipError_t e = hipStreamSynchronize(strm);
+        delete host_ints;
+        if (!st) st = check_hip(e, "tidas_build_kernels: synchronize");
+    }
     if (!st) {
         hipLaunchKernelGGL(paper_ref_kernel, dim3((unsigned)nref), dim3(PAPER_THREADS), 0, strm, s, K, grid->z0,
                            grid->dz, Qf, d_refs, h_ref, width);
@@ -426,16 +454,18 @@ extern "C" int32_t tidas_build_kernels(const tidas_array* array, const tidas_tx*
                            d_map, d_refs, h_ref, width, (int32_t)(mode == TIDAS_MODE_LINE), kernels, theta);
         st = check_launch("tidas_build_kernels(paper, rows)");
     }
-    // the host staging vector must outlive the copy: order it before returning
-    hipError_t e = hipStreamSynchronize(strm);
-    hipError_t e2 = hipFreeAsync(buf, strm);
-    if (!st) st = check_hip(e, "tidas_build_kernels: synchronize");
-    if (!st) st = check_hip(e2, "tidas_build_kernels: free");
-    return st;
+    const int32_t st2 = workspace_release("tidas_build_kernels: free", ws, strm);
+    return st ? st : st2;
+}
+
+extern "C" size_t tidas_simulate_rf_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_samples) {
+    if (n_angles < 1 || n_elem < 1 || n_samples < 1) return 0;
+    return sizeof(double) * ((size_t)n_angles * n_elem * n_samples + 1);
 }
 
 extern "C" int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* tx, const double* scat, int32_t n_scat,
-                                     int32_t n_samples, float* rf, void* stream) {
+                                     int32_t n_samples, float* rf, void* workspace, size_t workspace_bytes,
+                                     void* stream) {
     int32_t st;
     if ((st = validate_array(array)) || (st = validate_tx(tx, true))) return st;
     if (!rf || (n_scat > 0 && !scat)) return fail(TIDAS_EINVAL, "tidas_simulate_rf: null pointer");
@@ -445,10 +475,12 @@ extern "C" int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* t
     if ((st = fill_setup(array, tx, nullptr, n_samples, s))) return st;
     hipStream_t strm = (hipStream_t)stream;
     const int64_t n = (int64_t)s.A * s.C * s.T;
-    void* buf = nullptr;
+    const size_t need = sizeof(double) * ((size_t)n + 1);
+    if ((st = workspace_check("tidas_simulate_rf", workspace, workspace_bytes, need))) return st;
     // [fixed-point accumulator n x 8 bytes | scale (8 bytes)]
-    if ((st = check_hip(hipMallocAsync(&buf, sizeof(double) * (n + 1), strm), "tidas_simulate_rf: accumulator")))
-        return st;
+    Workspace ws;
+    if ((st = workspace_acquire("tidas_simulate_rf: accumulator", workspace, need, strm, ws))) return st;
+    void* buf = ws.ptr;
     unsigned long long* acc = (unsigned long long*)buf;
     double* scale = (double*)buf + n;
     // the all-zero bit pattern is the integer 0
@@ -469,9 +501,8 @@ extern "C" int32_t tidas_simulate_rf(const tidas_array* array, const tidas_tx* t
         hipLaunchKernelGGL(round_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, strm, acc, n, scale, rf);
         st = check_launch("tidas_simulate_rf(round)");
     }
-    hipError_t e = hipFreeAsync(buf, strm);
-    if (!st) st = check_hip(e, "tidas_simulate_rf: free");
-    return st;
+    const int32_t st2 = workspace_release("tidas_simulate_rf: free", ws, strm);
+    return st ? st : st2;
 }
 
 extern "C" int32_t tidas_kernels_at(const tidas_array* array, double fs, double t0, double cycles, int32_t n_samples,

@@ -32,6 +32,47 @@ inline int32_t check_hip(hipError_t e, const char* what) {
     return TIDAS_OK;
 }
 
+// ------------------------------------------------------------ workspace ----
+// Entry points that need device scratch take (workspace, workspace_bytes): a
+// caller buffer of at least the size their query returns, 256-byte aligned,
+// or NULL with 0 bytes, in which case the call allocates the scratch
+// stream-ordered on its own stream and frees it the same way.
+struct Workspace {
+    char* ptr = nullptr;
+    bool owned = false;
+};
+
+// Argument check (before anything is enqueued).
+inline int32_t workspace_check(const char* who, const void* ws, size_t bytes, size_t need) {
+    if (!ws) {
+        if (bytes != 0) return fail(TIDAS_EINVAL, std::string(who) + ": workspace_bytes must be 0 with a null workspace");
+        return TIDAS_OK;
+    }
+    if (bytes < need) return fail(TIDAS_EINVAL, std::string(who) + ": workspace smaller than its size query");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(TIDAS_EINVAL, std::string(who) + ": workspace not 256-byte aligned");
+    return TIDAS_OK;
+}
+
+// The caller's buffer, or `need` bytes allocated stream-ordered.
+inline int32_t workspace_acquire(const char* who, void* ws, size_t need, hipStream_t s, Workspace& w) {
+    if (ws) {
+        w.ptr = (char*)ws;
+        w.owned = false;
+        return TIDAS_OK;
+    }
+    w.owned = true;
+    if (need == 0) return TIDAS_OK;
+    return check_hip(hipMallocAsync((void**)&w.ptr, need, s), who);
+}
+
+inline int32_t workspace_release(const char* who, Workspace& w, hipStream_t s) {
+    if (!w.owned || !w.ptr) return TIDAS_OK;
+    const int32_t st = check_hip(hipFreeAsync(w.ptr, s), who);
+    w.ptr = nullptr;
+    return st;
+}
+
 // Validation of the descriptors shared by several entry points.  Returns
 // TIDAS_OK or TIDAS_EINVAL with a message.
 int32_t validate_array(const tidas_array* a);

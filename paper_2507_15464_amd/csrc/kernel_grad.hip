@@ -410,8 +410,21 @@ extern "C" int32_t tidas_kernel_grad_kernel(int32_t X, const void* refl, const v
     return kgrad_split_path(X, refl, image_bar) ? TIDAS_KGRAD_SPLIT_BF16 : TIDAS_KGRAD_FP32;
 }
 
+// partial-sum slices of one call: [ranges][Z][K] floats
+static size_t kgrad_part_bytes(int32_t K, int32_t B, int32_t Z, int32_t X, bool vec) {
+    int nt = 1;
+    const KgGeom g = kgrad_geometry(K, B, Z, X, vec ? KB_CW : KG_CW, &nt);
+    return (size_t)g.n_split * Z * K * sizeof(float);
+}
+
+extern "C" size_t tidas_kernel_grad_workspace_bytes(int32_t K, int32_t B, int32_t Z, int32_t X) {
+    if (K < 1 || (K % 2) == 0 || B < 1 || Z < 1 || X < 1) return 0;
+    return std::max(kgrad_part_bytes(K, B, Z, X, true), kgrad_part_bytes(K, B, Z, X, false));
+}
+
 extern "C" int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* image_bar, int32_t B, int32_t Z,
-                                     int32_t X, float* kernels_bar, void* stream) {
+                                     int32_t X, float* kernels_bar, void* workspace, size_t workspace_bytes,
+                                     void* stream) {
     if (!refl || !image_bar || !kernels_bar) return fail(TIDAS_EINVAL, "tidas_kernel_grad: null pointer");
     if (K < 1 || (K % 2) == 0) return fail(TIDAS_EINVAL, "tidas_kernel_grad: K must be odd and >= 1");
     if (B < 1 || Z < 1 || X < 1) return fail(TIDAS_EINVAL, "tidas_kernel_grad: B, Z, X must be >= 1");
@@ -427,10 +440,13 @@ extern "C" int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* 
         return fail(TIDAS_EUNSUPPORTED, "tidas_kernel_grad: grid too large");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = (int64_t)Z * K;
-    float* part = nullptr;
-    int32_t st = check_hip(hipMallocAsync((void**)&part, (size_t)g.n_split * n * sizeof(float), s),
-                           "tidas_kernel_grad: partial sums");
+    const size_t need = (size_t)g.n_split * n * sizeof(float);
+    int32_t st = workspace_check("tidas_kernel_grad", workspace, workspace_bytes,
+                                 tidas_kernel_grad_workspace_bytes(K, B, Z, X));
     if (st) return st;
+    Workspace ws;
+    if ((st = workspace_acquire("tidas_kernel_grad: partial sums", workspace, need, s, ws))) return st;
+    float* part = (float*)ws.ptr;
     switch (nt) {
         case 1: launch_kgrad<1>(vec, g, image_bar, refl, part, s); break;
         case 2: launch_kgrad<2>(vec, g, image_bar, refl, part, s); break;
@@ -445,6 +461,6 @@ extern "C" int32_t tidas_kernel_grad(int32_t K, const float* refl, const float* 
                            n, kernels_bar);
         st = check_launch("tidas_kernel_grad(reduce)");
     }
-    const int32_t st2 = check_hip(hipFreeAsync(part, s), "tidas_kernel_grad: partial sums");
+    const int32_t st2 = workspace_release("tidas_kernel_grad: partial sums", ws, s);
     return st ? st : st2;
 }

@@ -1733,8 +1733,42 @@ extern "C" int32_t tidas_adjoint_prepared(const void* prepared, int32_t K, const
                               beta, base, refl_bar, (hipStream_t)stream);
 }
 
+// Scratch of one deconvolution: [N in float64 (two steps per launch) | N
+// (or N + I) | N^2 | band images of the launch's bank | c | c2]; total 0 when
+// the kernels are too long for the step-operator path.
+struct DeconvLayout {
+    bool one, two;
+    int KN, KN2, KP;
+    size_t off_nd, off_n1, off_np, off_img, off_c, off_c2, total;
+};
+
+static DeconvLayout deconv_layout(int32_t K, int32_t B, int32_t Z, int32_t X) {
+    DeconvLayout L{};
+    L.KN = 2 * K - 1;
+    L.KN2 = 2 * L.KN - 1;
+    L.two = bx_path(L.KN2, B, Z, X) && bx_lds_bytes(L.KN2) <= 160 * 1024;
+    L.one = bx_path(L.KN, B, Z, X) && bx_lds_bytes(L.KN) <= 160 * 1024;
+    if (!L.one) return L;
+    L.KP = L.two ? L.KN2 : L.KN;
+    const size_t frame_bytes = (size_t)B * Z * X * sizeof(float);
+    L.off_nd = 0;
+    L.off_n1 = L.off_nd + (L.two ? align_up((size_t)Z * L.KN * sizeof(double), 256) : 0);
+    L.off_np = L.off_n1 + align_up((size_t)Z * L.KN * sizeof(float), 256);
+    L.off_img = L.off_np + (L.two ? align_up((size_t)Z * L.KP * sizeof(float), 256) : 0);
+    L.off_c = L.off_img + align_up(prepared_bytes(L.KP, Z, 1), 256);
+    L.off_c2 = L.off_c + align_up(frame_bytes, 256);
+    L.total = L.off_c2 + (L.two ? align_up(frame_bytes, 256) : 0);
+    return L;
+}
+
+extern "C" size_t tidas_deconvolve_workspace_bytes(int32_t K, int32_t B, int32_t Z, int32_t X) {
+    if (K < 1 || (K % 2) == 0 || B < 1 || Z < 1 || X < 1) return 0;
+    return deconv_layout(K, B, Z, X).total;
+}
+
 extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float* y, int32_t B, int32_t Z, int32_t X,
-                                    float lam, float eta, int32_t iters, float* r, float* work, void* stream) {
+                                    float lam, float eta, int32_t iters, float* r, float* work, void* workspace,
+                                    size_t workspace_bytes, void* stream) {
     if (!y || !r || !work || !kernels) return fail(TIDAS_EINVAL, "tidas_deconvolve: null pointer");
     if (iters < 0) return fail(TIDAS_EINVAL, "tidas_deconvolve: iters must be >= 0");
     if (!(lam >= 0.0f) || !std::isfinite(lam) || !(eta > 0.0f) || !std::isfinite(eta))
@@ -1745,6 +1779,8 @@ extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float
     for (int a = 0; a < 4; ++a)
         for (int c = a + 1; c < 4; ++c)
             if (ptrs[a] == ptrs[c]) return fail(TIDAS_EINVAL, "tidas_deconvolve: buffers must be distinct");
+    const DeconvLayout L = deconv_layout(K, B, Z, X);
+    if (int32_t st = workspace_check("tidas_deconvolve", workspace, workspace_bytes, L.total)) return st;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = (int64_t)B * Z * X;
     if (iters == 0) {
@@ -1756,10 +1792,9 @@ extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float
     // (the same step, regrouped), r_1 = c; with N^2 and c2 = N c + c two steps
     // per launch: r_{t+2} = N^2 r_t + c2.  The step operator's bank has 2K - 1
     // taps (N^2: 4K - 3); both run on the split-bfloat16 two-block tile.
-    const int KN = 2 * K - 1, KN2 = 2 * KN - 1;
-    const bool two = bx_path(KN2, B, Z, X) && bx_lds_bytes(KN2) <= 160 * 1024;
-    const bool one = bx_path(KN, B, Z, X) && bx_lds_bytes(KN) <= 160 * 1024;
-    if (!one) {
+    const int KN = L.KN, KN2 = L.KN2;
+    const bool two = L.two;
+    if (!L.one) {
         // large kernels: two fused launches per step (residual, update)
         hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s, r,
                            n, 0.0f);
@@ -1771,24 +1806,18 @@ extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float
         }
         return st;
     }
-    const int KP = two ? KN2 : KN;  // bank of one launch
+    const int KP = L.KP;  // bank of one launch
     const size_t frame_bytes = (size_t)n * sizeof(float);
-    const size_t off_nd = 0;
-    const size_t off_n1 = off_nd + (two ? align_up((size_t)Z * KN * sizeof(double), 256) : 0);
-    const size_t off_np = off_n1 + align_up((size_t)Z * KN * sizeof(float), 256);
-    const size_t off_img = off_np + (two ? align_up((size_t)Z * KP * sizeof(float), 256) : 0);
-    const size_t off_c = off_img + align_up(prepared_bytes(KP, Z, 1), 256);
-    const size_t off_c2 = off_c + align_up(frame_bytes, 256);
-    const size_t total = off_c2 + (two ? align_up(frame_bytes, 256) : 0);
-    char* tmp = nullptr;
-    int32_t st = check_hip(hipMallocAsync((void**)&tmp, total, s), "tidas_deconvolve: temporaries");
+    Workspace ws;
+    int32_t st = workspace_acquire("tidas_deconvolve: temporaries", workspace, L.total, s, ws);
     if (st) return st;
-    double* nd = two ? (double*)(tmp + off_nd) : nullptr;
-    float* n1 = (float*)(tmp + off_n1);  // N, or N + I with two steps per launch
-    float* np = two ? (float*)(tmp + off_np) : n1;
-    uint16_t* img = (uint16_t*)(tmp + off_img);
-    float* c = (float*)(tmp + off_c);
-    float* c2 = two ? (float*)(tmp + off_c2) : nullptr;
+    char* tmp = ws.ptr;
+    double* nd = two ? (double*)(tmp + L.off_nd) : nullptr;
+    float* n1 = (float*)(tmp + L.off_n1);  // N, or N + I with two steps per launch
+    float* np = two ? (float*)(tmp + L.off_np) : n1;
+    uint16_t* img = (uint16_t*)(tmp + L.off_img);
+    float* c = (float*)(tmp + L.off_c);
+    float* c2 = two ? (float*)(tmp + L.off_c2) : nullptr;
     const int64_t e1 = (int64_t)Z * KN;
     // with two steps per launch n1 is N + I (for c2 = (N + I) c), else N
     hipLaunchKernelGGL(normal_bank_kernel, dim3((unsigned)((e1 + 255) / 256)), dim3(256), 0, s, kernels, K, Z,
@@ -1831,15 +1860,23 @@ extern "C" int32_t tidas_deconvolve(const float* kernels, int32_t K, const float
         // iters = 1 (r = c), or iters = 2 with two steps per launch (r = c2)
         st = check_hip(hipMemcpyAsync(r, x, frame_bytes, hipMemcpyDeviceToDevice, s), "tidas_deconvolve: copy");
     }
-    const int32_t st2 = check_hip(hipFreeAsync(tmp, s), "tidas_deconvolve: temporaries");
+    const int32_t st2 = workspace_release("tidas_deconvolve: temporaries", ws, s);
     return st ? st : st2;
 }
 
+extern "C" size_t tidas_operator_norm_sq_workspace_bytes(int32_t K, int32_t Z) {
+    if (K < 1 || (K % 2) == 0 || Z < 1 || !bx_path(K, 1, Z, 1)) return 0;
+    return full_prepared_bytes(K, Z);
+}
+
 extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32_t Z, int32_t iters, float* work,
-                                          double* out, void* stream) {
+                                          double* out, void* workspace, size_t workspace_bytes, void* stream) {
     if (!kernels || !work || !out) return fail(TIDAS_EINVAL, "tidas_operator_norm_sq: null pointer");
     if (K < 1 || (K % 2) == 0 || Z < 1 || iters < 1)
         return fail(TIDAS_EINVAL, "tidas_operator_norm_sq: K odd >= 1, Z >= 1, iters >= 1 required");
+    const bool bx = bx_path(K, 1, Z, 1);
+    const size_t need = bx ? full_prepared_bytes(K, Z) : 0;
+    if (int32_t st = workspace_check("tidas_operator_norm_sq", workspace, workspace_bytes, need)) return st;
     hipStream_t s = (hipStream_t)stream;
     // work layout: v [Z] | Av [Z] | w [Z] | norm (double, 8-byte aligned); v and w swap roles
     float* v = work;
@@ -1849,13 +1886,12 @@ extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<int64_t>((Z + 255) / 256, 65536)), dim3(256), 0, s, v,
                        (int64_t)Z, 1.0f);
     int32_t st = check_launch("tidas_operator_norm_sq(init)");
-    void* imgs = nullptr;
-    const bool bx = bx_path(K, 1, Z, 1);
-    if (!st && bx && !(st = check_hip(hipMallocAsync(&imgs, full_prepared_bytes(K, Z), s), "tidas_operator_norm_sq: bands"))) {
-        prepare_full(kernels, K, Z, (uint16_t*)imgs, s);
+    Workspace ws;
+    if (!st && bx && !(st = workspace_acquire("tidas_operator_norm_sq: bands", workspace, need, s, ws))) {
+        prepare_full(kernels, K, Z, (uint16_t*)ws.ptr, s);
         st = check_launch("tidas_operator_norm_sq(prepare)");
     }
-    const uint16_t* prep = (const uint16_t*)imgs;
+    const uint16_t* prep = (const uint16_t*)ws.ptr;
     for (int it = 0; it < iters && !st; ++it) {
         // v <- A^T A v / ||A^T A v||; the last norm is the largest eigenvalue of A^T A
         if (bx) {
@@ -1871,10 +1907,8 @@ extern "C" int32_t tidas_operator_norm_sq(const float* kernels, int32_t K, int32
         }
         std::swap(v, w);
     }
-    if (imgs) {
-        const int32_t st2 = check_hip(hipFreeAsync(imgs, s), "tidas_operator_norm_sq: bands");
-        if (!st) st = st2;
-    }
+    const int32_t st2 = workspace_release("tidas_operator_norm_sq: bands", ws, s);
+    if (!st) st = st2;
     if (!st) st = check_hip(hipMemcpyAsync(out, nrm, sizeof(double), hipMemcpyDeviceToHost, s), "norm download");
     if (!st) st = check_hip(hipStreamSynchronize(s), "tidas_operator_norm_sq: synchronize");
     return st;

@@ -54,17 +54,30 @@ int main() {
     expect("prepared bytes 0", (long long)tidas_prepared_bytes(0, 64), 0);
     expect("prepare short", tidas_prepare(F, 65, 64, A, 16, nullptr), E);
     expect("lateral even", tidas_apply_lateral(F, 4, (float*)A, 1, 8, 8, (float*)B, nullptr), E);
-    expect("kgrad even", tidas_kernel_grad(4, (float*)A, (float*)B, 1, 8, 8, F, nullptr), E);
+    expect("kgrad even", tidas_kernel_grad(4, (float*)A, (float*)B, 1, 8, 8, F, nullptr, 0, nullptr), E);
     expect("kgrad path", tidas_kernel_grad_kernel(16, A, B), TIDAS_KGRAD_SPLIT_BF16);
     expect("kgrad path unaligned", tidas_kernel_grad_kernel(16, reinterpret_cast<void*>(0x1004), B), TIDAS_KGRAD_FP32);
     expect("deconv alias", tidas_deconvolve(F, 65, (float*)A, 1, 8, 8, 1e-3f, 1e-2f, 3, (float*)A, (float*)B,
-                                            nullptr), E);
-    expect("deconv eta", tidas_deconvolve(F, 65, (float*)A, 1, 8, 8, 1e-3f, 0.0f, 3, (float*)B, (float*)C, nullptr), E);
+                                            nullptr, 0, nullptr), E);
+    expect("deconv eta", tidas_deconvolve(F, 65, (float*)A, 1, 8, 8, 1e-3f, 0.0f, 3, (float*)B, (float*)C, nullptr, 0,
+                                          nullptr), E);
     double nrm = 0.0;
-    expect("norm iters", tidas_operator_norm_sq(F, 65, 8, 0, (float*)A, &nrm, nullptr), E);
+    expect("norm iters", tidas_operator_norm_sq(F, 65, 8, 0, (float*)A, &nrm, nullptr, 0, nullptr), E);
     expect("build null", tidas_build_kernels(&arr, &tx, &rx, &grid, 2048, 65, 0, nullptr, nullptr, nullptr,
-                                             nullptr), E);
-    expect("simulate negative", tidas_simulate_rf(&arr, &tx, (const double*)A, -1, 2048, F, nullptr), E);
+                                             nullptr, 0, nullptr), E);
+    expect("simulate negative", tidas_simulate_rf(&arr, &tx, (const double*)A, -1, 2048, F, nullptr, 0, nullptr), E);
+
+    // caller workspaces: queries and checks
+    expect("build ws exact", (long long)tidas_build_kernels_workspace_bytes(64, 65, 0), 0);
+    const size_t bws = tidas_build_kernels_workspace_bytes(64, 65, 1);
+    expect("build ws short", tidas_build_kernels(&arr, &tx, &rx, &grid, 2048, 65, 1, nullptr, F, nullptr, A, bws - 1,
+                                                 nullptr), E);
+    expect("simulate ws", (long long)tidas_simulate_rf_workspace_bytes(1, 64, 100), 8 * (64 * 100 + 1));
+    expect("simulate ws misaligned", tidas_simulate_rf(&arr, &tx, (const double*)A, 3, 100, F,
+                                                       reinterpret_cast<void*>(0x100010), 8 * 6401, nullptr), E);
+    expect("kgrad ws no pointer", tidas_kernel_grad(5, (float*)A, (float*)B, 1, 8, 8, F, nullptr, 64, nullptr), E);
+    expect("deconv ws even K", (long long)tidas_deconvolve_workspace_bytes(64, 1, 8, 8), 0);
+    expect("norm ws Z=0", (long long)tidas_operator_norm_sq_workspace_bytes(65, 0), 0);
 
     // ragged batches: host tables
     expect("batch bytes", (long long)tidas_batch_workspace_bytes(3), 512);

@@ -129,23 +129,69 @@ def test_fixed_delay_beamform_rejects_invalid_arguments(lib):
 def test_build_kernels_rejects_invalid_arguments(lib):
     arr, tx, rx, g = _geom()
     ok = (ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g))
-    assert lib.tidas_build_kernels(*ok, 2048, 65, 0, None, NUL, NUL, NUL) == -1       # null kernels
-    assert lib.tidas_build_kernels(*ok, 2048, 64, 0, None, FAKE, NUL, NUL) == -1      # even K
-    assert lib.tidas_build_kernels(*ok, 2048, 65, 7, None, FAKE, NUL, NUL) == -1      # bad mode
-    assert lib.tidas_build_kernels(*ok, 1, 65, 0, None, FAKE, NUL, NUL) == -1         # n_samples
-    assert lib.tidas_build_kernels(*ok, 2048, 65, 0, None, FAKE, FAKE, NUL) == -1     # theta aliases
+    assert lib.tidas_build_kernels(*ok, 2048, 65, 0, None, NUL, NUL, NUL, 0, NUL) == -1       # null kernels
+    assert lib.tidas_build_kernels(*ok, 2048, 64, 0, None, FAKE, NUL, NUL, 0, NUL) == -1      # even K
+    assert lib.tidas_build_kernels(*ok, 2048, 65, 7, None, FAKE, NUL, NUL, 0, NUL) == -1      # bad mode
+    assert lib.tidas_build_kernels(*ok, 1, 65, 0, None, FAKE, NUL, NUL, 0, NUL) == -1         # n_samples
+    assert lib.tidas_build_kernels(*ok, 2048, 65, 0, None, FAKE, FAKE, NUL, 0, NUL) == -1     # theta aliases
     bad_ref = (ctypes.c_int32 * 256)(*([0] * 255 + [256]))
-    assert lib.tidas_build_kernels(*ok, 2048, 65, 1, bad_ref, FAKE, NUL, NUL) == -1   # ref out of range
+    assert lib.tidas_build_kernels(*ok, 2048, 65, 1, bad_ref, FAKE, NUL, NUL, 0, NUL) == -1   # ref out of range
     nopulse = _lib.make_tx([0.0], 40e6, 0, 0.0, 2)
-    assert lib.tidas_build_kernels(ok[0], ctypes.byref(nopulse), *ok[2:], 2048, 65, 0, None, FAKE, NUL, NUL) == -1
+    assert lib.tidas_build_kernels(ok[0], ctypes.byref(nopulse), *ok[2:], 2048, 65, 0, None, FAKE, NUL, NUL, 0,
+                                   NUL) == -1
 
 
 def test_simulate_rejects_invalid_arguments(lib):
     arr, tx, _, _ = _geom()
-    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), NUL, 5, 2048, FAKE, NUL) == -1
-    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, -1, 2048, FAKE, NUL) == -1
-    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 0, FAKE, NUL) == -1
-    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 2048, NUL, NUL) == -1
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), NUL, 5, 2048, FAKE, NUL, 0, NUL) == -1
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, -1, 2048, FAKE, NUL, 0, NUL) == -1
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 0, FAKE, NUL, 0, NUL) == -1
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 2048, NUL, NUL, 0, NUL) == -1
+
+
+def test_workspace_queries_and_checks(lib):
+    """Every entry point that needs device scratch sizes it through a query and
+    takes it from the caller (or allocates it itself when given NULL, 0):
+    a short, misaligned or size-without-pointer workspace is EINVAL before
+    anything is enqueued."""
+    Z, K = 256, 65
+    # kernel build: paper and line modes only, sized for every row its own reference
+    assert lib.tidas_build_kernels_workspace_bytes(Z, K, _lib.MODE_EXACT) == 0
+    assert lib.tidas_build_kernels_workspace_bytes(Z, K, _lib.MODE_LATERAL) == 0
+    need = lib.tidas_build_kernels_workspace_bytes(Z, K, _lib.MODE_PAPER)
+    assert need == 8 * Z * K + 16 * Z + 16 == lib.tidas_build_kernels_workspace_bytes(Z, K, _lib.MODE_LINE)
+    arr, tx, rx, g = _geom()
+    ok = (ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g))
+    ws = ctypes.c_void_p(0x100000)
+    assert lib.tidas_build_kernels(*ok, 2048, K, 1, None, FAKE, NUL, ws, need - 1, NUL) == -1      # short
+    assert lib.tidas_build_kernels(*ok, 2048, K, 1, None, FAKE, NUL, ctypes.c_void_p(0x100080), need,
+                                   NUL) == -1                                                     # misaligned
+    assert lib.tidas_build_kernels(*ok, 2048, K, 1, None, FAKE, NUL, NUL, need, NUL) == -1         # bytes, no pointer
+    assert lib.tidas_last_error()
+    # RF synthesis: the fixed-point accumulator and its scale
+    assert lib.tidas_simulate_rf_workspace_bytes(2, 64, 2048) == 8 * (2 * 64 * 2048 + 1)
+    assert lib.tidas_simulate_rf_workspace_bytes(0, 64, 2048) == 0
+    need = lib.tidas_simulate_rf_workspace_bytes(1, arr.n_elem, 2048)
+    assert lib.tidas_simulate_rf(ctypes.byref(arr), ctypes.byref(tx), FAKE, 5, 2048, ctypes.c_void_p(0x8000),
+                                 ws, need - 8, NUL) == -1
+    # kernel gradient: partial-sum slices (a whole number of Z x K slices)
+    need = lib.tidas_kernel_grad_workspace_bytes(K, 4, Z, 64)
+    assert need > 0 and need % (4 * Z * K) == 0
+    assert lib.tidas_kernel_grad_workspace_bytes(64, 4, Z, 64) == 0
+    assert lib.tidas_kernel_grad(K, FAKE, ctypes.c_void_p(0x2000), 4, Z, 64, ctypes.c_void_p(0x3000), ws, need - 4,
+                                 NUL) == -1
+    # deconvolution: step operators, band images, c and c2 (at least two frames)
+    need = lib.tidas_deconvolve_workspace_bytes(K, 1, Z, 64)
+    assert need >= 2 * 4 * Z * 64
+    f = ctypes.c_float
+    assert lib.tidas_deconvolve(FAKE, K, ctypes.c_void_p(0x4000), 1, Z, 64, f(1e-3), f(0.1), 10,
+                                ctypes.c_void_p(0x3000), ctypes.c_void_p(0x2000), ws, need - 1, NUL) == -1
+    # power iteration: the band images
+    need = lib.tidas_operator_norm_sq_workspace_bytes(K, Z)
+    assert need > 0 and lib.tidas_operator_norm_sq_workspace_bytes(K, 0) == 0
+    out = ctypes.c_double(0)
+    assert lib.tidas_operator_norm_sq(FAKE, K, Z, 10, ctypes.c_void_p(0x2000), ctypes.byref(out), ws, need - 1,
+                                      NUL) == -1
 
 
 def test_python_api_refuses_host_tensors():
@@ -169,14 +215,14 @@ def test_deconvolve_and_norm_reject_invalid_arguments(lib):
     r = ctypes.c_void_p(0x3000)
     y = ctypes.c_void_p(0x4000)
     f = ctypes.c_float
-    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.1), 10, r, r, NUL) == -1   # r aliases work
-    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.0), 10, r, w, NUL) == -1   # eta = 0
-    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(-1.0), f(0.1), 10, r, w, NUL) == -1   # lam < 0
-    assert lib.tidas_deconvolve(ok, 64, y, 1, 16, 16, f(1e-3), f(0.1), 10, r, w, NUL) == -1   # even K
-    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.1), -1, r, w, NUL) == -1   # iters < 0
+    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.1), 10, r, r, NUL, 0, NUL) == -1   # r aliases work
+    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.0), 10, r, w, NUL, 0, NUL) == -1   # eta = 0
+    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(-1.0), f(0.1), 10, r, w, NUL, 0, NUL) == -1   # lam < 0
+    assert lib.tidas_deconvolve(ok, 64, y, 1, 16, 16, f(1e-3), f(0.1), 10, r, w, NUL, 0, NUL) == -1   # even K
+    assert lib.tidas_deconvolve(ok, 65, y, 1, 16, 16, f(1e-3), f(0.1), -1, r, w, NUL, 0, NUL) == -1   # iters < 0
     out = ctypes.c_double(0)
-    assert lib.tidas_operator_norm_sq(ok, 65, 16, 0, w, ctypes.byref(out), NUL) == -1
-    assert lib.tidas_operator_norm_sq(ok, 65, 16, 10, w, None, NUL) == -1
+    assert lib.tidas_operator_norm_sq(ok, 65, 16, 0, w, ctypes.byref(out), NUL, 0, NUL) == -1
+    assert lib.tidas_operator_norm_sq(ok, 65, 16, 10, w, None, NUL, 0, NUL) == -1
     assert lib.tidas_apply_ex(ok, 65, y, 1, 16, 16, f(1.0), f(1.0), y, r, NUL) == -1        # base aliases input
     assert lib.tidas_adjoint_ex(ok, 65, y, 1, 16, 16, f(float("inf")), f(1.0), None, r, NUL) == -1
 
@@ -206,17 +252,17 @@ def test_batch_entry_points_reject_invalid_arguments(lib):
 def test_kernel_grad_rejects_invalid_arguments(lib):
     out = ctypes.c_void_p(0x3000)
     f = lib.tidas_kernel_grad
-    assert f(65, NUL, FAKE, 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL      # null refl
-    assert f(65, FAKE, NUL, 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL      # null image_bar
-    assert f(65, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, NUL, NUL) == _lib.TIDAS_EINVAL  # null output
-    assert f(64, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL  # even K
-    assert f(0, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, out, NUL) == _lib.TIDAS_EINVAL   # K = 0
-    assert f(5, FAKE, ctypes.c_void_p(0x2000), 0, 16, 16, out, NUL) == _lib.TIDAS_EINVAL   # B = 0
-    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 0, 16, out, NUL) == _lib.TIDAS_EINVAL    # Z = 0
-    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 16, -1, out, NUL) == _lib.TIDAS_EINVAL   # X < 0
-    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, FAKE, NUL) == _lib.TIDAS_EINVAL  # output aliases refl
+    assert f(65, NUL, FAKE, 1, 16, 16, out, NUL, 0, NUL) == _lib.TIDAS_EINVAL      # null refl
+    assert f(65, FAKE, NUL, 1, 16, 16, out, NUL, 0, NUL) == _lib.TIDAS_EINVAL      # null image_bar
+    assert f(65, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, NUL, NUL, 0, NUL) == _lib.TIDAS_EINVAL  # null output
+    assert f(64, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, out, NUL, 0, NUL) == _lib.TIDAS_EINVAL  # even K
+    assert f(0, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, out, NUL, 0, NUL) == _lib.TIDAS_EINVAL   # K = 0
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 0, 16, 16, out, NUL, 0, NUL) == _lib.TIDAS_EINVAL   # B = 0
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 0, 16, out, NUL, 0, NUL) == _lib.TIDAS_EINVAL    # Z = 0
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 16, -1, out, NUL, 0, NUL) == _lib.TIDAS_EINVAL   # X < 0
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 16, 16, FAKE, NUL, 0, NUL) == _lib.TIDAS_EINVAL  # output aliases refl
     # a frame whose 32-bit byte offsets would overflow
-    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 1 << 20, 1024, out, NUL) == _lib.TIDAS_EUNSUPPORTED
+    assert f(5, FAKE, ctypes.c_void_p(0x2000), 1, 1 << 20, 1024, out, NUL, 0, NUL) == _lib.TIDAS_EUNSUPPORTED
     assert lib.tidas_last_error()
 
 
