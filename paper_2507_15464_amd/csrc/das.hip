@@ -387,7 +387,7 @@ __global__ __launch_bounds__(256) void fixed_das_kernel(const DasArgs p, const D
 }
 
 // --------------------------------- fixed-delay beamformer, staged windows ----
-// One plane wave and groups of FB frames.  The time-invariant law makes a
+// One plane wave and groups of four frames.  The time-invariant law makes a
 // row's read position in element n's channel u_k = U_k + E(j, n): a per-row
 // term U_k = fs (tau_tx(x_j, z_k) + z_k / c - t0), which grows by
 // fs dz (1 + cos a) / c per row, plus the receive excess E of the row's
@@ -397,22 +397,29 @@ __global__ __launch_bounds__(256) void fixed_das_kernel(const DasArgs p, const D
 // first row to its last, over the lanes inside the element's aperture.  A
 // superset of it (bounded from the columns' extent and the aperture, with a
 // margin of two samples) is copied into the wave's LDS by direct-to-LDS
-// loads, FL_LMAX / 64 loads of 64 consecutive samples per frame (samples
-// outside the record read 0), FL_DEPTH - 1 elements ahead of the one being
-// summed; every pair of the run then reads its two samples from LDS: no
-// per-pair gathers, and the law (square root, reciprocal, Hann weight) once
-// per (column, element, run).  The ring slots are distinct LDS arrays, so
-// the compiler sees that a read of one slot does not depend on the copies
-// still landing in the others, and the wait before each element's sum is
-// the explicit one (its loads done, the later ones in flight).  Runs of
-// equal reference inside a wave are walked one after the other (a wave
-// whose rows all differ stages one window per row).  A window longer than
-// FL_LMAX samples is read from global memory pair by pair instead.  The
-// index split, the law and the sum of each pair are those of the DAS kernel
-// with FB > 1, so self-referenced rows give DAS's bits.
+// loads, FL_DEPTH - 1 elements ahead of the one being summed.  The copy
+// interleaves the four frames ([sample][frame]: each load's lane L takes
+// frame L % 4 of sample L / 4 of a 16-sample piece), so one 16-byte LDS read
+// returns a sample of all four frames, and the two samples of a pair are two
+// such reads from one address; the law (square root, reciprocal, Hann
+// weight) is computed once per (column, element, run) and each row's index
+// split and interpolation weights once for the four frames.  Rows are summed
+// in groups of four (their reads in flight together); a group that a run
+// covers only in part gives its other rows weight 0, and every index is
+// clamped into the staged window, so lanes outside the aperture (weight 0)
+// read staged values too.  The ring slots are distinct LDS arrays, so the
+// compiler sees that a read of one slot does not depend on the copies still
+// landing in the others, and the wait before each element's sum is the
+// explicit one (its loads done, the later ones in flight).  A window longer
+// than FL_LMAX samples, or reaching outside the record, is read from global
+// memory pair by pair instead (there each frame's own range check gives the
+// zeros outside the record).  The index split, the law and the sum of each
+// pair are those of the DAS kernel with several frames per thread, so
+// self-referenced rows give DAS's values.
 constexpr int FL_RW = 16;     // rows per wave
-constexpr int FL_LMAX = 256;  // samples per staged window (one frame, one slot)
-constexpr int FL_PIECES = FL_LMAX / 64;
+constexpr int FL_FB = 4;      // frames per wave, interleaved in LDS
+constexpr int FL_LMAX = 256;  // samples per staged window
+constexpr int FL_PIECES = FL_LMAX * FL_FB / 64;  // direct-to-LDS loads per window
 constexpr int FL_DEPTH = 4;   // ring slots: the element being summed and the next three
 constexpr int FL_WAVES = 4;   // waves per workgroup, stacked in depth
 
@@ -425,16 +432,21 @@ __device__ __forceinline__ void fl_static_for(F&& f) {
     fl_static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int FB>
+// Byte offsets of the four frames' copies of one channel must fit 31 bits.
+__host__ __device__ inline bool fd_lds_fits(int32_t C, int32_t T) {
+    return (int64_t)(FL_FB - 1) * C * T * 4 + (int64_t)T * 4 + 64 * 4 < ((int64_t)1 << 31);
+}
+
 __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasGrid gr, const int32_t* __restrict__ ref,
                                                      const float* __restrict__ theta, const float* __restrict__ rf,
                                                      float* __restrict__ img) {
+    constexpr int FB = FL_FB;
     static_assert(FL_DEPTH == 4, "four ring slots below");
-    // ring slots, one array each: [wave][frame][FL_LMAX]
-    __shared__ float fl_s0[FL_WAVES * FB * FL_LMAX];
-    __shared__ float fl_s1[FL_WAVES * FB * FL_LMAX];
-    __shared__ float fl_s2[FL_WAVES * FB * FL_LMAX];
-    __shared__ float fl_s3[FL_WAVES * FB * FL_LMAX];
+    // ring slots, one array each: [wave][sample][frame]
+    __shared__ float4 fl_s0[FL_WAVES * FL_LMAX];
+    __shared__ float4 fl_s1[FL_WAVES * FL_LMAX];
+    __shared__ float4 fl_s2[FL_WAVES * FL_LMAX];
+    __shared__ float4 fl_s3[FL_WAVES * FL_LMAX];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int i_base = (blockIdx.x * FL_WAVES + wave) * FL_RW;
@@ -445,8 +457,8 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
     const size_t frame_img = (size_t)gr.nz * gr.nx;
     const float* rf0 = rf + fr0 * frame_rf;
     float* img0 = img + fr0 * frame_img;
-    const int wo = wave * FB * FL_LMAX;
-    auto slot = [&](auto D_) -> float* {
+    const int wo = wave * FL_LMAX;
+    auto slot = [&](auto D_) -> float4* {
         constexpr int d = decltype(D_)::value;
         if constexpr (d == 0) return fl_s0 + wo;
         else if constexpr (d == 1) return fl_s1 + wo;
@@ -462,6 +474,7 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
     const float pitch_f = (float)p.pitch, pitch_lo = (float)(p.pitch - (double)pitch_f);
     const double sa = p.sin_a[0], ca = p.cos_a[0];
     int q[FL_RW];
+    float qfl[FL_RW];  // q as float (staged windows: exact there)
     float fp[FL_RW];
 #pragma unroll
     for (int k = 0; k < FL_RW; ++k) {
@@ -469,6 +482,7 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
         const double U = p.fs * ((xd * sa + zd * ca) / p.c + zd / p.c - p.t0);
         const double Uf = floor(U);
         q[k] = (int)Uf;
+        qfl[k] = (float)Uf;
         fp[k] = (float)(U - Uf);
     }
     float acc[FL_RW][FB];
@@ -484,10 +498,20 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
         const int r = ref ? ref[ii] : ii;
         return __builtin_amdgcn_readfirstlane(min(max(r, 0), gr.nz - 1));
     };
+    // the staged copy: one record over channel n of the group's frames (frames
+    // past the group's last lie past its end and read 0); lane L's offset
+    // within a 16-sample piece
+    const uint32_t frame_bytes = (uint32_t)(frame_rf * 4);
+    const uint32_t rec_bytes = (uint32_t)(((size_t)(nfr - 1) * frame_rf + p.T) * 4);
+    const int lane_off = (lane & 3) * (int)frame_bytes + (lane >> 2) * 4;
+    auto chan4 = [&](int n, bool live) {
+        return make_rsrc(rf0 + (size_t)(live ? n : 0) * p.T, live ? rec_bytes : 0u);
+    };
+    // one frame's channel n (the pair-by-pair path)
     const uint32_t row_bytes = (uint32_t)p.T * 4u;
-    auto chan = [&](int f, int n, bool live) {
-        const bool fv = live && f < nfr;
-        return make_rsrc(rf0 + (fv ? f : 0) * frame_rf + (size_t)(live ? n : 0) * p.T, fv ? row_bytes : 0u);
+    auto chan1 = [&](int f, int n) {
+        const bool fv = f < nfr;
+        return make_rsrc(rf0 + (fv ? f : 0) * frame_rf + (size_t)n * p.T, fv ? row_bytes : 0u);
     };
     // the wave's columns, relative to element 0 (uniform)
     const int j_end = min(j_base + 63, gr.nx - 1);
@@ -525,13 +549,14 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
 
         struct Win {
             float w, e;
-            int lo, len;  // len 0: no lane in the aperture (or n past the run); len > FL_LMAX: read pair by pair
+            int lo, len;  // len 0: no lane in the aperture (or n past the run)
+            bool staged;  // the window lies in LDS; else read pair by pair
         };
         // element n's law (per lane), window (uniform) and its copy into slot
-        // S: every call issues FL_PIECES loads per frame (dummy ones, which read
+        // S: every call issues FL_PIECES loads (dummy ones, which read
         // nothing, for an element past the run, out of reach or not staged)
         auto prep = [&](int n, auto S_) {
-            Win W{0.0f, 0.0f, 0, 0};
+            Win W{0.0f, 0.0f, 0, 0, false};
             if (n <= n_hi) {
                 const float nf = (float)n;
                 const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
@@ -550,42 +575,63 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
                     W.len = hi - W.lo + 1;
                 }
             }
-            const bool staged = W.len > 0 && W.len <= FL_LMAX;
-            float* dst = slot(S_);
+            W.staged = W.len > 0 && W.len <= FL_LMAX && W.lo >= 0 && W.lo + W.len <= p.T;
+            float* dst = reinterpret_cast<float*>(slot(S_));
+            const auto rs = chan4(n, W.staged);
+            const int vb = lane_off + W.lo * 4;
 #pragma unroll
             for (int c = 0; c < FL_PIECES; ++c)
-#pragma unroll
-                for (int f = 0; f < FB; ++f)
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        chan(f, n, staged), (__attribute__((address_space(3))) void*)(dst + f * FL_LMAX + 64 * c), 4,
-                        (W.lo + 64 * c + lane) * 4, 0, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(dst + 64 * c), 4,
+                                                         vb + 64 * c, 0, 0, 0);
             return W;
         };
         // sum element n of the run from slot S (or pair by pair from the record)
         auto sum = [&](int n, auto S_, const Win& W) {
             if (W.len == 0) return;
             const float w = W.w;
-            if (W.len <= FL_LMAX) {
-                const float* ws = slot(S_);
+            if (W.staged) {
+                // the slot seen from sample 0 of the record: sample u at ws[u]
+                const float4* ws = slot(S_) - W.lo;
+                const float u_lo = (float)W.lo, u_hi = (float)(W.lo + W.len - 2);
+                // the run's bounds, opaque here so that the row masks are made
+                // where they are used (scalar work) instead of held in registers
+                int r0 = k0, r1 = k1;
+                asm volatile("" : "+s"(r0), "+s"(r1));
+                fl_static_for<FL_RW / 4>([&](auto G_) {
+                    constexpr int g0 = 4 * decltype(G_)::value;
+                    if (g0 > r1 || g0 + 3 < r0) return;  // wave-uniform
+                    // the group's reads first, then its products
+                    float wa[4], wb[4];
+                    float4 s0[4], s1[4];
 #pragma unroll
-                for (int k = 0; k < FL_RW; ++k) {
-                    if (k < k0 || k > k1) continue;  // wave-uniform
-                    const float v = fp[k] + W.e;
-                    const float qf = floorf(v);
-                    const float fr = v - qf;
-                    const int idx = w != 0.0f ? q[k] + (int)qf - W.lo : 0;
-                    const float wa = w * (1.0f - fr), wbb = w * fr;
-#pragma unroll
-                    for (int f = 0; f < FB; ++f) {
-                        const float s0 = ws[f * FL_LMAX + idx];
-                        const float s1 = ws[f * FL_LMAX + idx + 1];
-                        acc[k][f] = fmaf(wbb, s1, fmaf(wa, s0, acc[k][f]));
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int k = g0 + kk;
+                        // the run's rows only (a uniform 1 or 0)
+                        const float mk = __int_as_float((unsigned)(k - r0) <= (unsigned)(r1 - r0) ? 0x3f800000 : 0);
+                        const float wk = w * mk;
+                        const float v = fp[k] + W.e;
+                        const float qf = floorf(v);
+                        const float fr = v - qf;
+                        // read position, clamped into the window (integers below 2^24: exact in float)
+                        const int u = (int)__builtin_amdgcn_fmed3f(qfl[k] + qf, u_lo, u_hi);
+                        wa[kk] = wk * (1.0f - fr);
+                        wb[kk] = wk * fr;
+                        s0[kk] = ws[u];
+                        s1[kk] = ws[u + 1];
                     }
-                }
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int k = g0 + kk;
+                        acc[k][0] = fmaf(wb[kk], s1[kk].x, fmaf(wa[kk], s0[kk].x, acc[k][0]));
+                        acc[k][1] = fmaf(wb[kk], s1[kk].y, fmaf(wa[kk], s0[kk].y, acc[k][1]));
+                        acc[k][2] = fmaf(wb[kk], s1[kk].z, fmaf(wa[kk], s0[kk].z, acc[k][2]));
+                        acc[k][3] = fmaf(wb[kk], s1[kk].w, fmaf(wa[kk], s0[kk].w, acc[k][3]));
+                    }
+                });
             } else {
 #pragma unroll
                 for (int k = 0; k < FL_RW; ++k) {
-                    if (k < k0 || k > k1) continue;
+                    if (k < k0 || k > k1) continue;  // wave-uniform
                     const float v = fp[k] + W.e;
                     const float qf = floorf(v);
                     const float fr = v - qf;
@@ -593,11 +639,13 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
                     const float wa = w * (1.0f - fr), wbb = w * fr;
 #pragma unroll
                     for (int f = 0; f < FB; ++f) {
-                        const auto rs = chan(f, n, true);
+                        const auto rs = chan1(f, n);
                         const float s0 = buffer_load_f32(rs, off);
                         const float s1 = buffer_load_f32(rs, off + 4);
                         acc[k][f] = fmaf(wbb, s1, fmaf(wa, s0, acc[k][f]));
                     }
+                    // one row's loads in flight at a time: this path is the rare one
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         };
@@ -619,7 +667,7 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
                         ring[sl_next] = prep(n + FL_DEPTH - 1, std::integral_constant<int, sl_next>{});
                         // element n's copy has landed: only the FL_DEPTH - 1 later
                         // elements' loads may still be outstanding
-                        constexpr int later = (FL_DEPTH - 1) * FL_PIECES * FB;
+                        constexpr int later = (FL_DEPTH - 1) * FL_PIECES;
                         static_assert(later <= 63, "vmcnt range");
                         __builtin_amdgcn_s_waitcnt((later & 15) | ((later >> 4) << 14) | 0x70 | 0xF00);
                         sum(n, D_, ring[d]);
@@ -801,12 +849,11 @@ extern "C" int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, 
     // 2 rows 0.64 ms, x 4 rows 0.78, x 8 rows 0.82 (166 registers)
     const bool multi = n_frames >= 8;
     if (p.A == 1) {
-        if (multi) {
+        if (multi && fd_lds_fits(p.C, p.T)) {
             // groups of four frames: the staged-window kernel
-            constexpr int FB = 4;
             const dim3 grid((gr.nz + FL_WAVES * FL_RW - 1) / (FL_WAVES * FL_RW), (gr.nx + 63) / 64,
-                            (n_frames + FB - 1) / FB);
-            hipLaunchKernelGGL(fd_lds_kernel<FB>, grid, dim3(FL_WAVES * 64), 0, s, p, gr, ref_row, theta, rf, image);
+                            (n_frames + FL_FB - 1) / FL_FB);
+            hipLaunchKernelGGL(fd_lds_kernel, grid, dim3(FL_WAVES * 64), 0, s, p, gr, ref_row, theta, rf, image);
         } else {
             launch_fixed_das<1, 1, 4>(p, gr, ref_row, theta, rf, image, s);
         }
