@@ -13,9 +13,10 @@
 // A(m, k) = A[m sam + k sak] and B(k, n) = B[k sbk + n sbn] (bfloat16), so the
 // forward (H W^T), data-gradient (G W) and weight-gradient (G^T H) products
 // differ only in strides.  Tiles of 64 x 64 outputs, 4 waves, each wave a
-// 32 x 32 block as 2 x 2 MFMA 16x16x32 accumulators; the k dimension moves
-// through LDS in chunks of 32 with operands stored k-contiguous, so each
-// lane's 8 bfloat16 operand values are one 16-byte LDS read.
+// 32 x 32 block as 2 x 2 MFMA 16x16x32 accumulators; the k dimension is
+// staged in LDS in blocks of 256 with operands stored k-contiguous, and
+// multiplied in chunks of 32, so each lane's 8 bfloat16 operand values are
+// one 16-byte LDS read.
 //   A operand (16 x 32): lane l holds A[l % 16][8 (l / 16) .. +7]
 //   B operand (32 x 16): lane l holds B[8 (l / 16) .. +7][l % 16]
 //   D (16 x 16): register r of lane l holds D[4 (l / 16) + r][l % 16]
@@ -60,13 +61,14 @@ struct GemmArgs {
     int64_t ldz;
 };
 
-constexpr int GM = 64, GN = 64, GK = 32, GPAD = 8;  // LDS rows of GK + GPAD bfloat16
+constexpr int GM = 64, GN = 64, GK = 32, GPAD = 8;
+constexpr int GKB = 128;  // k staged in LDS at once
 static_assert(GM == GN, "operand staging assumes square tiles");
 
 template <int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[GM][GK + GPAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[GN][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t As[GM][GKB + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[GN][GKB + GPAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x * GM, n0 = blockIdx.y * GN;
@@ -82,59 +84,71 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    // each thread stages 8 elements of each operand per chunk; the next
-    // chunk's loads are issued before the current chunk's MFMAs
-    constexpr int PER = (GM * GK) / 256;
-    uint16_t ra[PER], rb[PER];
-    // element e of a chunk maps to (row, k) k-fastest when the operand is
-    // k-contiguous in memory and row-fastest otherwise, so neighbouring
-    // threads read neighbouring addresses in both layouts
-    const bool a_kfast = g.sak == 1, b_kfast = g.sbk == 1;
-    auto rk = [](int e, bool kfast, int& r, int& k) {
-        if (kfast) {
-            r = e / GK;
-            k = e % GK;
-        } else {
-            r = e % GM;
-            k = e / GM;
-        }
+    // The slice's k moves through LDS in blocks of GKB = 128: every load of a block
+    // is issued before the first is awaited (one memory latency per block, not
+    // one per 32-wide chunk: these products are small and latency-bound),
+    // then its chunks of GK are multiplied in ascending order, as a chunk-by-
+    // chunk walk would.  Each thread stages PER elements of each operand:
+    // element j of thread t is (row, k) = (t / GKB + j * 256 / GKB, t % GKB)
+    // when the operand is k-contiguous in memory and (t % GM, t / GM + j *
+    // 256 / GM) otherwise, so neighbouring threads read neighbouring
+    // addresses in both layouts.  Rows past the operand and k past the slice
+    // read a clamped (valid) address; such rows only feed outputs that are
+    // not stored, and the k past the slice up to the chunk's end are set to
+    // zero in LDS in both operands before the products.
+    constexpr int PER = (GM * GKB) / 256;
+    struct Walk {
+        int r0, k0, dr, dk;
     };
-    auto load = [&](int k0) {
+    auto walk = [&](bool kfast) {
+        return kfast ? Walk{tid / GKB, tid % GKB, 256 / GKB, 0} : Walk{tid % GM, tid / GM, 0, 256 / GM};
+    };
+    const Walk wa_ = walk(g.sak == 1), wb_ = walk(g.sbk == 1);
+    // byte offsets (32-bit: the host checks the operands' extents) through
+    // buffer records over each operand
+    const int sam = (int)g.sam * 2, sak = (int)g.sak * 2, sbk = (int)g.sbk * 2, sbn = (int)g.sbn * 2;
+    const auto rsa = make_rsrc(g.A, 0x7fffffff), rsb = make_rsrc(g.B, 0x7fffffff);
+    for (int kb = kbeg; kb < kend; kb += GKB) {
+        const int kn = min(GKB, kend - kb);
+        uint16_t ra[PER], rb[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int e = tid + 256 * j;
-            int r, k;
-            rk(e, a_kfast, r, k);
-            const int m = m0 + r, kk = k0 + k;
-            ra[j] = (m < g.M && kk < kend) ? g.A[(int64_t)m * g.sam + (int64_t)kk * g.sak] : (uint16_t)0;
-            rk(e, b_kfast, r, k);
-            const int n = n0 + r, kn = k0 + k;
-            rb[j] = (n < g.N && kn < kend) ? g.B[(int64_t)kn * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
+            const int ma = min(m0 + wa_.r0 + j * wa_.dr, g.M - 1), ka = kb + min(wa_.k0 + j * wa_.dk, kn - 1);
+            const int nb = min(n0 + wb_.r0 + j * wb_.dr, g.N - 1), kb_ = kb + min(wb_.k0 + j * wb_.dk, kn - 1);
+            ra[j] = __builtin_amdgcn_raw_buffer_load_b16(rsa, ma * sam + ka * sak, 0, 0);
+            rb[j] = __builtin_amdgcn_raw_buffer_load_b16(rsb, kb_ * sbk + nb * sbn, 0, 0);
         }
-    };
-    if (kbeg < kend) load(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        if (kb > kbeg) __syncthreads();  // the previous block's reads are done
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int e = tid + 256 * j;
-            int r, k;
-            rk(e, a_kfast, r, k);
-            As[r][k] = ra[j];
-            rk(e, b_kfast, r, k);
-            Bs[r][k] = rb[j];
+            As[wa_.r0 + j * wa_.dr][wa_.k0 + j * wa_.dk] = ra[j];
+            Bs[wb_.r0 + j * wb_.dr][wb_.k0 + j * wb_.dk] = rb[j];
+        }
+        const int kpad = (kn + GK - 1) / GK * GK;
+        if (kpad > kn) {
+            __syncthreads();  // the staged values are in place before the padding overwrites them
+            const int w = kpad - kn;
+            for (int e = tid; e < GM * w; e += 256) {
+                As[e / w][kn + e % w] = 0;
+                Bs[e / w][kn + e % w] = 0;
+            }
         }
         __syncthreads();
-        if (k0 + GK < kend) load(k0 + GK);
-        bf16x8 af[2], bfr[2];
+        const int nch = (kn + GK - 1) / GK;
+        for (int c = 0; c < nch; ++c) {
+            bf16x8 af[2], bfr[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) af[a] = *reinterpret_cast<const bf16x8*>(&As[wr + 16 * a + li][8 * lq]);
+            for (int a = 0; a < 2; ++a)
+                af[a] = *reinterpret_cast<const bf16x8*>(&As[wr + 16 * a + li][GK * c + 8 * lq]);
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bfr[b] = *reinterpret_cast<const bf16x8*>(&Bs[wc + 16 * b + li][8 * lq]);
+            for (int b = 0; b < 2; ++b)
+                bfr[b] = *reinterpret_cast<const bf16x8*>(&Bs[wc + 16 * b + li][GK * c + 8 * lq]);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
-        __syncthreads();
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        }
     }
 
     // split-K partials go to slice blockIdx.z of c32 (reduced afterwards)
@@ -451,6 +465,11 @@ static int32_t mlp_common(const char* name, const int32_t* widths, int32_t N, vo
     if ((reinterpret_cast<uintptr_t>(work) & 255) != 0)
         return fail(TIDAS_EINVAL, std::string(name) + ": workspace must be 256-byte aligned");
     if (N > (1 << 22)) return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": batch too large");
+    // the GEMMs address their bfloat16 operands with 32-bit byte offsets
+    int64_t widest = 1;
+    for (int i = 0; i < 5; ++i) widest = std::max<int64_t>(widest, L.w[i]);
+    if ((int64_t)N * widest * 2 >= ((int64_t)1 << 31) || widest * widest * 2 >= ((int64_t)1 << 31))
+        return fail(TIDAS_EUNSUPPORTED, std::string(name) + ": operands beyond 2 GiB");
     return TIDAS_OK;
 }
 
