@@ -77,8 +77,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=64, help="frames per step")
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle parity check")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
-    ap.add_argument("--cpu-pool", action="store_true",
-                    help="also time the CPU oracle over a pool of worker processes (one per host core, at most 16)")
+    ap.add_argument("--cpu-single-core", action="store_true",
+                    help="time the CPU oracle on one core only (no worker processes)")
     ap.add_argument("--only", choices=["tidas", "das"], default=None, help="time one op only (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one plain device copy of the input batch (known byte count) so "
@@ -134,9 +134,10 @@ def _oracle_apply_frames(task):
 
 
 def _cpu_pool():
-    """Worker processes for the pooled CPU baseline, forked before anything
-    initialises the GPU (they never touch it): one per host core the job may
-    use, at most 16.  None when the host has a single core."""
+    """Worker processes for the CPU baseline, forked before anything
+    initialises the GPU (they never touch it, and they have exited before the
+    GPU work starts): one per host core the job may use, at most 16.  None
+    when the host has a single core."""
     import multiprocessing
     n = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1))
     if n < 2:
@@ -155,34 +156,109 @@ def _cpu_model():
     return None
 
 
+def _main_oracle_inputs(s, phantoms, K):
+    """Host-side inputs of the oracle for the main workload, from the seeded
+    generators and the oracle itself (never from device results): the FP64
+    exact bank, the reflectivity maps of frames 0-3 and the RF of frame 0."""
+    import numpy as np
+
+    from oracle import kernels as o_k, simulate as o_sim
+    from workloads import generators
+    Z, X = s.nz, s.nx
+    xs = s.x0 + np.arange(X) * s.dx
+    zs = s.z0 + np.arange(Z) * s.dz
+    okw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, fc=s.fc, sigma=s.sigma,
+               n_samples=s.n_samples, angles=list(s.angles))
+    dkw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, angles=list(s.angles), fnumber=s.fnumber)
+    kb_o = o_k.exact_kernels(zs, s.dz, K, fnumber=s.fnumber, **okw)
+    R_host = []
+    for b in range(4):
+        xb, zb, ab = phantoms[b]
+        ib, jb, _, _ = generators.snap_to_grid(xb, zb, s.x0, s.dx, X, s.z0, s.dz, Z)
+        R_host.append(generators.reflectivity_map(ib, jb, ab, Z, X).astype(np.float32))
+    x, z, a = phantoms[0]
+    rf_o = o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **okw))
+    return dict(kb_o=kb_o, R_host=np.stack(R_host), rf_o=rf_o, xs=xs, zs=zs, dkw=dkw)
+
+
+def _main_cpu_baselines(host, single_core):
+    """The oracle timed on the host's cores, before the GPU is touched: the
+    line model over a pool of worker processes (one batch of 4 frames per task,
+    about 12 s), the line model on one core (about 12 s) and DAS on one core
+    (about 8 s).  The workers exit before this returns."""
+    import numpy as np
+
+    from oracle import das as o_das, tidas as o_t
+    kb_o, Rc = host["kb_o"], host["R_host"].astype(np.float64)
+    res = {}
+    pool = None if single_core else _cpu_pool()
+    if pool is not None:
+        n_w = pool._processes
+        tasks = [(kb_o, Rc)] * n_w
+        n_fr, t_c = 0, time.perf_counter()
+        while time.perf_counter() - t_c < 12.0:
+            n_fr += sum(pool.map(_oracle_apply_frames, tasks))
+        res["pool"] = {"value": n_fr / (time.perf_counter() - t_c), "unit": "frames/s", "cores": n_w,
+                       "kind": "oracle",
+                       "sample": f"FP64 oracle line model on {n_fr} frames of the workload over {n_w} worker "
+                                 f"processes (batches of 4 frames), about 12 s"}
+        pool.close()
+        pool.join()
+    n_fr, t_c = 0, time.perf_counter()
+    while time.perf_counter() - t_c < 12.0:
+        o_t.apply(kb_o, Rc)
+        n_fr += Rc.shape[0]
+    res["single"] = {"value": n_fr / (time.perf_counter() - t_c), "unit": "frames/s", "cores": 1,
+                     "kind": "oracle", "sample": f"FP64 oracle line model on {n_fr} frames of the workload "
+                                                 f"(batches of 4), about 12 s"}
+    n_d, t_c = 0, time.perf_counter()
+    while time.perf_counter() - t_c < 8.0:
+        o_das.das(host["rf_o"], host["xs"], host["zs"], **host["dkw"])
+        n_d += 1
+    res["das"] = {"value": n_d / (time.perf_counter() - t_c), "unit": "frames/s", "cores": 1,
+                  "kind": "oracle", "sample": f"FP64 oracle DAS on {n_d} frames, about 8 s"}
+    return res
+
+
 def run_main(args):
     import numpy as np
 
-    # the pooled CPU baseline's workers are forked here, before torch touches the GPU
-    # (opt-in: with the idle workers present the DAS launches measured ~40 % slower)
-    pool = _cpu_pool() if (args.cpu_pool and not args.no_cpu_baseline) else None
-
-    import torch
-
-    import paper_2507_15464_amd as td
     from workloads import config, generators
     from workloads.configs import CYSTS, N_SCATTERERS
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     s = config(2)
     B, K = args.batch, s.K
     Z, X = s.nz, s.nx
-
-    # ---- inputs (untimed): per-frame phantoms, RF synthesised on the GPU, snapped reflectivity maps
-    t_in = time.perf_counter()
-    rf = torch.empty((B, 1, s.n_elem, s.n_samples), device=dev, dtype=torch.float32)
-    R = torch.empty((B, Z, X), device=dev, dtype=torch.float32)
     phantoms = []
     for b in range(B):
         x, z, a, _ = generators.speckle_with_cysts(N_SCATTERERS[2], s.field_w, s.field_d, CYSTS["n"], CYSTS["r_lo"],
                                                    CYSTS["r_hi"], seed=b)
         phantoms.append((x, z, a))
+    # the oracle's inputs and the CPU baselines come first: the baseline's
+    # worker processes are forked, timed and gone before torch touches the GPU
+    host = cpu = None
+    if not (args.no_parity and args.no_cpu_baseline):
+        t_p = time.perf_counter()
+        host = _main_oracle_inputs(s, phantoms, K)
+        log(f"oracle inputs ready in {time.perf_counter() - t_p:.1f}s")
+    if not args.no_cpu_baseline:
+        cpu = _main_cpu_baselines(host, args.cpu_single_core)
+        log("cpu baselines: " + ", ".join(f"{k} {v['value']:.2f} {v['unit']} on {v['cores']} cores"
+                                          for k, v in cpu.items()))
+
+    import torch
+
+    import paper_2507_15464_amd as td
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # ---- inputs (untimed): per-frame phantoms, RF synthesised on the GPU, snapped reflectivity maps
+    t_in = time.perf_counter()
+    rf = torch.empty((B, 1, s.n_elem, s.n_samples), device=dev, dtype=torch.float32)
+    R = torch.empty((B, Z, X), device=dev, dtype=torch.float32)
+    for b in range(B):
+        x, z, a = phantoms[b]
         scat = torch.tensor(np.stack([x, z, a], 1), dtype=torch.float64, device=dev)
         td.simulate_rf(s, scat, out=rf[b])
         i, j, _, _ = generators.snap_to_grid(x, z, s.x0, s.dx, X, s.z0, s.dz, Z)
@@ -261,7 +337,7 @@ def run_main(args):
     nsb = next((n for n in (4, 6, 8, 10, 12) if n >= need), 0)
     cols = -(-X // 256) * 256
     if td.line_kernel(K, B, Z, X) == td._lib.LINE_FOUR_BLOCK:
-        kernel = f"tidas_b4_kernel<false,{nsb}>"
+        kernel = f"tidas_b4_kernel<false,{nsb},false>"
         mfma_flops = 2.0 * 6 * (16 * nsb) * (-(-Z // 128) * 128) * cols * B
     else:
         ns = ((64 + K - 1 + 15) // 16 + 3) // 4 * 4
@@ -340,25 +416,10 @@ def run_main(args):
                         "lines_global_sq": {p: e1d[p]["global_sq"] for p in ("5_uniform", "5_rising", "100_uniform")},
                         "paper_threshold": 0.05}
 
-    if not (args.no_parity and args.no_cpu_baseline):
-        # host-side inputs for the oracle, built from the seeded generators and
-        # the oracle itself (never from device results)
-        from oracle import das as o_das, kernels as o_k, simulate as o_sim, tidas as o_t
-        t_p = time.perf_counter()
-        xs = s.x0 + np.arange(X) * s.dx
-        zs = s.z0 + np.arange(Z) * s.dz
-        okw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, fc=s.fc, sigma=s.sigma,
-                   n_samples=s.n_samples, angles=list(s.angles))
-        dkw = dict(n_elem=s.n_elem, pitch=s.pitch, c=s.c, fs=s.fs, t0=s.t0, angles=list(s.angles), fnumber=s.fnumber)
-        kb_o = o_k.exact_kernels(zs, s.dz, K, fnumber=s.fnumber, **okw)
-        R_host = []
-        for b in range(4):
-            xb, zb, ab = phantoms[b]
-            ib, jb, _, _ = generators.snap_to_grid(xb, zb, s.x0, s.dx, X, s.z0, s.dz, Z)
-            R_host.append(generators.reflectivity_map(ib, jb, ab, Z, X).astype(np.float32))
-        R_host = np.stack(R_host)
-        rf_o = o_sim.to_fp32(o_sim.simulate_rf(x, z, a, **okw))
-        log(f"oracle inputs ready in {time.perf_counter() - t_p:.1f}s")
+    if host is not None:
+        from oracle import das as o_das, tidas as o_t
+        kb_o, R_host, rf_o = host["kb_o"], host["R_host"], host["rf_o"]
+        xs, zs, dkw = host["xs"], host["zs"], host["dkw"]
 
     if not args.no_parity:
         t_p = time.perf_counter()
@@ -377,37 +438,12 @@ def run_main(args):
         out["das"]["rel_l2_vs_oracle"] = float(np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref))
         log(f"parity done in {time.perf_counter() - t_p:.1f}s")
 
-    if not args.no_cpu_baseline:
-        Rc = R_host.astype(np.float64)
-        n_fr, t_c = 0, time.perf_counter()
-        while time.perf_counter() - t_c < 12.0:
-            o_t.apply(kb_o, Rc)
-            n_fr += Rc.shape[0]
-        cpu_tidas = n_fr / (time.perf_counter() - t_c)
-        out["cpu_baseline"] = {"value": cpu_tidas, "unit": "frames/s", "cores": 1, "kind": "oracle",
-                               "sample": f"FP64 oracle line model on {n_fr} frames of the workload "
-                                         f"(batches of 4), about 12 s"}
-        n_d, t_c = 0, time.perf_counter()
-        while time.perf_counter() - t_c < 8.0:
-            o_das.das(rf_o, xs, zs, **dkw)
-            n_d += 1
-        out["cpu_baseline_das"] = {"value": n_d / (time.perf_counter() - t_c), "unit": "frames/s", "cores": 1,
-                                   "kind": "oracle", "sample": f"FP64 oracle DAS on {n_d} frames, about 8 s"}
+    if cpu is not None:
+        # the all-core figure is the baseline; the one-core figures beside it
+        out["cpu_baseline"] = cpu.get("pool", cpu["single"])
+        out["cpu_baseline_single_core"] = cpu["single"]
+        out["cpu_baseline_das"] = cpu["das"]
         out["cpu_model"] = _cpu_model()
-        if pool is not None:
-            # the same oracle over a process pool, one batch of 4 frames per task, for ~12 s
-            n_w = pool._processes
-            tasks = [(kb_o, Rc)] * n_w
-            n_fr, t_c = 0, time.perf_counter()
-            while time.perf_counter() - t_c < 12.0:
-                n_fr += sum(pool.map(_oracle_apply_frames, tasks))
-            out["cpu_baseline_pool"] = {"value": n_fr / (time.perf_counter() - t_c), "unit": "frames/s",
-                                        "cores": n_w, "kind": "oracle",
-                                        "sample": f"FP64 oracle line model on {n_fr} frames over {n_w} worker "
-                                                  f"processes (batches of 4 frames), about 12 s"}
-    if pool is not None:
-        pool.close()
-        pool.join()
     print(json.dumps(out), flush=True)
 
 
