@@ -395,8 +395,10 @@ typedef struct tidas_frame {
 } tidas_frame;
 
 /* Launch-shape variants the batch entry points accept (chosen by an autotuner):
- *   DAS:        variant v -> 4 or 8 waves per workgroup (v & 1), and 2, 4 or 8
- *               workgroups per compute unit (v >> 1)
+ *   DAS:        variant v -> wave tile of 1 x 64, 2 x 32 or 4 x 16 pixels
+ *               (depth x lateral, v / 6), 4 or 8 waves per workgroup stacked
+ *               in depth (v & 1), and 2, 4 or 8 workgroups per compute unit
+ *               ((v % 6) >> 1)
  *   line model: variants 0-5: persistent workgroups over the 64-row tiles of
  *               all frames (split-bfloat16 two-block tile: 1, 2, 3, 4, 6 or 8
  *               workgroups per compute unit; for K > 321 the float32 matrix
@@ -408,7 +410,7 @@ typedef struct tidas_frame {
  *               four-block tile, walking the frame's 256-column tiles; it
  *               needs tidas_apply_batch_workspace_bytes and a 256-byte
  *               aligned workspace.  Every variant gives the same bits. */
-#define TIDAS_DAS_BATCH_VARIANTS 6
+#define TIDAS_DAS_BATCH_VARIANTS 18
 #define TIDAS_APPLY_BATCH_VARIANTS 7
 #define TIDAS_APPLY_BATCH_FOUR_BLOCK 6
 

@@ -54,7 +54,7 @@ class Frame(ctypes.Structure):
                 ("out", ctypes.c_void_p)]
 
 
-DAS_BATCH_VARIANTS = 6
+DAS_BATCH_VARIANTS = 18
 APPLY_BATCH_VARIANTS = 7
 APPLY_BATCH_FOUR_BLOCK = 6
 

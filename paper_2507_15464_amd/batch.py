@@ -2,7 +2,7 @@
 
 Each frame carries its own image grid and buffers; the array / transmit /
 receive set-up (and the tap count K for the line model) are shared.  The
-launch variant (workgroup shape, workgroups per compute unit, prefetch depth)
+launch variant (wave tile and workgroup shape, workgroups per compute unit, prefetch depth)
 is a parameter; ``autotune`` picks it by timing.
 """
 import ctypes

@@ -69,11 +69,12 @@ constexpr int DAS_BZ = 4;   // wave tiles per workgroup, stacked in depth
 // frames sharing the geometry.  rf points at the first frame's [A][C][T]
 // record, img at its [nz][nx] image; frame f of the group is rf + f *
 // frame_rf, img + f * frame_img.
-template <int FB, int NA>
+template <int FB, int NA, int WZ = das_wz(NA)>
 __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, int i_base, int j_base, int nfr,
                                          const float* __restrict__ rf, size_t frame_rf, float* img,
                                          size_t frame_img) {
-    constexpr int WZ = das_wz(NA), WX = das_wx(NA);
+    static_assert(WZ == 1 || WZ == 2 || WZ == 4, "wave tiles of 1 x 64, 2 x 32 or 4 x 16 pixels");
+    constexpr int WX = 64 / WZ;
     const int lane = threadIdx.x & 63;
     const int i = i_base + (lane % WZ);
     const int j = j_base + (lane / WZ);
@@ -720,7 +721,7 @@ __device__ __forceinline__ int find_frame(const BatchFrameDev* __restrict__ fr, 
     return lo;
 }
 
-template <int NA, int WAVES>
+template <int NA, int WAVES, int WZ>
 __global__ __launch_bounds__(WAVES * 64) void das_batch_kernel(const DasArgs p, const BatchFrameDev* __restrict__ fr,
                                                                int32_t n_frames, int64_t total) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -732,13 +733,12 @@ __global__ __launch_bounds__(WAVES * 64) void das_batch_kernel(const DasArgs p, 
         const int f = find_frame(fr, n_frames, t);
         const DasGrid gr = fr[f].grid;
         const int64_t local = t - fr[f].tile_start;
-        // tile of WAVES wave tiles stacked in depth
-        constexpr int WZ = das_wz(NA);
+        // tile of WAVES wave tiles (WZ x 64 / WZ pixels) stacked in depth
         const int row_tiles = (gr.nz + WAVES * WZ - 1) / (WAVES * WZ);
         const int rt = (int)(local % row_tiles);
         const int ct = (int)(local / row_tiles);
         const int i_base = (rt * WAVES + wave) * WZ;
-        if (i_base < gr.nz) das_wave<1, NA>(p, gr, i_base, ct * das_wx(NA), 1, fr[f].rf, 0, fr[f].out, 0);
+        if (i_base < gr.nz) das_wave<1, NA, WZ>(p, gr, i_base, ct * (64 / WZ), 1, fr[f].rf, 0, fr[f].out, 0);
     }
 }
 
@@ -916,6 +916,21 @@ extern "C" size_t tidas_batch_workspace_bytes(int32_t n_frames) {
     return n_frames < 1 ? 0 : ((128 * (size_t)n_frames + 255) / 256) * 256;
 }
 
+template <int NA>
+static void launch_das_batch(int wz, int waves, unsigned nblk, hipStream_t s, const DasArgs& p,
+                             const BatchFrameDev* tab, int32_t n_frames, int64_t total) {
+    const dim3 grid(nblk), block(waves * 64);
+    if (waves == 8) {
+        if (wz == 1) hipLaunchKernelGGL((das_batch_kernel<NA, 8, 1>), grid, block, 0, s, p, tab, n_frames, total);
+        else if (wz == 2) hipLaunchKernelGGL((das_batch_kernel<NA, 8, 2>), grid, block, 0, s, p, tab, n_frames, total);
+        else hipLaunchKernelGGL((das_batch_kernel<NA, 8, 4>), grid, block, 0, s, p, tab, n_frames, total);
+    } else {
+        if (wz == 1) hipLaunchKernelGGL((das_batch_kernel<NA, 4, 1>), grid, block, 0, s, p, tab, n_frames, total);
+        else if (wz == 2) hipLaunchKernelGGL((das_batch_kernel<NA, 4, 2>), grid, block, 0, s, p, tab, n_frames, total);
+        else hipLaunchKernelGGL((das_batch_kernel<NA, 4, 4>), grid, block, 0, s, p, tab, n_frames, total);
+    }
+}
+
 extern "C" int32_t das_beamform_batch(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                                       int32_t n_samples, const tidas_frame* frames, int32_t n_frames,
                                       void* workspace, size_t workspace_bytes, int32_t variant, void* stream) {
@@ -929,13 +944,14 @@ extern "C" int32_t das_beamform_batch(const tidas_array* array, const tidas_tx* 
             return fail(TIDAS_EUNSUPPORTED, "das_beamform_batch: sample indices exceed 2^28");
     if (variant < 0 || variant >= TIDAS_DAS_BATCH_VARIANTS)
         return fail(TIDAS_EINVAL, "das_beamform_batch: variant out of range");
+    // variant = 6 shape + occupancy: wave tile 1 x 64, 2 x 32 or 4 x 16 pixels;
+    // 4 or 8 waves per workgroup; 2, 4 or 8 workgroups per compute unit
+    const int wz = 1 << (variant / 6);
     const int waves = (variant & 1) ? 8 : 4;
-    const int per_cu = (variant >> 1) == 0 ? 2 : ((variant >> 1) == 1 ? 4 : 8);
+    const int per_cu = ((variant % 6) >> 1) == 0 ? 2 : (((variant % 6) >> 1) == 1 ? 4 : 8);
     hipStream_t s = (hipStream_t)stream;
     int64_t total = 0;
-    // the tile of the kernel launched below (one angle: das_wz(1); else das_wz(0) = das_wz(11))
-    const int na = p.A == 1 ? 1 : 0;
-    if ((st = upload_batch(frames, n_frames, waves * das_wz(na), das_wx(na), workspace, s, total))) return st;
+    if ((st = upload_batch(frames, n_frames, waves * wz, 64 / wz, workspace, s, total))) return st;
     int dev = 0, n_cu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
@@ -947,15 +963,8 @@ extern "C" int32_t das_beamform_batch(const tidas_array* array, const tidas_tx* 
     const int64_t nb = std::max<int64_t>(8, std::min<int64_t>(total, want));
     const unsigned nblk = (unsigned)((nb + 7) / 8 * 8);
     const BatchFrameDev* tab = (const BatchFrameDev*)workspace;
-    if (p.A == 11) {
-        if (waves == 8) hipLaunchKernelGGL((das_batch_kernel<11, 8>), dim3(nblk), dim3(512), 0, s, p, tab, n_frames, total);
-        else hipLaunchKernelGGL((das_batch_kernel<11, 4>), dim3(nblk), dim3(256), 0, s, p, tab, n_frames, total);
-    } else if (p.A == 1) {
-        if (waves == 8) hipLaunchKernelGGL((das_batch_kernel<1, 8>), dim3(nblk), dim3(512), 0, s, p, tab, n_frames, total);
-        else hipLaunchKernelGGL((das_batch_kernel<1, 4>), dim3(nblk), dim3(256), 0, s, p, tab, n_frames, total);
-    } else {
-        if (waves == 8) hipLaunchKernelGGL((das_batch_kernel<0, 8>), dim3(nblk), dim3(512), 0, s, p, tab, n_frames, total);
-        else hipLaunchKernelGGL((das_batch_kernel<0, 4>), dim3(nblk), dim3(256), 0, s, p, tab, n_frames, total);
-    }
+    if (p.A == 11) launch_das_batch<11>(wz, waves, nblk, s, p, tab, n_frames, total);
+    else if (p.A == 1) launch_das_batch<1>(wz, waves, nblk, s, p, tab, n_frames, total);
+    else launch_das_batch<0>(wz, waves, nblk, s, p, tab, n_frames, total);
     return check_launch("das_beamform_batch");
 }

@@ -237,7 +237,7 @@ def test_batch_entry_points_reject_invalid_arguments(lib):
     ws = ctypes.c_void_p(0x10000)
     geo = (ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx))
     assert lib.das_beamform_batch(*geo, 2048, frames, 2, ws, need - 1, 0, NUL) == -1       # small workspace
-    assert lib.das_beamform_batch(*geo, 2048, frames, 2, ws, need, 6, NUL) == -1           # variant
+    assert lib.das_beamform_batch(*geo, 2048, frames, 2, ws, need, _lib.DAS_BATCH_VARIANTS, NUL) == -1  # variant
     assert lib.das_beamform_batch(*geo, 2048, frames, 0, ws, need, 0, NUL) == -1           # no frames
     assert lib.das_beamform_batch(*geo, 2048, frames, 2, ctypes.c_void_p(0x10004), need, 0, NUL) == -1  # alignment
     assert lib.tidas_apply_batch(frames, 2, 64, ws, need, 0, NUL) == -1                     # even K
