@@ -337,7 +337,7 @@ def run_main(args):
     nsb = next((n for n in (4, 6, 8, 10, 12) if n >= need), 0)
     cols = -(-X // 256) * 256
     if td.line_kernel(K, B, Z, X) == td._lib.LINE_FOUR_BLOCK:
-        kernel = f"tidas_b4_kernel<false,{nsb},false>"
+        kernel = f"tidas_b4_kernel<false,{nsb},false,true>"
         mfma_flops = 2.0 * 6 * (16 * nsb) * (-(-Z // 128) * 128) * cols * B
     else:
         ns = ((64 + K - 1 + 15) // 16 + 3) // 4 * 4
@@ -527,7 +527,7 @@ def run_batch(args):
         # read every bank once (8 Z X + 4 Z K bytes per frame)
         "roofline": {"bound": "hbm", "achieved": batch_bytes / (app_prep * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": batch_bytes / (app_prep * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "tidas_b4_kernel<false,6,true> (prepared batch)", "bytes_per_launch": batch_bytes},
+                     "kernel": "tidas_b4_kernel<false,6,true,true> (prepared batch)", "bytes_per_launch": batch_bytes},
     }
     print(json.dumps(out), flush=True)
 

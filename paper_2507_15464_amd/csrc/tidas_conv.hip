@@ -918,7 +918,9 @@ struct B4Geom {
 // frames of a plain launch (the ring runs on from one to the next), each
 // addressed from a base 256 columns further on, so rows past the image still
 // fall outside the range and read 0; columns past X are computed but not stored.
-template <bool ADJ, int NSB, bool BATCH>
+// PLAIN: alpha = 1 and no base, the results stored as accumulated (the
+// epilogue's base values then hold no registers).
+template <bool ADJ, int NSB, bool BATCH, bool PLAIN>
 __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, const uint16_t* __restrict__ images,
                                                               const float* __restrict__ In, float* Out,
                                                               const ConvFrameDev* __restrict__ tab, int32_t n_tab) {
@@ -1091,8 +1093,8 @@ __global__ __launch_bounds__(B4_THREADS) void tidas_b4_kernel(const B4Geom g, co
         // byte and columns past X start at INT32_MIN, so the range check drops both.
         const int vbase = ((i0 + 4 * gk) * X + col) * 4;
         const int vstart = col < X ? vbase : INT32_MIN;
-        const bool has_base = Base0 != nullptr;
-        const bool plain = g.alpha == 1.0f && !has_base;  // results stored as accumulated
+        constexpr bool plain = PLAIN;
+        const bool has_base = !PLAIN && Base0 != nullptr;
         // base values of the block to be stored two iterations on (two buffers:
         // consecutive blocks are stored two iterations apart)
         float bv[2][16];
@@ -1358,17 +1360,17 @@ static void launch_b4_prepare(const float* kernels, int32_t K, int32_t Z, int mo
     const dim3 grid((unsigned)((per_tile + 255) / 256), (unsigned)n_rt, (unsigned)n_modes);
     hipLaunchKernelGGL(b4_prepare_kernel, grid, dim3(256), 0, stream, kernels, K, Z, n_rt, nsb, out, mode0);
 }
-template <bool ADJ>
+template <bool ADJ, bool PLAIN>
 static void launch_b4_mode(const B4Geom& g, int nsb, const uint16_t* images, const float* in, float* out,
                            hipStream_t stream) {
     const dim3 grid(g.n_blocks), block(B4_THREADS);
     const size_t lds = b4_image_bytes(nsb);
     switch (nsb) {
-        case 4: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 4, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
-        case 6: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 6, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
-        case 8: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 8, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
-        case 10: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 10, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
-        default: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 12, false>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        case 4: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 4, false, PLAIN>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        case 6: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 6, false, PLAIN>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        case 8: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 8, false, PLAIN>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        case 10: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 10, false, PLAIN>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
+        default: hipLaunchKernelGGL((tidas_b4_kernel<ADJ, 12, false, PLAIN>), grid, block, lds, stream, g, images, in, out, nullptr, 0); break;
     }
 }
 // images: the four-block band images of the operator's mode, tile rt at
@@ -1389,8 +1391,15 @@ static void launch_b4(bool adj, const uint16_t* images, int32_t K, const float* 
     g.alpha = alpha;
     g.beta = beta;
     g.base = base;
-    if (adj) launch_b4_mode<true>(g, b4_nsb(K), images, in, out, stream);
-    else launch_b4_mode<false>(g, b4_nsb(K), images, in, out, stream);
+    // alpha = 1 and no base: the plain store (no base registers held)
+    const bool plain = alpha == 1.0f && base == nullptr;
+    if (adj) {
+        if (plain) launch_b4_mode<true, true>(g, b4_nsb(K), images, in, out, stream);
+        else launch_b4_mode<true, false>(g, b4_nsb(K), images, in, out, stream);
+    } else {
+        if (plain) launch_b4_mode<false, true>(g, b4_nsb(K), images, in, out, stream);
+        else launch_b4_mode<false, false>(g, b4_nsb(K), images, in, out, stream);
+    }
 }
 
 static bool mfma_fits(int K, int Z, int X) {
@@ -1992,11 +2001,11 @@ static int32_t b4_batch_launch(const char* name, int32_t n_frames, int32_t K, co
     const ConvFrameDev* d = (const ConvFrameDev*)workspace;
     const uint16_t* img = (const uint16_t*)workspace;
     switch (nsb) {
-        case 4: hipLaunchKernelGGL((tidas_b4_kernel<false, 4, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
-        case 6: hipLaunchKernelGGL((tidas_b4_kernel<false, 6, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
-        case 8: hipLaunchKernelGGL((tidas_b4_kernel<false, 8, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
-        case 10: hipLaunchKernelGGL((tidas_b4_kernel<false, 10, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
-        default: hipLaunchKernelGGL((tidas_b4_kernel<false, 12, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        case 4: hipLaunchKernelGGL((tidas_b4_kernel<false, 4, true, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        case 6: hipLaunchKernelGGL((tidas_b4_kernel<false, 6, true, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        case 8: hipLaunchKernelGGL((tidas_b4_kernel<false, 8, true, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        case 10: hipLaunchKernelGGL((tidas_b4_kernel<false, 10, true, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
+        default: hipLaunchKernelGGL((tidas_b4_kernel<false, 12, true, true>), grid, block, lds, s, g, img, nullptr, nullptr, d, n_frames); break;
     }
     return check_launch(name);
 }
