@@ -121,6 +121,25 @@ const char* tidas_version(void);
 const char* tidas_last_error(void);
 
 /*
+ * Debug builds (the library compiled with -DTIDAS_DEBUG: libtidas_debug.so)
+ * check inside the kernels what the derivations promise and record failures
+ * as bits, without trapping:
+ *   TIDAS_DBG_FD_WINDOW     the fixed-delay beamformer read a weighted sample
+ *                           outside the channel window it staged in LDS
+ *   TIDAS_DBG_NONFINITE_IN  a non-finite input (RF sample, map value or
+ *                           kernel tap) entered DAS or the line model
+ *   TIDAS_DBG_STUDY_SPAN    the single-point study skipped a non-zero echo
+ *                           sample (its support table was wrong)
+ * tidas_debug_flags synchronises the device and writes the OR of the bits
+ * recorded since the last reset to *flags (HOST); reset != 0 clears them.
+ * A release build writes 0 and returns TIDAS_EUNSUPPORTED.
+ */
+#define TIDAS_DBG_FD_WINDOW 1u
+#define TIDAS_DBG_NONFINITE_IN 2u
+#define TIDAS_DBG_STUDY_SPAN 4u
+int32_t tidas_debug_flags(uint32_t* flags, int32_t reset);
+
+/*
  * Exact Delay-and-Sum, Sec. 2 eqn:appF: every pixel gets its own delay
  * profile.  For each frame b
  *   image[b][i][j] = sum_a sum_n w(x_j - x_n, z_i) *

@@ -10,6 +10,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtidas.so")
+DEBUG_LIB_PATH = os.path.join(HERE, "libtidas_debug.so")  # built with -DTIDAS_DEBUG
 
 TIDAS_OK = 0
 TIDAS_EINVAL = -1
@@ -22,6 +23,7 @@ MODE_LINE = 2
 MODE_LATERAL = 3
 LINE_FOUR_BLOCK, LINE_TWO_BLOCK, LINE_FP32_MATRIX, LINE_VECTOR = 1, 2, 3, 4
 KGRAD_SPLIT_BF16, KGRAD_FP32 = 1, 2
+DBG_FD_WINDOW, DBG_NONFINITE_IN, DBG_STUDY_SPAN = 1, 2, 4
 
 
 class TidasError(RuntimeError):
@@ -65,6 +67,7 @@ _Z = ctypes.c_size_t
 _SIGS = {
     "tidas_version": (ctypes.c_char_p, []),
     "tidas_last_error": (ctypes.c_char_p, []),
+    "tidas_debug_flags": (_I, [ctypes.POINTER(ctypes.c_uint32), _I]),
     "das_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),
                           _P, _I, _I, _P, _P]),
     "tidas_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),

@@ -3,7 +3,9 @@
 Every source under ``csrc/`` is compiled with hipcc for gfx950 only, then
 linked into one shared library next to this file.  Packed FP32 instructions
 are disabled (``-packed-fp32-ops``): the kernels are written for plain
-v_fma_f32.
+v_fma_f32.  ``build(debug=True)`` makes ``libtidas_debug.so`` with
+``-DTIDAS_DEBUG``: the same kernels with their device-side checks on
+(``tidas_debug_flags``).
 """
 import concurrent.futures as cf
 import os
@@ -16,6 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtidas.so")
+BUILD_DEBUG = os.path.join(HERE, "_build_debug")
+LIB_DEBUG = os.path.join(HERE, "libtidas_debug.so")
 
 ARCH = "gfx950"
 FLAGS = [
@@ -40,8 +44,8 @@ def sources():
     return out
 
 
-def _compile(src, extra):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(src, extra, build_dir=BUILD):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
     cmd = [hipcc()] + FLAGS + extra + lang + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,23 +54,27 @@ def _compile(src, extra):
     return obj
 
 
-def build(verbose=False, extra=()):
-    """Compile every source and link ``libtidas.so``; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=False, extra=(), debug=False):
+    """Compile every source and link ``libtidas.so`` (``libtidas_debug.so``
+    with ``debug``); returns its path."""
+    build_dir, lib = (BUILD_DEBUG, LIB_DEBUG) if debug else (BUILD, LIB)
+    extra = list(extra) + (["-DTIDAS_DEBUG"] if debug else [])
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, list(extra)), srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, extra, build_dir), srcs))
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} sources", file=sys.stderr)
-    return LIB
+        print(f"built {lib} from {len(srcs)} sources", file=sys.stderr)
+    return lib
 
 
 if __name__ == "__main__":
     build(verbose=True)
+    build(verbose=True, debug=True)

@@ -49,8 +49,30 @@ int32_t validate_grid(const tidas_grid* g) {
     return TIDAS_OK;
 }
 
+// flag words of the source files with debug checks
+uint32_t tidas_debug_read_das(bool reset);
+uint32_t tidas_debug_read_conv(bool reset);
+uint32_t tidas_debug_read_study(bool reset);
+
 }  // namespace tidas
 
 extern "C" const char* tidas_version(void) { return "tidas-mi355x 0.1 (gfx950)"; }
+
+extern "C" int32_t tidas_debug_flags(uint32_t* flags, int32_t reset) {
+    if (!flags) return tidas::fail(TIDAS_EINVAL, "tidas_debug_flags: null flags pointer");
+#ifdef TIDAS_DEBUG
+    if (hipDeviceSynchronize() != hipSuccess) return tidas::fail(TIDAS_EHIP, "tidas_debug_flags: synchronize");
+    const bool r = reset != 0;
+    const uint32_t v = tidas::tidas_debug_read_das(r) | tidas::tidas_debug_read_conv(r) |
+                       tidas::tidas_debug_read_study(r);
+    if (v == ~0u) return tidas::fail(TIDAS_EHIP, "tidas_debug_flags: flag word copy failed");
+    *flags = v;
+    return TIDAS_OK;
+#else
+    (void)reset;
+    *flags = 0;
+    return tidas::fail(TIDAS_EUNSUPPORTED, "tidas_debug_flags: not a debug build (TIDAS_DEBUG)");
+#endif
+}
 
 extern "C" const char* tidas_last_error(void) { return tidas::g_last_error.c_str(); }

@@ -32,6 +32,36 @@ inline int32_t check_hip(hipError_t e, const char* what) {
     return TIDAS_OK;
 }
 
+// ---------------------------------------------------------- debug checks ----
+// Built with -DTIDAS_DEBUG (libtidas_debug.so), kernels check values and
+// indices against what their derivation promises; a failed check sets its
+// bit in its source file's flag word (nothing traps, and every access stays
+// as in the release build).  tidas_debug_flags returns the OR of the words.
+// (the bits, TIDAS_DBG_*, are declared in tidas.h)
+#ifdef TIDAS_DEBUG
+#define TIDAS_DEBUG_FLAGS_DEFINE(name)                                                               \
+    static __device__ unsigned int tidas_dbg_word;                                                   \
+    uint32_t tidas_debug_read_##name(bool reset) {                                                   \
+        unsigned int v = 0;                                                                          \
+        if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(tidas_dbg_word), sizeof(v)) != hipSuccess) v = ~0u;   \
+        if (reset) {                                                                                 \
+            const unsigned int z = 0;                                                                \
+            if (hipMemcpyToSymbol(HIP_SYMBOL(tidas_dbg_word), &z, sizeof(z)) != hipSuccess) v = ~0u; \
+        }                                                                                            \
+        return v;                                                                                    \
+    }
+#define TIDAS_DCHECK(cond, bit)                                    \
+    do {                                                           \
+        if (!(cond)) atomicOr(&tidas_dbg_word, (unsigned)(bit)); \
+    } while (0)
+#else
+#define TIDAS_DEBUG_FLAGS_DEFINE(name) \
+    uint32_t tidas_debug_read_##name(bool) { return 0; }
+#define TIDAS_DCHECK(cond, bit) \
+    do {                        \
+    } while (0)
+#endif
+
 // ------------------------------------------------------------ workspace ----
 // Entry points that need device scratch take (workspace, workspace_bytes): a
 // caller buffer of at least the size their query returns, 256-byte aligned,

@@ -37,6 +37,8 @@
 
 namespace tidas {
 
+TIDAS_DEBUG_FLAGS_DEFINE(das)
+
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 
 constexpr int DAS_MAX_ANGLES = 32;
@@ -166,6 +168,8 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
                         const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
                         const floatx2 sp =
                             __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
+                        TIDAS_DCHECK((wa == 0.0f || __builtin_isfinite(sp[0])) && (wb == 0.0f || __builtin_isfinite(sp[1])),
+                                     TIDAS_DBG_NONFINITE_IN);
                         acc[f] = fmaf(wb, sp[1], fmaf(wa, sp[0], acc[f]));
                     }
                 } else {
@@ -178,6 +182,7 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
                     const auto rs = make_rsrc(rf + ch * p.T, nfr > 0 ? row_bytes : 0u);
                     const float s0 = buffer_load_f32(rs, off);
                     const float s1 = buffer_load_f32(rs, off1);
+                    TIDAS_DCHECK(w == 0.0f || (__builtin_isfinite(s0) && __builtin_isfinite(s1)), TIDAS_DBG_NONFINITE_IN);
                     acc[0] = fmaf(w, fmaf(fr, s1 - s0, s0), acc[0]);
                 }
             }
@@ -614,6 +619,7 @@ __global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasG
                         const float qf = floorf(v);
                         const float fr = v - qf;
                         // read position, clamped into the window (integers below 2^24: exact in float)
+                        TIDAS_DCHECK(wk == 0.0f || (qfl[k] + qf >= u_lo && qfl[k] + qf <= u_hi), TIDAS_DBG_FD_WINDOW);
                         const int u = (int)__builtin_amdgcn_fmed3f(qfl[k] + qf, u_lo, u_hi);
                         wa[kk] = wk * (1.0f - fr);
                         wb[kk] = wk * fr;
@@ -867,6 +873,7 @@ extern "C" int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, 
 
 // ------------------------------------------------------------------ batch ----
 namespace tidas {
+
 
 int32_t validate_batch(const char* name, const tidas_frame* frames, int32_t n_frames, void* workspace,
                        size_t workspace_bytes, bool need_rf, bool need_conv) {

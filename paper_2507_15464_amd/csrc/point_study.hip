@@ -35,6 +35,8 @@
 #include "envelope.hpp"
 
 namespace tidas {
+
+TIDAS_DEBUG_FLAGS_DEFINE(study)
 namespace {
 
 constexpr int ST_THREADS = 256;
@@ -265,6 +267,11 @@ __global__ __launch_bounds__(ST_THREADS) void study_pair_kernel(const StudyGeom 
             for (int j = 0; j < ST_RB; ++j) {
                 const int e = j * g.C + n;
                 const int k = k_rn[e] + q;
+#ifdef TIDAS_DEBUG
+                // the support table: samples it leaves out are zero
+                if (k >= 0 && k < g.T && (k < su.x || k > su.y))
+                    TIDAS_DCHECK(w_rn[e] == 0.0 || row[k] == 0.0, TIDAS_DBG_STUDY_SPAN);
+#endif
                 if (k >= su.x - 1 && k <= su.y) {
                     const double f = f_rn[e];
                     const double s0 = k >= su.x ? row[k] : 0.0;

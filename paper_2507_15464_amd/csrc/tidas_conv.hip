@@ -46,6 +46,8 @@
 
 namespace tidas {
 
+TIDAS_DEBUG_FLAGS_DEFINE(conv)
+
 // Bijective remap of the linear block id: hardware dispatches block L to XCD
 // L % 8; logical tiles [x * q + min(x, r), ...) go to XCD x.
 __device__ __forceinline__ int xcd_remap(int L, int n) {
@@ -496,7 +498,10 @@ __device__ __forceinline__ const T* uniform_ptr(const T* p) {
 }
 
 // bfloat16 parts of the exact split, each as the top half of a 32-bit word
+// (every operand of the line model, map and bank, passes here: a debug build
+// flags non-finite ones)
 __device__ __forceinline__ void split3(float v, uint32_t& w0, uint32_t& w1, uint32_t& w2) {
+    TIDAS_DCHECK(__builtin_isfinite(v), TIDAS_DBG_NONFINITE_IN);
     const uint32_t u = __float_as_uint(v);
     const float r1 = v - __uint_as_float(u & 0xffff0000u);
     const uint32_t u1 = __float_as_uint(r1);

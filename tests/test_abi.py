@@ -44,6 +44,20 @@ def test_version_string(lib):
     assert b"gfx950" in lib.tidas_version()
 
 
+def test_debug_flags_in_the_release_and_debug_builds(lib):
+    """The release library has no device checks: tidas_debug_flags answers
+    EUNSUPPORTED with 0 flags; both builds export every declared symbol."""
+    v = ctypes.c_uint32(7)
+    assert lib.tidas_debug_flags(ctypes.byref(v), 0) == _lib.TIDAS_EUNSUPPORTED and v.value == 0
+    assert lib.tidas_debug_flags(None, 0) == _lib.TIDAS_EINVAL
+    if not os.path.exists(_lib.DEBUG_LIB_PATH):
+        pytest.fail("libtidas_debug.so is not built (run __graft_entry__.build())")
+    dbg = _lib.load(_lib.DEBUG_LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(dbg, name), name
+    assert dbg.tidas_debug_flags(None, 0) == _lib.TIDAS_EINVAL
+
+
 def _geom():
     arr = _lib.make_array(64, 0.3e-3, 1540.0)
     tx = _lib.make_tx([0.0], 40e6, 0.0, 5e6, 2.0)
