@@ -67,6 +67,12 @@ int main() {
                                              nullptr, 0, nullptr), E);
     expect("simulate negative", tidas_simulate_rf(&arr, &tx, (const double*)A, -1, 2048, F, nullptr, 0, nullptr), E);
 
+    // the debug-flag query of a release build
+    uint32_t dbg_flags = 7;
+    expect("debug flags release", tidas_debug_flags(&dbg_flags, 1), U);
+    expect("debug flags zeroed", (long long)dbg_flags, 0);
+    expect("debug flags null", tidas_debug_flags(nullptr, 0), E);
+
     // caller workspaces: queries and checks
     expect("build ws exact", (long long)tidas_build_kernels_workspace_bytes(64, 65, 0), 0);
     const size_t bws = tidas_build_kernels_workspace_bytes(64, 65, 1);
