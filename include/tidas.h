@@ -168,7 +168,10 @@ int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_r
  * (ones), e.g. the weights tidas_build_kernels returns in paper mode.  rf,
  * image and n_frames as in das_beamform; image must not alias an input.
  * Waves whose rows share one reference (one law per neighbourhood or per
- * line) evaluate the law once per element for all their rows.
+ * line) evaluate the law once per element for all their rows; with eight or
+ * more frames of one plane wave they also stage each element's channel
+ * window for those rows in LDS (four frames per read) instead of gathering
+ * every pair from memory.  The same values either way.
  */
 int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                        const tidas_grid* grid, const float* rf, int32_t n_samples, int32_t n_frames,
