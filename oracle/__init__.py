@@ -31,6 +31,6 @@ All arithmetic is float64 (numpy).  Nothing is blocked, fused or reordered
 beyond what the definitions state.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test against a
-closed form, a brute-force loop, a library routine or an invariant, except
-the two listed as "parity unpinned" in their own module headers.
+closed form, a brute-force loop, a library routine or an invariant; none is
+unpinned.
 """
