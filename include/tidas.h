@@ -147,11 +147,17 @@ int32_t tidas_debug_flags(uint32_t* flags, int32_t reset);
  * with tau_n = (x sin a + z cos a) / c + sqrt((x - x_n)^2 + z^2) / c, the
  * angles coherently compounded.  rf is DEV [n_frames][A][C][n_samples],
  * image DEV [n_frames][nz][nx] (overwritten).  n_frames >= 1,
- * n_samples >= 2.  All frames share one geometry.
+ * n_samples >= 2.  All frames share one geometry.  workspace DEV (device
+ * scratch convention above): with one angle and eight or more frames the
+ * call reads the RF through a frame-interleaved copy, four frames per
+ * 16-byte load ([ceil(n_frames / 4)][A][C][n_samples][4] floats);
+ * das_beamform_workspace_bytes gives its size (0: no scratch needed).
  */
 int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                      const tidas_grid* grid, const float* rf, int32_t n_samples,
-                     int32_t n_frames, float* image, void* stream);
+                     int32_t n_frames, float* image, void* workspace, size_t workspace_bytes,
+                     void* stream);
+size_t das_beamform_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_samples, int32_t n_frames);
 
 /*
  * The paper's time-invariant beamformer applied to the RF (Sec. 2.3 eqn:tDAS:

@@ -69,7 +69,8 @@ _SIGS = {
     "tidas_last_error": (ctypes.c_char_p, []),
     "tidas_debug_flags": (_I, [ctypes.POINTER(ctypes.c_uint32), _I]),
     "das_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),
-                          _P, _I, _I, _P, _P]),
+                          _P, _I, _I, _P, _P, _Z, _P]),
+    "das_beamform_workspace_bytes": (_Z, [_I, _I, _I, _I]),
     "tidas_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),
                             _P, _I, _I, _P, _P, _P, _P]),
     "tidas_build_kernels": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx),

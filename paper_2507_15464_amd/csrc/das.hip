@@ -40,6 +40,7 @@ namespace tidas {
 TIDAS_DEBUG_FLAGS_DEFINE(das)
 
 typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int DAS_MAX_ANGLES = 32;
 
@@ -70,8 +71,10 @@ constexpr int DAS_BZ = 4;   // wave tiles per workgroup, stacked in depth
 // One wave: the WZ x WX pixel tile at rows i_base.., columns j_base.., for FB
 // frames sharing the geometry.  rf points at the first frame's [A][C][T]
 // record, img at its [nz][nx] image; frame f of the group is rf + f *
-// frame_rf, img + f * frame_img.
-template <int FB, int NA, int WZ = das_wz(NA)>
+// frame_rf, img + f * frame_img.  IL (FB a multiple of 4): rf points at the
+// group's frame-interleaved record [A][C][T][FB] instead (das_interleave_kernel),
+// so one 16-byte load returns a sample of four frames.
+template <int FB, int NA, int WZ = das_wz(NA), bool IL = false>
 __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, int i_base, int j_base, int nfr,
                                          const float* __restrict__ rf, size_t frame_rf, float* img,
                                          size_t frame_img) {
@@ -158,19 +161,41 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
                     const int d = off - oc;
                     const float wa = d == 0 ? w * (1.0f - fr) : (d == -4 ? w * fr : 0.0f);
                     const float wb = d == 0 ? w * fr : (d == 4 ? w * (1.0f - fr) : 0.0f);
+                    if constexpr (IL) {
+                        // channel ch of the group: T samples x FB frames; sample
+                        // q of frames 4k..4k+3 at byte 16 (FB / 4 q + k)
+                        static_assert(FB % 4 == 0, "interleaved records hold frames in fours");
+                        constexpr int NQ = FB / 4;
+                        const auto rs = make_rsrc(rf + ch * p.T * FB, row_bytes * FB);
+                        floatx4 s0[NQ], s1[NQ];
 #pragma unroll
-                    for (int f = 0; f < FB; ++f) {
-                        // every frame slot loads (a slot past the group's last
-                        // frame has an empty record: it reads 0 and is never
-                        // stored), so the loads of all slots and of the next
-                        // element are in flight together
-                        const bool fv = f < nfr;
-                        const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
-                        const floatx2 sp =
-                            __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
-                        TIDAS_DCHECK((wa == 0.0f || __builtin_isfinite(sp[0])) && (wb == 0.0f || __builtin_isfinite(sp[1])),
-                                     TIDAS_DBG_NONFINITE_IN);
-                        acc[f] = fmaf(wb, sp[1], fmaf(wa, sp[0], acc[f]));
+                        for (int k = 0; k < NQ; ++k) {
+                            s0[k] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, oc * FB + 16 * k, 0, 0));
+                            s1[k] = __builtin_bit_cast(floatx4,
+                                                       __builtin_amdgcn_raw_buffer_load_b128(rs, (oc + 4) * FB + 16 * k, 0, 0));
+                        }
+#pragma unroll
+                        for (int f = 0; f < FB; ++f) {
+                            const float a0 = s0[f / 4][f % 4], a1 = s1[f / 4][f % 4];
+                            TIDAS_DCHECK((wa == 0.0f || __builtin_isfinite(a0)) && (wb == 0.0f || __builtin_isfinite(a1)),
+                                         TIDAS_DBG_NONFINITE_IN);
+                            acc[f] = fmaf(wb, a1, fmaf(wa, a0, acc[f]));
+                        }
+                    } else {
+#pragma unroll
+                        for (int f = 0; f < FB; ++f) {
+                            // every frame slot loads (a slot past the group's last
+                            // frame has an empty record: it reads 0 and is never
+                            // stored), so the loads of all slots and of the next
+                            // element are in flight together
+                            const bool fv = f < nfr;
+                            const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
+                            const floatx2 sp =
+                                __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
+                            TIDAS_DCHECK((wa == 0.0f || __builtin_isfinite(sp[0])) && (wb == 0.0f || __builtin_isfinite(sp[1])),
+                                         TIDAS_DBG_NONFINITE_IN);
+                            acc[f] = fmaf(wb, sp[1], fmaf(wa, sp[0], acc[f]));
+                        }
                     }
                 } else {
                     // one frame (per-angle work not shared): two dword reads, each
@@ -196,15 +221,61 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
 }
 
 // workgroup = DAS_BZ wave tiles stacked in depth
-template <int FB, int NA>
+// (IL: rf is the frame-interleaved copy, group g's [A][C][T][FB] record at
+// the same offset, g FB frame_rf, as its first frame in the plain layout)
+template <int FB, int NA, bool IL = false>
 __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid gr, const float* __restrict__ rf,
                                                   float* __restrict__ img) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int fr0 = blockIdx.z * FB;
     const size_t frame_rf = (size_t)p.A * p.C * p.T;
     const size_t frame_img = (size_t)gr.nz * gr.nx;
-    das_wave<FB, NA>(p, gr, (blockIdx.x * DAS_BZ + wave) * das_wz(NA), blockIdx.y * das_wx(NA), min(FB, p.n_frames - fr0),
-                     rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
+    das_wave<FB, NA, das_wz(NA), IL>(p, gr, (blockIdx.x * DAS_BZ + wave) * das_wz(NA), blockIdx.y * das_wx(NA),
+                                     min(FB, p.n_frames - fr0), rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img,
+                                     frame_img);
+}
+
+// Frame-interleaved copy of the RF for das_kernel<FB, NA, true>: frames
+// 0..B-1 of [B][E] (E = A C T samples per frame) -> [G][E][FB], G = ceil(B /
+// FB), frames past B zero.  One thread per (group, sample): FB coalesced
+// dword reads, FB / 4 16-byte writes (contiguous over the wave).
+template <int FB>
+__global__ __launch_bounds__(256) void das_interleave_kernel(const float* __restrict__ rf, int32_t B, int64_t E,
+                                                             float* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= E) return;
+    const int g = blockIdx.y;
+    float v[FB];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        const int b = g * FB + f;
+        v[f] = b < B ? rf[(size_t)b * E + e] : 0.0f;
+    }
+    floatx4* dst = reinterpret_cast<floatx4*>(out + ((size_t)g * E + e) * FB);
+#pragma unroll
+    for (int k = 0; k < FB / 4; ++k) dst[k] = floatx4{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
+}
+// The same for E a multiple of 4 and rf 16-byte aligned: one thread per four
+// consecutive samples, FB 16-byte reads (one per frame) and a 4 x FB
+// transpose in registers written as 4 FB contiguous floats.
+template <int FB>
+__global__ __launch_bounds__(256) void das_interleave4_kernel(const float* __restrict__ rf, int32_t B, int64_t E,
+                                                              float* __restrict__ out) {
+    const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (e >= E) return;
+    const int g = blockIdx.y;
+    floatx4 v[FB];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        const int b = g * FB + f;
+        v[f] = b < B ? *reinterpret_cast<const floatx4*>(rf + (size_t)b * E + e) : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    floatx4* dst = reinterpret_cast<floatx4*>(out + ((size_t)g * E + e) * FB);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int k = 0; k < FB / 4; ++k)
+            dst[t * (FB / 4) + k] = floatx4{v[4 * k][t], v[4 * k + 1][t], v[4 * k + 2][t], v[4 * k + 3][t]};
 }
 
 // ------------------------------------------------- fixed-delay beamformer ----
@@ -755,6 +826,17 @@ static void launch_das(const DasArgs& p, const DasGrid& gr, const float* rf, flo
     hipLaunchKernelGGL((das_kernel<FB, NA>), grid, dim3(256), 0, s, p, gr, rf, img);
 }
 
+// Frames per interleaved group and the copy's bytes (0: the call reads the
+// RF in place: one frame per thread, or several angles).
+constexpr int DAS_IL_FB = 4;
+static size_t das_il_bytes(int32_t A, int32_t C, int32_t T, int32_t n_frames) {
+    if (A != 1 || n_frames < 8) return 0;
+    const int64_t groups = (n_frames + DAS_IL_FB - 1) / DAS_IL_FB;
+    return ((size_t)groups * DAS_IL_FB * A * C * T * sizeof(float) + 255) / 256 * 256;
+}
+// the interleaved channel record (T FB floats) and its byte offsets fit 31 bits
+static bool das_il_fits(int32_t T) { return (int64_t)T * 4 * DAS_IL_FB + 64 < ((int64_t)1 << 31); }
+
 template <int FB, int NA, int FD_RB>
 static void launch_fixed_das(const DasArgs& p, const DasGrid& gr, const int32_t* ref, const float* theta,
                              const float* rf, float* img, hipStream_t s) {
@@ -806,9 +888,16 @@ static DasGrid to_grid(const tidas_grid* g) { return DasGrid{g->nz, g->nx, g->z0
 
 using namespace tidas;
 
+extern "C" size_t das_beamform_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_samples,
+                                               int32_t n_frames) {
+    if (n_angles < 1 || n_elem < 1 || n_samples < 2 || n_frames < 1 || !das_il_fits(n_samples)) return 0;
+    return das_il_bytes(n_angles, n_elem, n_samples, n_frames);
+}
+
 extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                                 const tidas_grid* grid, const float* rf, int32_t n_samples,
-                                int32_t n_frames, float* image, void* stream) {
+                                int32_t n_frames, float* image, void* workspace, size_t workspace_bytes,
+                                void* stream) {
     DasArgs p;
     int32_t st = das_setup("das_beamform", array, tx, rx, n_samples, p);
     if (st) return st;
@@ -817,10 +906,34 @@ extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, co
     if (n_frames < 1) return fail(TIDAS_EINVAL, "das_beamform: n_frames must be >= 1");
     if ((const void*)rf == (const void*)image) return fail(TIDAS_EINVAL, "das_beamform: image aliases rf");
     if (!das_grid_in_range(p, grid)) return fail(TIDAS_EUNSUPPORTED, "das_beamform: sample indices exceed 2^28");
+    const size_t need = das_il_fits(p.T) ? das_il_bytes(p.A, p.C, p.T, n_frames) : 0;
+    if ((st = workspace_check("das_beamform", workspace, workspace_bytes, need))) return st;
     p.n_frames = n_frames;
     const DasGrid gr = to_grid(grid);
     hipStream_t s = (hipStream_t)stream;
-    // several frames per thread amortise the geometry over a batch
+    // several frames per thread amortise the geometry over a batch; their
+    // samples are read four frames per 16-byte load from an interleaved copy
+    if (need) {
+        Workspace w;
+        if ((st = workspace_acquire("das_beamform", workspace, need, s, w))) return st;
+        float* il = reinterpret_cast<float*>(w.ptr);
+        const int64_t E = (int64_t)p.A * p.C * p.T;
+        const unsigned n_groups = (unsigned)((n_frames + DAS_IL_FB - 1) / DAS_IL_FB);
+        if (E % 4 == 0 && (reinterpret_cast<uintptr_t>(rf) & 15) == 0)
+            hipLaunchKernelGGL(das_interleave4_kernel<DAS_IL_FB>, dim3((unsigned)((E / 4 + 255) / 256), n_groups),
+                               dim3(256), 0, s, rf, n_frames, E, il);
+        else
+            hipLaunchKernelGGL(das_interleave_kernel<DAS_IL_FB>, dim3((unsigned)((E + 255) / 256), n_groups),
+                               dim3(256), 0, s, rf, n_frames, E, il);
+        const dim3 grid((gr.nz + DAS_BZ * das_wz(1) - 1) / (DAS_BZ * das_wz(1)), (gr.nx + das_wx(1) - 1) / das_wx(1),
+                        (n_frames + DAS_IL_FB - 1) / DAS_IL_FB);
+        hipLaunchKernelGGL((das_kernel<DAS_IL_FB, 1, true>), grid, dim3(256), 0, s, p, gr, il, image);
+        if ((st = check_launch("das_beamform"))) {
+            workspace_release("das_beamform", w, s);
+            return st;
+        }
+        return workspace_release("das_beamform", w, s);
+    }
     const bool multi = n_frames >= 8;
     if (p.A == 1) {
         if (multi) launch_das<4, 1>(p, gr, rf, image, s);

@@ -32,14 +32,14 @@ int main() {
     const int E = TIDAS_EINVAL, U = TIDAS_EUNSUPPORTED;
 
     // das_beamform / tidas_beamform
-    expect("das null rf", das_beamform(&arr, &tx, &rx, &grid, nullptr, 2048, 1, F, nullptr), E);
+    expect("das null rf", das_beamform(&arr, &tx, &rx, &grid, nullptr, 2048, 1, F, nullptr, 0, nullptr), E);
     tidas_array bad_arr{0, 0.3e-3, 1540.0};
-    expect("das bad array", das_beamform(&bad_arr, &tx, &rx, &grid, F, 2048, 1, (float*)B, nullptr), E);
+    expect("das bad array", das_beamform(&bad_arr, &tx, &rx, &grid, F, 2048, 1, (float*)B, nullptr, 0, nullptr), E);
     tidas_tx bad_tx{1, &ang_bad, 40e6, 0.0, 5e6, 2.0};
-    expect("das bad angle", das_beamform(&arr, &bad_tx, &rx, &grid, F, 2048, 1, (float*)B, nullptr), E);
+    expect("das bad angle", das_beamform(&arr, &bad_tx, &rx, &grid, F, 2048, 1, (float*)B, nullptr, 0, nullptr), E);
     tidas_grid bad_grid{0, 32, 1e-3, 1e-4, -1e-3, 1e-4};
-    expect("das bad grid", das_beamform(&arr, &tx, &rx, &bad_grid, F, 2048, 1, (float*)B, nullptr), E);
-    expect("das aliasing", das_beamform(&arr, &tx, &rx, &grid, F, 2048, 1, F, nullptr), E);
+    expect("das bad grid", das_beamform(&arr, &tx, &rx, &bad_grid, F, 2048, 1, (float*)B, nullptr, 0, nullptr), E);
+    expect("das aliasing", das_beamform(&arr, &tx, &rx, &grid, F, 2048, 1, F, nullptr, 0, nullptr), E);
     expect("beamform null", tidas_beamform(&arr, &tx, &rx, &grid, nullptr, 2048, 1, nullptr, nullptr, F, nullptr), E);
 
     // line model and its forms

@@ -99,26 +99,44 @@ def test_conv_rejects_invalid_arguments(lib, args):
 def test_das_rejects_invalid_arguments(lib):
     arr, tx, rx, g = _geom()
     ok = (ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g))
-    assert lib.das_beamform(*ok, NUL, 2048, 1, FAKE, NUL) == _lib.TIDAS_EINVAL
-    assert lib.das_beamform(*ok, FAKE, 1, 1, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EINVAL
-    assert lib.das_beamform(*ok, FAKE, 2048, 0, ctypes.c_void_p(0x2000), NUL) == _lib.TIDAS_EINVAL
-    assert lib.das_beamform(*ok, FAKE, 2048, 1, FAKE, NUL) == _lib.TIDAS_EINVAL  # aliasing
+    assert lib.das_beamform(*ok, NUL, 2048, 1, FAKE, NUL, 0, NUL) == _lib.TIDAS_EINVAL
+    assert lib.das_beamform(*ok, FAKE, 1, 1, ctypes.c_void_p(0x2000), NUL, 0, NUL) == _lib.TIDAS_EINVAL
+    assert lib.das_beamform(*ok, FAKE, 2048, 0, ctypes.c_void_p(0x2000), NUL, 0, NUL) == _lib.TIDAS_EINVAL
+    assert lib.das_beamform(*ok, FAKE, 2048, 1, FAKE, NUL, 0, NUL) == _lib.TIDAS_EINVAL  # aliasing
     for bad in (_lib.make_array(0, 0.3e-3, 1540.0), _lib.make_array(64, -1.0, 1540.0),
                 _lib.make_array(64, 0.3e-3, 0.0)):
-        assert lib.das_beamform(ctypes.byref(bad), *ok[1:], FAKE, 2048, 1, ctypes.c_void_p(0x2000), NUL) == -1
+        assert lib.das_beamform(ctypes.byref(bad), *ok[1:], FAKE, 2048, 1, ctypes.c_void_p(0x2000), NUL, 0, NUL) == -1
     for badtx in (_lib.make_tx([], 40e6, 0, 5e6, 2), _lib.make_tx([0.0], 0.0, 0, 5e6, 2),
                   _lib.make_tx([2.0], 40e6, 0, 5e6, 2)):
         assert lib.das_beamform(ok[0], ctypes.byref(badtx), *ok[2:], FAKE, 2048, 1, ctypes.c_void_p(0x2000),
-                                NUL) == -1
+                                NUL, 0, NUL) == -1
     badrx = _lib.make_rx(0.0)
     assert lib.das_beamform(ok[0], ok[1], ctypes.byref(badrx), ok[3], FAKE, 2048, 1, ctypes.c_void_p(0x2000),
-                            NUL) == -1
+                            NUL, 0, NUL) == -1
     for badg in (_lib.make_grid(0, 4, 0, 1e-4, 0, 1e-4), _lib.make_grid(4, 4, 0, -1e-4, 0, 1e-4),
                  _lib.make_grid(4, 4, float("nan"), 1e-4, 0, 1e-4)):
-        assert lib.das_beamform(*ok[:3], ctypes.byref(badg), FAKE, 2048, 1, ctypes.c_void_p(0x2000), NUL) == -1
+        assert lib.das_beamform(*ok[:3], ctypes.byref(badg), FAKE, 2048, 1, ctypes.c_void_p(0x2000), NUL, 0, NUL) == -1
     tx33 = _lib.make_tx([0.0] * 33, 40e6, 0, 5e6, 2)
     assert lib.das_beamform(ok[0], ctypes.byref(tx33), *ok[2:], FAKE, 2048, 1, ctypes.c_void_p(0x2000),
-                            NUL) == _lib.TIDAS_EUNSUPPORTED
+                            NUL, 0, NUL) == _lib.TIDAS_EUNSUPPORTED
+    # the interleaved copy's workspace (one angle, eight frames or more)
+    img = ctypes.c_void_p(0x2000)
+    assert lib.das_beamform(*ok, FAKE, 2048, 8, img, NUL, 64, NUL) == _lib.TIDAS_EINVAL  # bytes without a buffer
+    need = lib.das_beamform_workspace_bytes(1, 64, 2048, 8)
+    assert lib.das_beamform(*ok, FAKE, 2048, 8, img, ctypes.c_void_p(0x10040), need, NUL) == _lib.TIDAS_EINVAL
+    assert lib.das_beamform(*ok, FAKE, 2048, 8, img, ctypes.c_void_p(0x10000), need - 256, NUL) == _lib.TIDAS_EINVAL
+
+
+def test_das_workspace_query(lib):
+    """Interleaved groups of four frames, 256-byte rounded; none below eight
+    frames, with several angles or for invalid sizes."""
+    assert lib.das_beamform_workspace_bytes(1, 64, 2048, 8) == 2 * 4 * 64 * 2048 * 4
+    assert lib.das_beamform_workspace_bytes(1, 128, 4096, 64) == 64 * 128 * 4096 * 4
+    assert lib.das_beamform_workspace_bytes(1, 3, 5, 9) == (3 * 4 * 3 * 5 * 4 + 255) // 256 * 256
+    assert lib.das_beamform_workspace_bytes(1, 64, 2048, 7) == 0
+    assert lib.das_beamform_workspace_bytes(11, 64, 2048, 64) == 0
+    assert lib.das_beamform_workspace_bytes(1, 0, 2048, 64) == 0
+    assert lib.das_beamform_workspace_bytes(1, 64, 1, 64) == 0
 
 
 def test_fixed_delay_beamform_rejects_invalid_arguments(lib):

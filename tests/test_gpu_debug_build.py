@@ -94,6 +94,8 @@ def test_nonfinite_inputs_are_flagged(dbg):
     td.apply(kb, R)
     td.adjoint(td.prepare(kb), R)
     td.das_beamform(speckle_rf(s, 1, 800), s)
+    rf8 = speckle_rf(s, 8, 810)
+    td.das_beamform(rf8, s)  # eight frames: the interleaved copy
     assert flags(dbg) == 0
     R[2, 100, 10] = float("nan")
     td.apply(td.prepare(kb), R)
@@ -101,6 +103,9 @@ def test_nonfinite_inputs_are_flagged(dbg):
     rf = speckle_rf(s, 1, 801)
     rf[0, 0, 32, 800] = float("inf")  # a centre channel inside the imaged depths
     td.das_beamform(rf, s)
+    assert flags(dbg) & _lib.DBG_NONFINITE_IN
+    rf8[5, 0, 32, 800] = float("inf")
+    td.das_beamform(rf8, s)
     assert flags(dbg) & _lib.DBG_NONFINITE_IN
     assert flags(dbg) == 0  # reset by the previous query
 
