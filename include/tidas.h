@@ -124,8 +124,6 @@ const char* tidas_last_error(void);
  * Debug builds (the library compiled with -DTIDAS_DEBUG: libtidas_debug.so)
  * check inside the kernels what the derivations promise and record failures
  * as bits, without trapping:
- *   TIDAS_DBG_FD_WINDOW     the fixed-delay beamformer read a weighted sample
- *                           outside the channel window it staged in LDS
  *   TIDAS_DBG_NONFINITE_IN  a non-finite input (RF sample, map value or
  *                           kernel tap) entered DAS or the line model
  *   TIDAS_DBG_STUDY_SPAN    the single-point study skipped a non-zero echo
@@ -134,7 +132,6 @@ const char* tidas_last_error(void);
  * recorded since the last reset to *flags (HOST); reset != 0 clears them.
  * A release build writes 0 and returns TIDAS_EUNSUPPORTED.
  */
-#define TIDAS_DBG_FD_WINDOW 1u
 #define TIDAS_DBG_NONFINITE_IN 2u
 #define TIDAS_DBG_STUDY_SPAN 4u
 int32_t tidas_debug_flags(uint32_t* flags, int32_t reset);
@@ -174,14 +171,16 @@ size_t das_beamform_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_
  * (ones), e.g. the weights tidas_build_kernels returns in paper mode.  rf,
  * image and n_frames as in das_beamform; image must not alias an input.
  * Waves whose rows share one reference (one law per neighbourhood or per
- * line) evaluate the law once per element for all their rows; with eight or
- * more frames of one plane wave they also stage each element's channel
- * window for those rows in LDS (four frames per read) instead of gathering
- * every pair from memory.  The same values either way.
+ * line) evaluate the law once per element for all their rows.  workspace
+ * as in das_beamform (eight or more frames of one plane wave read the RF
+ * through the same interleaved copy); tidas_beamform_workspace_bytes gives
+ * its size.
  */
 int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                        const tidas_grid* grid, const float* rf, int32_t n_samples, int32_t n_frames,
-                       const int32_t* ref_row, const float* theta, float* image, void* stream);
+                       const int32_t* ref_row, const float* theta, float* image, void* workspace,
+                       size_t workspace_bytes, void* stream);
+size_t tidas_beamform_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_samples, int32_t n_frames);
 
 /*
  * Per-depth-row kernel bank of the line model, evaluated on the centre line

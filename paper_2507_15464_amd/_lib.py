@@ -23,7 +23,7 @@ MODE_LINE = 2
 MODE_LATERAL = 3
 LINE_FOUR_BLOCK, LINE_TWO_BLOCK, LINE_FP32_MATRIX, LINE_VECTOR = 1, 2, 3, 4
 KGRAD_SPLIT_BF16, KGRAD_FP32 = 1, 2
-DBG_FD_WINDOW, DBG_NONFINITE_IN, DBG_STUDY_SPAN = 1, 2, 4
+DBG_NONFINITE_IN, DBG_STUDY_SPAN = 2, 4
 
 
 class TidasError(RuntimeError):
@@ -72,7 +72,8 @@ _SIGS = {
                           _P, _I, _I, _P, _P, _Z, _P]),
     "das_beamform_workspace_bytes": (_Z, [_I, _I, _I, _I]),
     "tidas_beamform": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx), ctypes.POINTER(Grid),
-                            _P, _I, _I, _P, _P, _P, _P]),
+                            _P, _I, _I, _P, _P, _P, _P, _Z, _P]),
+    "tidas_beamform_workspace_bytes": (_Z, [_I, _I, _I, _I]),
     "tidas_build_kernels": (_I, [ctypes.POINTER(Array), ctypes.POINTER(Tx), ctypes.POINTER(Rx),
                                  ctypes.POINTER(Grid), _I, _I, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _Z,
                                  _P]),

@@ -99,8 +99,9 @@ def tidas_beamform(rf, setup, ref_row=None, theta=None, grid=None, out=None):
         out = torch.empty((B, grid.nz, grid.nx), device=rf.device, dtype=torch.float32)
     _check_tensor(out, "out")
     arr, tx, rx, g = _descs(setup, grid)
+    ws, nws = _workspace(lib.tidas_beamform_workspace_bytes(len(setup.angles), setup.n_elem, T, B), rf.device)
     _lib.check(lib.tidas_beamform(ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g),
-                                  _ptr(r4), T, B, _ptr(ref_row), _ptr(theta), _ptr(out), _stream()))
+                                  _ptr(r4), T, B, _ptr(ref_row), _ptr(theta), _ptr(out), _ptr(ws), nws, _stream()))
     return out[0] if squeeze else out
 
 

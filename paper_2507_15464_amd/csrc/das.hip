@@ -237,45 +237,29 @@ __global__ __launch_bounds__(256) void das_kernel(const DasArgs p, const DasGrid
 
 // Frame-interleaved copy of the RF for das_kernel<FB, NA, true>: frames
 // 0..B-1 of [B][E] (E = A C T samples per frame) -> [G][E][FB], G = ceil(B /
-// FB), frames past B zero.  One thread per (group, sample): FB coalesced
-// dword reads, FB / 4 16-byte writes (contiguous over the wave).
-template <int FB>
+// FB), frames past B zero.  A thread takes samples e + 256 k (k < S) of its
+// block's 256 S: per sample FB dword reads (each coalesced over the wave) and
+// FB / 4 16-byte writes (a wave writes 64 FB contiguous floats).
+template <int FB, int S>
 __global__ __launch_bounds__(256) void das_interleave_kernel(const float* __restrict__ rf, int32_t B, int64_t E,
                                                              float* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= E) return;
     const int g = blockIdx.y;
-    float v[FB];
+    const int64_t e0 = (int64_t)blockIdx.x * 256 * S + threadIdx.x;
 #pragma unroll
-    for (int f = 0; f < FB; ++f) {
-        const int b = g * FB + f;
-        v[f] = b < B ? rf[(size_t)b * E + e] : 0.0f;
+    for (int k = 0; k < S; ++k) {
+        const int64_t e = e0 + 256 * k;
+        if (e < E) {
+            float v[FB];
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                const int b = g * FB + f;
+                v[f] = b < B ? rf[(size_t)b * E + e] : 0.0f;
+            }
+            floatx4* dst = reinterpret_cast<floatx4*>(out + ((size_t)g * E + e) * FB);
+#pragma unroll
+            for (int q = 0; q < FB / 4; ++q) dst[q] = floatx4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+        }
     }
-    floatx4* dst = reinterpret_cast<floatx4*>(out + ((size_t)g * E + e) * FB);
-#pragma unroll
-    for (int k = 0; k < FB / 4; ++k) dst[k] = floatx4{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
-}
-// The same for E a multiple of 4 and rf 16-byte aligned: one thread per four
-// consecutive samples, FB 16-byte reads (one per frame) and a 4 x FB
-// transpose in registers written as 4 FB contiguous floats.
-template <int FB>
-__global__ __launch_bounds__(256) void das_interleave4_kernel(const float* __restrict__ rf, int32_t B, int64_t E,
-                                                              float* __restrict__ out) {
-    const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-    if (e >= E) return;
-    const int g = blockIdx.y;
-    floatx4 v[FB];
-#pragma unroll
-    for (int f = 0; f < FB; ++f) {
-        const int b = g * FB + f;
-        v[f] = b < B ? *reinterpret_cast<const floatx4*>(rf + (size_t)b * E + e) : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    }
-    floatx4* dst = reinterpret_cast<floatx4*>(out + ((size_t)g * E + e) * FB);
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int k = 0; k < FB / 4; ++k)
-            dst[t * (FB / 4) + k] = floatx4{v[4 * k][t], v[4 * k + 1][t], v[4 * k + 2][t], v[4 * k + 3][t]};
 }
 
 // ------------------------------------------------- fixed-delay beamformer ----
@@ -291,7 +275,7 @@ __global__ __launch_bounds__(256) void das_interleave4_kernel(const float* __res
 // per neighbourhood or per line), the law of an element is computed once and
 // serves FD_RB rows, so a pair costs its index, its reads and its FMAs only;
 // a wave whose rows have different references evaluates the law per row.
-template <int FB, int NA, int FD_RB>
+template <int FB, int NA, int FD_RB, bool IL = false>
 __device__ __forceinline__ void fd_wave(const DasArgs& p, const DasGrid& gr, int i_base, int j_base, int nfr,
                                         const int32_t* __restrict__ ref, const float* __restrict__ theta,
                                         const float* __restrict__ rf, size_t frame_rf, float* img, size_t frame_img) {
@@ -365,12 +349,24 @@ __device__ __forceinline__ void fd_wave(const DasArgs& p, const DasGrid& gr, int
             const int d = off - oc;
             const float wa = d == 0 ? w * (1.0f - fr) : (d == -4 ? w * fr : 0.0f);
             const float wb = d == 0 ? w * fr : (d == 4 ? w * (1.0f - fr) : 0.0f);
+            if constexpr (IL) {
+                // the frame-interleaved record, as in das_wave
+                static_assert(FB == 4, "interleaved records hold frames in fours");
+                const auto rs = make_rsrc(rf + ch * p.T * FB, row_bytes * FB);
+                const floatx4 s0 = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, oc * FB, 0, 0));
+                const floatx4 s1 =
+                    __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, (oc + 4) * FB, 0, 0));
 #pragma unroll
-            for (int f = 0; f < FB; ++f) {
-                const bool fv = f < nfr;
-                const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
-                const floatx2 sp = __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
-                acc[k][f] = fmaf(wb, sp[1], fmaf(wa, sp[0], acc[k][f]));
+                for (int f = 0; f < FB; ++f) acc[k][f] = fmaf(wb, s1[f], fmaf(wa, s0[f], acc[k][f]));
+            } else {
+#pragma unroll
+                for (int f = 0; f < FB; ++f) {
+                    const bool fv = f < nfr;
+                    const auto rs = make_rsrc(rf + (fv ? f : 0) * frame_rf + ch * p.T, fv ? row_bytes : 0u);
+                    const floatx2 sp =
+                        __builtin_bit_cast(floatx2, __builtin_amdgcn_raw_buffer_load_b64(rs, oc, 0, 0));
+                    acc[k][f] = fmaf(wb, sp[1], fmaf(wa, sp[0], acc[k][f]));
+                }
             }
         } else {
             const int off1 = (q + (int)(qf + 1.0f)) * 4;
@@ -412,6 +408,7 @@ __device__ __forceinline__ void fd_wave(const DasArgs& p, const DasGrid& gr, int
             const Law L = law_at(r_wave);
             int n_lo, n_hi;
             element_range(gr.z0 + (double)r_wave * gr.dz, n_lo, n_hi);
+#pragma unroll 2
             for (int n = n_lo; n <= n_hi; ++n) {
                 const float nf = (float)n;
                 const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
@@ -421,8 +418,18 @@ __device__ __forceinline__ void fd_wave(const DasArgs& p, const DasGrid& gr, int
                 for (int k = 0; k < FD_RB; ++k) accumulate(k, ch_a + n, q[k], fpart[k] + ke, w);
             }
         } else {
-            // every element (weights vanish outside each row's own aperture)
-            for (int n = 0; n < p.C; ++n) {
+            // the elements of the widest aperture among the wave's rows (the
+            // deepest reference; weights vanish outside each row's own)
+            int r_max = rk[0];
+#pragma unroll
+            for (int k = 1; k < FD_RB; ++k) r_max = max(r_max, rk[k]);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) r_max = max(r_max, __shfl_xor(r_max, o));
+            r_max = __builtin_amdgcn_readfirstlane(r_max);
+            int n_lo, n_hi;
+            element_range(gr.z0 + (double)r_max * gr.dz, n_lo, n_hi);
+#pragma unroll 2
+            for (int n = n_lo; n <= n_hi; ++n) {
                 const float nf = (float)n;
                 const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
 #pragma unroll
@@ -449,7 +456,7 @@ __device__ __forceinline__ void fd_wave(const DasArgs& p, const DasGrid& gr, int
 }
 
 // workgroup = DAS_BZ wave tiles stacked in depth, each WZ x FD_RB rows
-template <int FB, int NA, int FD_RB>
+template <int FB, int NA, int FD_RB, bool IL = false>
 __global__ __launch_bounds__(256) void fixed_das_kernel(const DasArgs p, const DasGrid gr, const int32_t* __restrict__ ref,
                                                         const float* __restrict__ theta, const float* __restrict__ rf,
                                                         float* __restrict__ img) {
@@ -459,316 +466,8 @@ __global__ __launch_bounds__(256) void fixed_das_kernel(const DasArgs p, const D
     const size_t frame_img = (size_t)gr.nz * gr.nx;
     const int i_base = (blockIdx.x * DAS_BZ + wave) * das_wz(NA) * FD_RB;
     if (i_base >= gr.nz) return;
-    fd_wave<FB, NA, FD_RB>(p, gr, i_base, blockIdx.y * das_wx(NA), min(FB, p.n_frames - fr0), ref, theta,
-                    rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
-}
-
-// --------------------------------- fixed-delay beamformer, staged windows ----
-// One plane wave and groups of four frames.  The time-invariant law makes a
-// row's read position in element n's channel u_k = U_k + E(j, n): a per-row
-// term U_k = fs (tau_tx(x_j, z_k) + z_k / c - t0), which grows by
-// fs dz (1 + cos a) / c per row, plus the receive excess E of the row's
-// reference depth, the same for every row of a run that shares the
-// reference.  So a wave (64 columns, lane = column, FL_RW consecutive rows)
-// reads, for one element, a single window of the channel, from the run's
-// first row to its last, over the lanes inside the element's aperture.  A
-// superset of it (bounded from the columns' extent and the aperture, with a
-// margin of two samples) is copied into the wave's LDS by direct-to-LDS
-// loads, FL_DEPTH - 1 elements ahead of the one being summed.  The copy
-// interleaves the four frames ([sample][frame]: each load's lane L takes
-// frame L % 4 of sample L / 4 of a 16-sample piece), so one 16-byte LDS read
-// returns a sample of all four frames, and the two samples of a pair are two
-// such reads from one address; the law (square root, reciprocal, Hann
-// weight) is computed once per (column, element, run) and each row's index
-// split and interpolation weights once for the four frames.  Rows are summed
-// in groups of four (their reads in flight together); a group that a run
-// covers only in part gives its other rows weight 0, and every index is
-// clamped into the staged window, so lanes outside the aperture (weight 0)
-// read staged values too.  The ring slots are distinct LDS arrays, so the
-// compiler sees that a read of one slot does not depend on the copies still
-// landing in the others, and the wait before each element's sum is the
-// explicit one (its loads done, the later ones in flight).  A window longer
-// than FL_LMAX samples, or reaching outside the record, is read from global
-// memory pair by pair instead (there each frame's own range check gives the
-// zeros outside the record).  The index split, the law and the sum of each
-// pair are those of the DAS kernel with several frames per thread, so
-// self-referenced rows give DAS's values.
-constexpr int FL_RW = 16;     // rows per wave
-constexpr int FL_FB = 4;      // frames per wave, interleaved in LDS
-constexpr int FL_LMAX = 256;  // samples per staged window
-constexpr int FL_PIECES = FL_LMAX * FL_FB / 64;  // direct-to-LDS loads per window
-constexpr int FL_DEPTH = 4;   // ring slots: the element being summed and the next three
-constexpr int FL_WAVES = 4;   // waves per workgroup, stacked in depth
-
-template <int N, typename F, int... I>
-__device__ __forceinline__ void fl_static_for_impl(F&& f, std::integer_sequence<int, I...>) {
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void fl_static_for(F&& f) {
-    fl_static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
-}
-
-// Byte offsets of the four frames' copies of one channel must fit 31 bits.
-__host__ __device__ inline bool fd_lds_fits(int32_t C, int32_t T) {
-    return (int64_t)(FL_FB - 1) * C * T * 4 + (int64_t)T * 4 + 64 * 4 < ((int64_t)1 << 31);
-}
-
-__global__ __launch_bounds__(256) void fd_lds_kernel(const DasArgs p, const DasGrid gr, const int32_t* __restrict__ ref,
-                                                     const float* __restrict__ theta, const float* __restrict__ rf,
-                                                     float* __restrict__ img) {
-    constexpr int FB = FL_FB;
-    static_assert(FL_DEPTH == 4, "four ring slots below");
-    // ring slots, one array each: [wave][sample][frame]
-    __shared__ float4 fl_s0[FL_WAVES * FL_LMAX];
-    __shared__ float4 fl_s1[FL_WAVES * FL_LMAX];
-    __shared__ float4 fl_s2[FL_WAVES * FL_LMAX];
-    __shared__ float4 fl_s3[FL_WAVES * FL_LMAX];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int i_base = (blockIdx.x * FL_WAVES + wave) * FL_RW;
-    if (i_base >= gr.nz) return;  // wave-uniform: the kernel has no barrier
-    const int fr0 = blockIdx.z * FB;
-    const int nfr = min(FB, p.n_frames - fr0);
-    const size_t frame_rf = (size_t)p.C * p.T;
-    const size_t frame_img = (size_t)gr.nz * gr.nx;
-    const float* rf0 = rf + fr0 * frame_rf;
-    float* img0 = img + fr0 * frame_img;
-    const int wo = wave * FL_LMAX;
-    auto slot = [&](auto D_) -> float4* {
-        constexpr int d = decltype(D_)::value;
-        if constexpr (d == 0) return fl_s0 + wo;
-        else if constexpr (d == 1) return fl_s1 + wo;
-        else if constexpr (d == 2) return fl_s2 + wo;
-        else return fl_s3 + wo;
-    };
-    const int j_base = blockIdx.y * 64;
-    const int j = j_base + lane;
-
-    const double xd = gr.x0 + (double)min(j, gr.nx - 1) * gr.dx;
-    const double ox = xd - p.x_first;
-    const float dx0 = (float)ox, dx0_lo = (float)(ox - (double)dx0);
-    const float pitch_f = (float)p.pitch, pitch_lo = (float)(p.pitch - (double)pitch_f);
-    const double sa = p.sin_a[0], ca = p.cos_a[0];
-    int q[FL_RW];
-    float qfl[FL_RW];  // q as float (staged windows: exact there)
-    float fp[FL_RW];
-#pragma unroll
-    for (int k = 0; k < FL_RW; ++k) {
-        const double zd = gr.z0 + (double)min(i_base + k, gr.nz - 1) * gr.dz;
-        const double U = p.fs * ((xd * sa + zd * ca) / p.c + zd / p.c - p.t0);
-        const double Uf = floor(U);
-        q[k] = (int)Uf;
-        qfl[k] = (float)Uf;
-        fp[k] = (float)(U - Uf);
-    }
-    float acc[FL_RW][FB];
-#pragma unroll
-    for (int k = 0; k < FL_RW; ++k)
-#pragma unroll
-        for (int f = 0; f < FB; ++f) acc[k][f] = 0.0f;
-
-    // reference row of row i (rows past the image take the wave's first
-    // row's), clamped into the image; wave-uniform
-    auto ref_of = [&](int i) {
-        const int ii = i < gr.nz ? i : i_base;
-        const int r = ref ? ref[ii] : ii;
-        return __builtin_amdgcn_readfirstlane(min(max(r, 0), gr.nz - 1));
-    };
-    // the staged copy: one record over channel n of the group's frames (frames
-    // past the group's last lie past its end and read 0); lane L's offset
-    // within a 16-sample piece
-    const uint32_t frame_bytes = (uint32_t)(frame_rf * 4);
-    const uint32_t rec_bytes = (uint32_t)(((size_t)(nfr - 1) * frame_rf + p.T) * 4);
-    const int lane_off = (lane & 3) * (int)frame_bytes + (lane >> 2) * 4;
-    auto chan4 = [&](int n, bool live) {
-        return make_rsrc(rf0 + (size_t)(live ? n : 0) * p.T, live ? rec_bytes : 0u);
-    };
-    // one frame's channel n (the pair-by-pair path)
-    const uint32_t row_bytes = (uint32_t)p.T * 4u;
-    auto chan1 = [&](int f, int n) {
-        const bool fv = f < nfr;
-        return make_rsrc(rf0 + (fv ? f : 0) * frame_rf + (size_t)n * p.T, fv ? row_bytes : 0u);
-    };
-    // the wave's columns, relative to element 0 (uniform)
-    const int j_end = min(j_base + 63, gr.nx - 1);
-    const float xl0 = (float)(gr.x0 + (double)j_base * gr.dx - p.x_first);
-    const float xh0 = (float)(gr.x0 + (double)j_end * gr.dx - p.x_first);
-    auto U_at = [&](double x, int k) {
-        const double zd = gr.z0 + (double)min(i_base + k, gr.nz - 1) * gr.dz;
-        return p.fs * ((x * sa + zd * ca) / p.c + zd / p.c - p.t0);
-    };
-    const double x_lo = gr.x0 + (double)j_base * gr.dx, x_hi = gr.x0 + (double)j_end * gr.dx;
-
-#pragma unroll 1
-    for (int k0 = 0; k0 < FL_RW;) {
-        const int r = ref_of(i_base + k0);
-        int k1 = k0;
-        while (k1 + 1 < FL_RW && ref_of(i_base + k1 + 1) == r) ++k1;
-        const double zr = gr.z0 + (double)r * gr.dz;
-        const float zrf = (float)zr, z2 = (float)(zr * zr);
-        const bool on = (j < gr.nx) && (zr > 0.0);
-        const float inv_az = on ? (float)(2.0 * p.fnumber / zr) : 0.0f;
-        const double a_ap = zr / (2.0 * p.fnumber);
-        const float a_f = (float)a_ap;
-        int n_lo = 0, n_hi = -1;
-        if (zr > 0.0) {
-            n_lo = max(0, (int)floor((x_lo - a_ap - p.x_first) / p.pitch));
-            n_hi = min(p.C - 1, (int)ceil((x_hi + a_ap - p.x_first) / p.pitch));
-        }
-        // lowest read position of the run's first row and highest of its last
-        // row over the wave's columns, before the receive excess
-        const float U_first = (float)fmin(U_at(x_lo, k0), U_at(x_hi, k0));
-        const float U_last = (float)fmax(U_at(x_lo, k1), U_at(x_hi, k1));
-        // receive excess at lateral distance d (float; the window keeps a
-        // margin of two samples for the rounding)
-        auto excess = [&](float d) { return p.kappa * (d * d) / (__builtin_amdgcn_sqrtf(fmaf(d, d, z2)) + zrf); };
-
-        struct Win {
-            float w, e;
-            int lo, len;  // len 0: no lane in the aperture (or n past the run)
-            bool staged;  // the window lies in LDS; else read pair by pair
-        };
-        // element n's law (per lane), window (uniform) and its copy into slot
-        // S: every call issues FL_PIECES loads (dummy ones, which read
-        // nothing, for an element past the run, out of reach or not staged)
-        auto prep = [&](int n, auto S_) {
-            Win W{0.0f, 0.0f, 0, 0, false};
-            if (n <= n_hi) {
-                const float nf = (float)n;
-                const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
-                const float t = fabsf(dx) * inv_az;
-                const float wh = hann_weight(fminf(t, 1.0f));
-                W.w = (on && t <= 1.0f) ? wh : 0.0f;
-                const float rho = __builtin_amdgcn_sqrtf(fmaf(dx, dx, z2));
-                W.e = p.kappa * (dx * dx) * __builtin_amdgcn_rcpf(rho + zrf);
-                const float xn = nf * pitch_f;  // element n relative to element 0
-                const float dl = xl0 - xn, dh = xh0 - xn;
-                const float d_near = (dl <= 0.0f && dh >= 0.0f) ? 0.0f : fminf(fabsf(dl), fabsf(dh));
-                const float d_far = fminf(a_f, fmaxf(fabsf(dl), fabsf(dh)));
-                if (d_near <= a_f * 1.0001f + 1e-9f) {
-                    W.lo = __builtin_amdgcn_readfirstlane((int)floorf(U_first + excess(d_near)) - 2);
-                    const int hi = __builtin_amdgcn_readfirstlane((int)floorf(U_last + excess(d_far)) + 3);
-                    W.len = hi - W.lo + 1;
-                }
-            }
-            W.staged = W.len > 0 && W.len <= FL_LMAX && W.lo >= 0 && W.lo + W.len <= p.T;
-            float* dst = reinterpret_cast<float*>(slot(S_));
-            const auto rs = chan4(n, W.staged);
-            const int vb = lane_off + W.lo * 4;
-#pragma unroll
-            for (int c = 0; c < FL_PIECES; ++c)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(dst + 64 * c), 4,
-                                                         vb + 64 * c, 0, 0, 0);
-            return W;
-        };
-        // sum element n of the run from slot S (or pair by pair from the record)
-        auto sum = [&](int n, auto S_, const Win& W) {
-            if (W.len == 0) return;
-            const float w = W.w;
-            if (W.staged) {
-                // the slot seen from sample 0 of the record: sample u at ws[u]
-                const float4* ws = slot(S_) - W.lo;
-                const float u_lo = (float)W.lo, u_hi = (float)(W.lo + W.len - 2);
-                // the run's bounds, opaque here so that the row masks are made
-                // where they are used (scalar work) instead of held in registers
-                int r0 = k0, r1 = k1;
-                asm volatile("" : "+s"(r0), "+s"(r1));
-                fl_static_for<FL_RW / 4>([&](auto G_) {
-                    constexpr int g0 = 4 * decltype(G_)::value;
-                    if (g0 > r1 || g0 + 3 < r0) return;  // wave-uniform
-                    // the group's reads first, then its products
-                    float wa[4], wb[4];
-                    float4 s0[4], s1[4];
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const int k = g0 + kk;
-                        // the run's rows only (a uniform 1 or 0)
-                        const float mk = __int_as_float((unsigned)(k - r0) <= (unsigned)(r1 - r0) ? 0x3f800000 : 0);
-                        const float wk = w * mk;
-                        const float v = fp[k] + W.e;
-                        const float qf = floorf(v);
-                        const float fr = v - qf;
-                        // read position, clamped into the window (integers below 2^24: exact in float)
-                        TIDAS_DCHECK(wk == 0.0f || (qfl[k] + qf >= u_lo && qfl[k] + qf <= u_hi), TIDAS_DBG_FD_WINDOW);
-                        const int u = (int)__builtin_amdgcn_fmed3f(qfl[k] + qf, u_lo, u_hi);
-                        wa[kk] = wk * (1.0f - fr);
-                        wb[kk] = wk * fr;
-                        s0[kk] = ws[u];
-                        s1[kk] = ws[u + 1];
-                    }
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const int k = g0 + kk;
-                        acc[k][0] = fmaf(wb[kk], s1[kk].x, fmaf(wa[kk], s0[kk].x, acc[k][0]));
-                        acc[k][1] = fmaf(wb[kk], s1[kk].y, fmaf(wa[kk], s0[kk].y, acc[k][1]));
-                        acc[k][2] = fmaf(wb[kk], s1[kk].z, fmaf(wa[kk], s0[kk].z, acc[k][2]));
-                        acc[k][3] = fmaf(wb[kk], s1[kk].w, fmaf(wa[kk], s0[kk].w, acc[k][3]));
-                    }
-                });
-            } else {
-#pragma unroll
-                for (int k = 0; k < FL_RW; ++k) {
-                    if (k < k0 || k > k1) continue;  // wave-uniform
-                    const float v = fp[k] + W.e;
-                    const float qf = floorf(v);
-                    const float fr = v - qf;
-                    const int off = (q[k] + (int)qf) * 4;
-                    const float wa = w * (1.0f - fr), wbb = w * fr;
-#pragma unroll
-                    for (int f = 0; f < FB; ++f) {
-                        const auto rs = chan1(f, n);
-                        const float s0 = buffer_load_f32(rs, off);
-                        const float s1 = buffer_load_f32(rs, off + 4);
-                        acc[k][f] = fmaf(wbb, s1, fmaf(wa, s0, acc[k][f]));
-                    }
-                    // one row's loads in flight at a time: this path is the rare one
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        };
-        if (n_lo <= n_hi) {
-            Win ring[FL_DEPTH];
-            fl_static_for<FL_DEPTH - 1>([&](auto D_) {
-                constexpr int d = decltype(D_)::value;
-                ring[d] = prep(n_lo + d, D_);
-            });
-#pragma unroll 1
-            for (int n0 = n_lo; n0 <= n_hi; n0 += FL_DEPTH) {
-                fl_static_for<FL_DEPTH>([&](auto D_) {
-                    constexpr int d = decltype(D_)::value;
-                    constexpr int sl_next = (d + FL_DEPTH - 1) % FL_DEPTH;
-                    const int n = n0 + d;
-                    if (n <= n_hi) {
-                        // the reads of the slot about to be refilled (element n - 1) are done
-                        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-                        ring[sl_next] = prep(n + FL_DEPTH - 1, std::integral_constant<int, sl_next>{});
-                        // element n's copy has landed: only the FL_DEPTH - 1 later
-                        // elements' loads may still be outstanding
-                        constexpr int later = (FL_DEPTH - 1) * FL_PIECES;
-                        static_assert(later <= 63, "vmcnt range");
-                        __builtin_amdgcn_s_waitcnt((later & 15) | ((later >> 4) << 14) | 0x70 | 0xF00);
-                        sum(n, D_, ring[d]);
-                    }
-                });
-            }
-            // the loads issued for elements past the run read nothing: drain them
-            __builtin_amdgcn_s_waitcnt(0x070);
-        }
-        k0 = k1 + 1;
-    }
-    if (j < gr.nx) {
-#pragma unroll
-        for (int k = 0; k < FL_RW; ++k) {
-            const int i = i_base + k;
-            if (i < gr.nz) {
-                const float th = theta ? theta[i] : 1.0f;
-#pragma unroll
-                for (int f = 0; f < FB; ++f)
-                    if (f < nfr) img0[f * frame_img + (size_t)i * gr.nx + j] = th * acc[k][f];
-            }
-        }
-    }
+    fd_wave<FB, NA, FD_RB, IL>(p, gr, i_base, blockIdx.y * das_wx(NA), min(FB, p.n_frames - fr0), ref, theta,
+                               rf + fr0 * frame_rf, frame_rf, img + fr0 * frame_img, frame_img);
 }
 
 // ----------------------------------------------------------------- batches ----
@@ -836,6 +535,15 @@ static size_t das_il_bytes(int32_t A, int32_t C, int32_t T, int32_t n_frames) {
 }
 // the interleaved channel record (T FB floats) and its byte offsets fit 31 bits
 static bool das_il_fits(int32_t T) { return (int64_t)T * 4 * DAS_IL_FB + 64 < ((int64_t)1 << 31); }
+// two samples per thread: measured on 64 frames of 128 x 4096 samples, 39 us
+// (6.8 TB/s of the copy's read and write) against 42 us for one and 40 us for
+// four; a variant reading four samples per 16-byte load and transposing in
+// registers took 62 us (its 16-byte writes strided 64 bytes apart)
+static void launch_interleave(const float* rf, int32_t B, int64_t E, float* il, hipStream_t s) {
+    constexpr int S = 2;
+    const dim3 grid((unsigned)((E + 256 * S - 1) / (256 * S)), (unsigned)((B + DAS_IL_FB - 1) / DAS_IL_FB));
+    hipLaunchKernelGGL((das_interleave_kernel<DAS_IL_FB, S>), grid, dim3(256), 0, s, rf, B, E, il);
+}
 
 template <int FB, int NA, int FD_RB>
 static void launch_fixed_das(const DasArgs& p, const DasGrid& gr, const int32_t* ref, const float* theta,
@@ -918,13 +626,7 @@ extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, co
         if ((st = workspace_acquire("das_beamform", workspace, need, s, w))) return st;
         float* il = reinterpret_cast<float*>(w.ptr);
         const int64_t E = (int64_t)p.A * p.C * p.T;
-        const unsigned n_groups = (unsigned)((n_frames + DAS_IL_FB - 1) / DAS_IL_FB);
-        if (E % 4 == 0 && (reinterpret_cast<uintptr_t>(rf) & 15) == 0)
-            hipLaunchKernelGGL(das_interleave4_kernel<DAS_IL_FB>, dim3((unsigned)((E / 4 + 255) / 256), n_groups),
-                               dim3(256), 0, s, rf, n_frames, E, il);
-        else
-            hipLaunchKernelGGL(das_interleave_kernel<DAS_IL_FB>, dim3((unsigned)((E + 255) / 256), n_groups),
-                               dim3(256), 0, s, rf, n_frames, E, il);
+        launch_interleave(rf, n_frames, E, il, s);
         const dim3 grid((gr.nz + DAS_BZ * das_wz(1) - 1) / (DAS_BZ * das_wz(1)), (gr.nx + das_wx(1) - 1) / das_wx(1),
                         (n_frames + DAS_IL_FB - 1) / DAS_IL_FB);
         hipLaunchKernelGGL((das_kernel<DAS_IL_FB, 1, true>), grid, dim3(256), 0, s, p, gr, il, image);
@@ -946,9 +648,15 @@ extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, co
     return check_launch("das_beamform");
 }
 
+extern "C" size_t tidas_beamform_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_samples,
+                                                 int32_t n_frames) {
+    return das_beamform_workspace_bytes(n_angles, n_elem, n_samples, n_frames);
+}
+
 extern "C" int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
                                   const tidas_grid* grid, const float* rf, int32_t n_samples, int32_t n_frames,
-                                  const int32_t* ref_row, const float* theta, float* image, void* stream) {
+                                  const int32_t* ref_row, const float* theta, float* image, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
     DasArgs p;
     int32_t st = das_setup("tidas_beamform", array, tx, rx, n_samples, p);
     if (st) return st;
@@ -959,23 +667,38 @@ extern "C" int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, 
         (const void*)ref_row == (const void*)image)
         return fail(TIDAS_EINVAL, "tidas_beamform: image aliases an input");
     if (!das_grid_in_range(p, grid)) return fail(TIDAS_EUNSUPPORTED, "tidas_beamform: sample indices exceed 2^28");
+    const size_t need = das_il_fits(p.T) ? das_il_bytes(p.A, p.C, p.T, n_frames) : 0;
+    if ((st = workspace_check("tidas_beamform", workspace, workspace_bytes, need))) return st;
     p.n_frames = n_frames;
     const DasGrid gr = to_grid(grid);
     hipStream_t s = (hipStream_t)stream;
-    // rows per lane: the gathers bound this kernel as they bound DAS, so the
-    // shapes keep registers (and waves in flight) close to DAS's; measured on
-    // 64 frames of 1024 x 256, 128 elements, one law per 64 rows: 4 frames x
-    // 2 rows 0.64 ms, x 4 rows 0.78, x 8 rows 0.82 (166 registers)
-    const bool multi = n_frames >= 8;
-    if (p.A == 1) {
-        if (multi && fd_lds_fits(p.C, p.T)) {
-            // groups of four frames: the staged-window kernel
-            const dim3 grid((gr.nz + FL_WAVES * FL_RW - 1) / (FL_WAVES * FL_RW), (gr.nx + 63) / 64,
-                            (n_frames + FL_FB - 1) / FL_FB);
-            hipLaunchKernelGGL(fd_lds_kernel, grid, dim3(FL_WAVES * 64), 0, s, p, gr, ref_row, theta, rf, image);
-        } else {
-            launch_fixed_das<1, 1, 4>(p, gr, ref_row, theta, rf, image, s);
+    if (need) {
+        // groups of four frames read from the interleaved copy, as DAS; two
+        // rows per lane share the frozen law (measured on 64 frames of 1024 x
+        // 256, 128 elements: 0.39-0.45 ms with one law per 64 rows or per row,
+        // one row per lane the same)
+        Workspace w;
+        if ((st = workspace_acquire("tidas_beamform", workspace, need, s, w))) return st;
+        float* il = reinterpret_cast<float*>(w.ptr);
+        launch_interleave(rf, n_frames, (int64_t)p.A * p.C * p.T, il, s);
+        constexpr int RB = 2;
+        const int rows_per_wg = DAS_BZ * das_wz(1) * RB;
+        const dim3 grid((gr.nz + rows_per_wg - 1) / rows_per_wg, (gr.nx + das_wx(1) - 1) / das_wx(1),
+                        (n_frames + DAS_IL_FB - 1) / DAS_IL_FB);
+        hipLaunchKernelGGL((fixed_das_kernel<DAS_IL_FB, 1, RB, true>), grid, dim3(256), 0, s, p, gr, ref_row, theta,
+                           il, image);
+        if ((st = check_launch("tidas_beamform"))) {
+            workspace_release("tidas_beamform", w, s);
+            return st;
         }
+        return workspace_release("tidas_beamform", w, s);
+    }
+    // one frame per thread: rows per lane share the law when their references
+    // agree; measured on 64 frames of 1024 x 256, 128 elements, one law per
+    // 64 rows, before the interleaved copy: 4 frames x 2 rows 0.64 ms, x 4
+    // rows 0.78, x 8 rows 0.82 (166 registers)
+    if (p.A == 1) {
+        launch_fixed_das<1, 1, 4>(p, gr, ref_row, theta, rf, image, s);
     } else if (p.A == 11) {
         launch_fixed_das<1, 11, 4>(p, gr, ref_row, theta, rf, image, s);
     } else {

@@ -40,7 +40,7 @@ int main() {
     tidas_grid bad_grid{0, 32, 1e-3, 1e-4, -1e-3, 1e-4};
     expect("das bad grid", das_beamform(&arr, &tx, &rx, &bad_grid, F, 2048, 1, (float*)B, nullptr, 0, nullptr), E);
     expect("das aliasing", das_beamform(&arr, &tx, &rx, &grid, F, 2048, 1, F, nullptr, 0, nullptr), E);
-    expect("beamform null", tidas_beamform(&arr, &tx, &rx, &grid, nullptr, 2048, 1, nullptr, nullptr, F, nullptr), E);
+    expect("beamform null", tidas_beamform(&arr, &tx, &rx, &grid, nullptr, 2048, 1, nullptr, nullptr, F, nullptr, 0, nullptr), E);
 
     // line model and its forms
     expect("apply even K", tidas_apply(F, 64, (float*)A, 1, 16, 16, (float*)B, nullptr), E);

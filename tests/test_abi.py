@@ -144,17 +144,23 @@ def test_fixed_delay_beamform_rejects_invalid_arguments(lib):
     ok = (ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(g))
     img = ctypes.c_void_p(0x2000)
     f = lib.tidas_beamform
-    assert f(*ok, NUL, 2048, 1, NUL, NUL, img, NUL) == _lib.TIDAS_EINVAL           # null rf
-    assert f(*ok, FAKE, 2048, 1, NUL, NUL, NUL, NUL) == _lib.TIDAS_EINVAL          # null image
-    assert f(*ok, FAKE, 1, 1, NUL, NUL, img, NUL) == _lib.TIDAS_EINVAL             # n_samples < 2
-    assert f(*ok, FAKE, 2048, 0, NUL, NUL, img, NUL) == _lib.TIDAS_EINVAL          # no frames
-    assert f(*ok, FAKE, 2048, 1, NUL, NUL, FAKE, NUL) == _lib.TIDAS_EINVAL         # image aliases rf
-    assert f(*ok, FAKE, 2048, 1, img, NUL, img, NUL) == _lib.TIDAS_EINVAL          # image aliases ref_row
-    assert f(*ok, FAKE, 2048, 1, NUL, img, img, NUL) == _lib.TIDAS_EINVAL          # image aliases theta
+    assert f(*ok, NUL, 2048, 1, NUL, NUL, img, NUL, 0, NUL) == _lib.TIDAS_EINVAL           # null rf
+    assert f(*ok, FAKE, 2048, 1, NUL, NUL, NUL, NUL, 0, NUL) == _lib.TIDAS_EINVAL          # null image
+    assert f(*ok, FAKE, 1, 1, NUL, NUL, img, NUL, 0, NUL) == _lib.TIDAS_EINVAL             # n_samples < 2
+    assert f(*ok, FAKE, 2048, 0, NUL, NUL, img, NUL, 0, NUL) == _lib.TIDAS_EINVAL          # no frames
+    assert f(*ok, FAKE, 2048, 1, NUL, NUL, FAKE, NUL, 0, NUL) == _lib.TIDAS_EINVAL         # image aliases rf
+    assert f(*ok, FAKE, 2048, 1, img, NUL, img, NUL, 0, NUL) == _lib.TIDAS_EINVAL          # image aliases ref_row
+    assert f(*ok, FAKE, 2048, 1, NUL, img, img, NUL, 0, NUL) == _lib.TIDAS_EINVAL          # image aliases theta
     badrx = _lib.make_rx(0.0)
-    assert f(ok[0], ok[1], ctypes.byref(badrx), ok[3], FAKE, 2048, 1, NUL, NUL, img, NUL) == _lib.TIDAS_EINVAL
+    assert f(ok[0], ok[1], ctypes.byref(badrx), ok[3], FAKE, 2048, 1, NUL, NUL, img, NUL, 0, NUL) == _lib.TIDAS_EINVAL
     tx33 = _lib.make_tx([0.0] * 33, 40e6, 0, 5e6, 2)
-    assert f(ok[0], ctypes.byref(tx33), *ok[2:], FAKE, 2048, 1, NUL, NUL, img, NUL) == _lib.TIDAS_EUNSUPPORTED
+    assert f(ok[0], ctypes.byref(tx33), *ok[2:], FAKE, 2048, 1, NUL, NUL, img, NUL, 0, NUL) == _lib.TIDAS_EUNSUPPORTED
+    # the interleaved copy's workspace (one angle, eight frames or more): same rules as DAS
+    assert f(*ok, FAKE, 2048, 8, NUL, NUL, img, NUL, 64, NUL) == _lib.TIDAS_EINVAL
+    need = lib.tidas_beamform_workspace_bytes(1, 64, 2048, 8)
+    assert need == lib.das_beamform_workspace_bytes(1, 64, 2048, 8) > 0
+    assert f(*ok, FAKE, 2048, 8, NUL, NUL, img, ctypes.c_void_p(0x10040), need, NUL) == _lib.TIDAS_EINVAL
+    assert f(*ok, FAKE, 2048, 8, NUL, NUL, img, ctypes.c_void_p(0x10000), need - 256, NUL) == _lib.TIDAS_EINVAL
     assert lib.tidas_last_error()
 
 

@@ -152,3 +152,21 @@ def test_interleaved_own_scratch_same_bits(dev):
                                     _ptr(rd), s.n_samples, B, _ptr(got), _ptr(ws), ws.numel(), _stream()))
         torch.cuda.synchronize()
         assert torch.equal(got, want)
+
+
+def test_fixed_delay_interleaved_own_scratch_same_bits(dev):
+    """tidas_beamform reads eight or more frames through the same copy: the
+    caller's workspace and the library's own scratch give the same bits."""
+    s = config(1).with_grid(120, 64)
+    B = 10
+    rd = g(point_frames(s, B, 450), dev)
+    refs = torch.from_numpy(np.minimum((np.arange(s.nz) // 16) * 16 + 8, s.nz - 1).astype(np.int32)).to(dev)
+    theta = g(1.0 + 0.2 * generators.normal(s.nz, seed=3), dev)
+    want = td.tidas_beamform(rd, s, ref_row=refs, theta=theta)
+    lib = _lib.load()
+    got = torch.empty_like(want)
+    arr, tx, rx, gd = _descs(s, s)
+    _lib.check(lib.tidas_beamform(ctypes.byref(arr), ctypes.byref(tx), ctypes.byref(rx), ctypes.byref(gd), _ptr(rd),
+                                  s.n_samples, B, _ptr(refs), _ptr(theta), _ptr(got), NUL, 0, _stream()))
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)

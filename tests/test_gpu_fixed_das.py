@@ -138,9 +138,10 @@ def test_clinical_size_batch_sampled(dev):
         assert rel(got, want) <= RTOL
 
 
-def test_staged_window_kernel_own_rows_are_das_bits(dev):
-    """Eight or more frames of one plane wave take the staged-window kernel:
-    with every row its own reference (runs of one row) it gives DAS's bits."""
+def test_interleaved_own_rows_are_das_bits(dev):
+    """Eight or more frames of one plane wave read the RF through the
+    frame-interleaved copy, as DAS: with every row its own reference (a law
+    per row, the elements of the wave's widest aperture) it gives DAS's bits."""
     s = config(1).with_grid(200, 96)
     rf = np.stack([point_rf(s, 200 + b) for b in range(8)])
     rd = g(rf, dev)
@@ -148,7 +149,7 @@ def test_staged_window_kernel_own_rows_are_das_bits(dev):
 
 
 @pytest.mark.parametrize("size", [1, 16, 64, 1000, -1])
-def test_staged_window_kernel_matches_oracle(dev, size):
+def test_interleaved_matches_oracle(dev, size):
     """Neighbourhoods of 1 / 16 / 64 / all rows, and scattered references
     (size -1: a random map with references outside the image, clamped), on 9
     frames; theta applied."""
@@ -168,7 +169,7 @@ def test_staged_window_kernel_matches_oracle(dev, size):
         assert np.max(np.abs(img[b] - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
-def test_staged_window_kernel_edge_grids(dev):
+def test_interleaved_edge_grids(dev):
     base = config(1).replace(n_samples=1500)
     frames = []
     for b in range(8):
