@@ -387,7 +387,9 @@ def run_main(args):
     out["das"]["terms_per_frame"] = terms
     out["das_roofline"] = {"bound": "alu", "achieved": das_tflops, "peak": FP32_VALU_NOPACK_TFLOPS,
                            "unit": "TFLOP/s", "frac": das_tflops / FP32_VALU_NOPACK_TFLOPS,
-                           "kernel": "das_kernel<4,1>", "flops_per_term": DAS_FLOPS_PER_TERM}
+                           "kernel": "das_interleave_kernel<4,2> + das_kernel<4,1,true>",
+                           "flops_per_term": DAS_FLOPS_PER_TERM,
+                           "note": "the call: interleaved copy and gathers; the gathers' address path bounds it"}
 
     # ---- tiDAS-vs-DAS approximation error on frame 0 (snapped phantom, both on the GPU)
     x, z, a = phantoms[0]
