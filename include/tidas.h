@@ -145,9 +145,9 @@ int32_t tidas_debug_flags(uint32_t* flags, int32_t reset);
  * angles coherently compounded.  rf is DEV [n_frames][A][C][n_samples],
  * image DEV [n_frames][nz][nx] (overwritten).  n_frames >= 1,
  * n_samples >= 2.  All frames share one geometry.  workspace DEV (device
- * scratch convention above): with one angle and eight or more frames the
- * call reads the RF through a frame-interleaved copy, four frames per
- * 16-byte load ([ceil(n_frames / 4)][A][C][n_samples][4] floats);
+ * scratch convention above): with eight or more frames of one angle or of
+ * eleven the call reads the RF through a frame-interleaved copy, four frames
+ * per 16-byte load ([ceil(n_frames / 4)][A][C][n_samples][4] floats);
  * das_beamform_workspace_bytes gives its size (0: no scratch needed).
  */
 int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,

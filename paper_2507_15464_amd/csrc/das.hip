@@ -131,7 +131,10 @@ __device__ __forceinline__ void das_wave(const DasArgs& p, const DasGrid& gr, in
 
     const uint32_t row_bytes = (uint32_t)p.T * 4u;
     const int last_pair = (p.T - 2) * 4;  // byte offset of the last sample pair
-#pragma unroll 2
+    // two elements' loads in flight together, except for the interleaved
+    // compounding, whose angles already hold 22 16-byte loads per element
+    constexpr int UNR = (IL && NA > 1) ? 1 : 2;
+#pragma unroll UNR
     for (int n = n_lo; n <= n_hi; ++n) {
         const float nf = (float)n;
         const float dx = fmaf(-nf, pitch_f, dx0) + fmaf(-nf, pitch_lo, dx0_lo);
@@ -518,23 +521,28 @@ __global__ __launch_bounds__(WAVES * 64) void das_batch_kernel(const DasArgs p, 
     }
 }
 
-template <int FB, int NA>
+template <int FB, int NA, bool IL = false>
 static void launch_das(const DasArgs& p, const DasGrid& gr, const float* rf, float* img, hipStream_t s) {
     dim3 grid((gr.nz + DAS_BZ * das_wz(NA) - 1) / (DAS_BZ * das_wz(NA)), (gr.nx + das_wx(NA) - 1) / das_wx(NA),
               (p.n_frames + FB - 1) / FB);
-    hipLaunchKernelGGL((das_kernel<FB, NA>), grid, dim3(256), 0, s, p, gr, rf, img);
+    hipLaunchKernelGGL((das_kernel<FB, NA, IL>), grid, dim3(256), 0, s, p, gr, rf, img);
 }
 
 // Frames per interleaved group and the copy's bytes (0: the call reads the
 // RF in place: one frame per thread, or several angles).
 constexpr int DAS_IL_FB = 4;
 static size_t das_il_bytes(int32_t A, int32_t C, int32_t T, int32_t n_frames) {
-    if (A != 1 || n_frames < 8) return 0;
     const int64_t groups = (n_frames + DAS_IL_FB - 1) / DAS_IL_FB;
     return ((size_t)groups * DAS_IL_FB * A * C * T * sizeof(float) + 255) / 256 * 256;
 }
 // the interleaved channel record (T FB floats) and its byte offsets fit 31 bits
 static bool das_il_fits(int32_t T) { return (int64_t)T * 4 * DAS_IL_FB + 64 < ((int64_t)1 << 31); }
+// which calls read the RF through the copy: eight or more frames of one plane
+// wave, or (DAS) of the 11-angle compounding the batch kernels serve
+static bool das_uses_il(int32_t A, int32_t T, int32_t n_frames) {
+    return (A == 1 || A == 11) && n_frames >= 8 && das_il_fits(T);
+}
+static bool fd_uses_il(int32_t A, int32_t T, int32_t n_frames) { return A == 1 && n_frames >= 8 && das_il_fits(T); }
 // two samples per thread: measured on 64 frames of 128 x 4096 samples, 39 us
 // (6.8 TB/s of the copy's read and write) against 42 us for one and 40 us for
 // four; a variant reading four samples per 16-byte load and transposing in
@@ -598,7 +606,8 @@ using namespace tidas;
 
 extern "C" size_t das_beamform_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_samples,
                                                int32_t n_frames) {
-    if (n_angles < 1 || n_elem < 1 || n_samples < 2 || n_frames < 1 || !das_il_fits(n_samples)) return 0;
+    if (n_angles < 1 || n_elem < 1 || n_samples < 2 || n_frames < 1 || !das_uses_il(n_angles, n_samples, n_frames))
+        return 0;
     return das_il_bytes(n_angles, n_elem, n_samples, n_frames);
 }
 
@@ -614,7 +623,7 @@ extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, co
     if (n_frames < 1) return fail(TIDAS_EINVAL, "das_beamform: n_frames must be >= 1");
     if ((const void*)rf == (const void*)image) return fail(TIDAS_EINVAL, "das_beamform: image aliases rf");
     if (!das_grid_in_range(p, grid)) return fail(TIDAS_EUNSUPPORTED, "das_beamform: sample indices exceed 2^28");
-    const size_t need = das_il_fits(p.T) ? das_il_bytes(p.A, p.C, p.T, n_frames) : 0;
+    const size_t need = das_uses_il(p.A, p.T, n_frames) ? das_il_bytes(p.A, p.C, p.T, n_frames) : 0;
     if ((st = workspace_check("das_beamform", workspace, workspace_bytes, need))) return st;
     p.n_frames = n_frames;
     const DasGrid gr = to_grid(grid);
@@ -627,9 +636,8 @@ extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, co
         float* il = reinterpret_cast<float*>(w.ptr);
         const int64_t E = (int64_t)p.A * p.C * p.T;
         launch_interleave(rf, n_frames, E, il, s);
-        const dim3 grid((gr.nz + DAS_BZ * das_wz(1) - 1) / (DAS_BZ * das_wz(1)), (gr.nx + das_wx(1) - 1) / das_wx(1),
-                        (n_frames + DAS_IL_FB - 1) / DAS_IL_FB);
-        hipLaunchKernelGGL((das_kernel<DAS_IL_FB, 1, true>), grid, dim3(256), 0, s, p, gr, il, image);
+        if (p.A == 1) launch_das<DAS_IL_FB, 1, true>(p, gr, il, image, s);
+        else launch_das<DAS_IL_FB, 11, true>(p, gr, il, image, s);
         if ((st = check_launch("das_beamform"))) {
             workspace_release("das_beamform", w, s);
             return st;
@@ -650,7 +658,9 @@ extern "C" int32_t das_beamform(const tidas_array* array, const tidas_tx* tx, co
 
 extern "C" size_t tidas_beamform_workspace_bytes(int32_t n_angles, int32_t n_elem, int32_t n_samples,
                                                  int32_t n_frames) {
-    return das_beamform_workspace_bytes(n_angles, n_elem, n_samples, n_frames);
+    if (n_angles < 1 || n_elem < 1 || n_samples < 2 || n_frames < 1 || !fd_uses_il(n_angles, n_samples, n_frames))
+        return 0;
+    return das_il_bytes(n_angles, n_elem, n_samples, n_frames);
 }
 
 extern "C" int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, const tidas_rx* rx,
@@ -667,7 +677,7 @@ extern "C" int32_t tidas_beamform(const tidas_array* array, const tidas_tx* tx, 
         (const void*)ref_row == (const void*)image)
         return fail(TIDAS_EINVAL, "tidas_beamform: image aliases an input");
     if (!das_grid_in_range(p, grid)) return fail(TIDAS_EUNSUPPORTED, "tidas_beamform: sample indices exceed 2^28");
-    const size_t need = das_il_fits(p.T) ? das_il_bytes(p.A, p.C, p.T, n_frames) : 0;
+    const size_t need = fd_uses_il(p.A, p.T, n_frames) ? das_il_bytes(p.A, p.C, p.T, n_frames) : 0;
     if ((st = workspace_check("tidas_beamform", workspace, workspace_bytes, need))) return st;
     p.n_frames = n_frames;
     const DasGrid gr = to_grid(grid);

@@ -129,12 +129,16 @@ def test_das_rejects_invalid_arguments(lib):
 
 def test_das_workspace_query(lib):
     """Interleaved groups of four frames, 256-byte rounded; none below eight
-    frames, with several angles or for invalid sizes."""
+    frames, for angle counts other than 1 and 11 (the fixed-delay beamformer:
+    other than 1) or for invalid sizes."""
     assert lib.das_beamform_workspace_bytes(1, 64, 2048, 8) == 2 * 4 * 64 * 2048 * 4
     assert lib.das_beamform_workspace_bytes(1, 128, 4096, 64) == 64 * 128 * 4096 * 4
     assert lib.das_beamform_workspace_bytes(1, 3, 5, 9) == (3 * 4 * 3 * 5 * 4 + 255) // 256 * 256
     assert lib.das_beamform_workspace_bytes(1, 64, 2048, 7) == 0
-    assert lib.das_beamform_workspace_bytes(11, 64, 2048, 64) == 0
+    assert lib.das_beamform_workspace_bytes(11, 64, 2048, 8) == 2 * 4 * 11 * 64 * 2048 * 4  # the compounding
+    assert lib.das_beamform_workspace_bytes(3, 64, 2048, 64) == 0
+    assert lib.tidas_beamform_workspace_bytes(11, 64, 2048, 64) == 0
+    assert lib.tidas_beamform_workspace_bytes(1, 64, 2048, 8) == 2 * 4 * 64 * 2048 * 4
     assert lib.das_beamform_workspace_bytes(1, 0, 2048, 64) == 0
     assert lib.das_beamform_workspace_bytes(1, 64, 1, 64) == 0
 

@@ -63,6 +63,20 @@ def test_interleaved_frames_match_oracle(dev, B):
         assert rel(img[b], ref) <= RTOL, b
 
 
+def test_interleaved_compounding_matches_oracle(dev):
+    """Eleven compounded angles, nine frames (groups of 4, 4, 1)."""
+    s = config(3).with_grid(160, 96)
+    B = 9
+    rf = point_frames(s, B, 600)
+    assert rf.shape[1] == 11
+    img = td.das_beamform(g(rf, dev), s).cpu().numpy()
+    xs, zs = axes(s)
+    for b in range(B):
+        ref = o_das.das(rf[b], xs, zs, **das_kw(s))
+        assert np.max(np.abs(img[b] - ref)) <= 1e-5 * np.max(np.abs(ref)), b
+        assert rel(img[b], ref) <= RTOL, b
+
+
 def test_interleaved_odd_record_and_unaligned_rf(dev):
     """A record of A C T samples not a multiple of four, and RF starting 4
     bytes past a 16-byte boundary: the copy takes its one-sample-per-thread
