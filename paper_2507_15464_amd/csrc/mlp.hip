@@ -61,7 +61,13 @@ struct GemmArgs {
     int64_t ldz;
 };
 
-constexpr int GM = 64, GN = 64, GK = 32, GPAD = 8;
+#ifndef MLP_TILE
+#define MLP_TILE 32
+#endif
+// output tiles of GM x GN per workgroup (four waves, each GM / 2 x GN / 2 in
+// 16 x 16 blocks)
+constexpr int GM = MLP_TILE, GN = MLP_TILE, GK = 32, GPAD = 8;
+constexpr int GW = GM / 2, GSUB = GW / 16;
 constexpr int GKB = 128;  // k staged in LDS at once
 static_assert(GM == GN, "operand staging assumes square tiles");
 
@@ -72,17 +78,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x * GM, n0 = blockIdx.y * GN;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int wr = (wave >> 1) * GW, wc = (wave & 1) * GW;
     const int li = lane & 15, lq = lane >> 4;
     // split-K: slice blockIdx.z of gridDim.z covers [kbeg, kend), a whole number of GK chunks
     const int kper = ((g.K + (int)gridDim.z - 1) / (int)gridDim.z + GK - 1) / GK * GK;
     const int kbeg = blockIdx.z * kper;
     const int kend = min(g.K, kbeg + kper);
-    floatx4 acc[2][2];
+    floatx4 acc[GSUB][GSUB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < GSUB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < GSUB; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     // The slice's k moves through LDS in blocks of GKB = 128: every load of a block
     // is issued before the first is awaited (one memory latency per block, not
@@ -136,17 +142,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
         __syncthreads();
         const int nch = (kn + GK - 1) / GK;
         for (int c = 0; c < nch; ++c) {
-            bf16x8 af[2], bfr[2];
+            bf16x8 af[GSUB], bfr[GSUB];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < GSUB; ++a)
                 af[a] = *reinterpret_cast<const bf16x8*>(&As[wr + 16 * a + li][GK * c + 8 * lq]);
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < GSUB; ++b)
                 bfr[b] = *reinterpret_cast<const bf16x8*>(&Bs[wc + 16 * b + li][GK * c + 8 * lq]);
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < GSUB; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < GSUB; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
         }
     }
@@ -154,9 +160,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
     // split-K partials go to slice blockIdx.z of c32 (reduced afterwards)
     float* c32 = g.c32 + (int64_t)blockIdx.z * g.M * g.ldc;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < GSUB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < GSUB; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wr + 16 * a + 4 * lq + r;
@@ -179,16 +185,6 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmArgs g) {
                     g.c16[(int64_t)m * g.ldc16 + n] = to_bf16(d);
                 }
             }
-}
-
-// out[m][n] = sum_s part[s][m][n] in slice order (deterministic split-K reduction)
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int32_t S, int64_t mn,
-                                                            float* __restrict__ out) {
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mn; e += (int64_t)gridDim.x * 256) {
-        float s = 0.0f;
-        for (int i = 0; i < S; ++i) s += part[(int64_t)i * mn + e];
-        out[e] = s;
-    }
 }
 
 static void gemm(int epi, const GemmArgs& g, hipStream_t s, int splits = 1) {
@@ -252,21 +248,37 @@ __global__ __launch_bounds__(256) void loss_finish_kernel(const double* __restri
 
 // db[o] = sum_b g[b][o]: 64 columns per workgroup, 16 row lanes each summing a
 // strided subset, then the 16 partial sums added in lane order (deterministic)
-__global__ __launch_bounds__(1024) void colsum_kernel(const float* __restrict__ g, int32_t N, int32_t O,
-                                                      float* __restrict__ db) {
-    __shared__ float part[16][65];
-    const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
-    const int o = blockIdx.x * 64 + c;
-    float s = 0.0f;
+// The end of a layer's weight gradient, one launch: blocks [0, nr) add the
+// split-K slices (out[e] = sum_s part[s][e], slices in order; nr = 0 without
+// split-K) and blocks [nr, nr + ceil(O / 8)) the bias gradient's column sums
+// db[o] = sum_b g[b][o], 8 columns per block: thread (r, c) sums rows r, r +
+// 32, ... of column c, then one thread per column adds the 32 partials in
+// order (fixed order throughout: bit-reproducible).
+__global__ __launch_bounds__(256) void wgrad_finish_kernel(const float* __restrict__ part, int32_t S, int64_t mn,
+                                                           float* __restrict__ out, int32_t nr,
+                                                           const float* __restrict__ g, int32_t N, int32_t O,
+                                                           float* __restrict__ db) {
+    __shared__ float cs[32][9];
+    if ((int)blockIdx.x < nr) {
+        for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mn; e += (int64_t)nr * 256) {
+            float sum = 0.0f;
+            for (int i = 0; i < S; ++i) sum += part[(int64_t)i * mn + e];
+            out[e] = sum;
+        }
+        return;
+    }
+    const int c = threadIdx.x & 7, r = threadIdx.x >> 3;
+    const int o = ((int)blockIdx.x - nr) * 8 + c;
+    float sum = 0.0f;
     if (o < O) {
 #pragma unroll 8
-        for (int b = rl; b < N; b += 16) s += g[(int64_t)b * O + o];
+        for (int b = r; b < N; b += 32) sum += g[(int64_t)b * O + o];
     }
-    part[rl][c] = s;
+    cs[r][c] = sum;
     __syncthreads();
-    if (rl == 0 && o < O) {
+    if (threadIdx.x < 8 && o < O) {
         float t = 0.0f;
-        for (int i = 0; i < 16; ++i) t += part[i][c];
+        for (int i = 0; i < 32; ++i) t += cs[i][c];
         db[o] = t;
     }
 }
@@ -519,17 +531,18 @@ extern "C" int32_t tidas_mlp_train_step(const int32_t* widths, const uint16_t* p
         gw.K = N;
         gw.ldc = in;
         const int S = wgrad_splits(N);
+        const int64_t mn = (int64_t)out * in;
+        int nr = 0;
         if (S > 1) {
             gw.c32 = w.splitk;
             gemm(EPI_STORE, gw, s, S);
-            const int64_t mn = (int64_t)out * in;
-            hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)std::min<int64_t>((mn + 255) / 256, 1024)), dim3(256),
-                               0, s, w.splitk, S, mn, grad + L.off_w[l]);
+            nr = (int)std::min<int64_t>((mn + 255) / 256, 1024);
         } else {
             gw.c32 = grad + L.off_w[l];
             gemm(EPI_STORE, gw, s);
         }
-        hipLaunchKernelGGL(colsum_kernel, dim3((out + 63) / 64), dim3(1024), 0, s, w.g32[l], N, out, grad + L.off_b[l]);
+        hipLaunchKernelGGL(wgrad_finish_kernel, dim3((unsigned)(nr + (out + 7) / 8)), dim3(256), 0, s, w.splitk, S, mn,
+                           grad + L.off_w[l], nr, w.g32[l], N, out, grad + L.off_b[l]);
         if (l > 0) {
             // g_{l-1}[b][i] = (sum_o g_l[b][o] W_l[o][i]) * GELU'(z_{l-1}[b][i])
             GemmArgs gd{};
