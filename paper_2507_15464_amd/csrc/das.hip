@@ -539,10 +539,13 @@ static size_t das_il_bytes(int32_t A, int32_t C, int32_t T, int32_t n_frames) {
 static bool das_il_fits(int32_t T) { return (int64_t)T * 4 * DAS_IL_FB + 64 < ((int64_t)1 << 31); }
 // which calls read the RF through the copy: eight or more frames of one plane
 // wave, or (DAS) of the 11-angle compounding the batch kernels serve
+// (the groups are the launches' third grid dimension: at most 65535)
 static bool das_uses_il(int32_t A, int32_t T, int32_t n_frames) {
-    return (A == 1 || A == 11) && n_frames >= 8 && das_il_fits(T);
+    return (A == 1 || A == 11) && n_frames >= 8 && n_frames <= 4 * 65535 && das_il_fits(T);
 }
-static bool fd_uses_il(int32_t A, int32_t T, int32_t n_frames) { return A == 1 && n_frames >= 8 && das_il_fits(T); }
+static bool fd_uses_il(int32_t A, int32_t T, int32_t n_frames) {
+    return A == 1 && n_frames >= 8 && n_frames <= 4 * 65535 && das_il_fits(T);
+}
 // two samples per thread: measured on 64 frames of 128 x 4096 samples, 39 us
 // (6.8 TB/s of the copy's read and write) against 42 us for one and 40 us for
 // four; a variant reading four samples per 16-byte load and transposing in
