@@ -12,11 +12,13 @@
 // One GEMM kernel serves every product: C[m][n] = sum_k A(m, k) B(k, n) with
 // A(m, k) = A[m sam + k sak] and B(k, n) = B[k sbk + n sbn] (bfloat16), so the
 // forward (H W^T), data-gradient (G W) and weight-gradient (G^T H) products
-// differ only in strides.  Tiles of 64 x 64 outputs, 4 waves, each wave a
-// 32 x 32 block as 2 x 2 MFMA 16x16x32 accumulators; the k dimension is
-// staged in LDS in blocks of 256 with operands stored k-contiguous, and
-// multiplied in chunks of 32, so each lane's 8 bfloat16 operand values are
-// one 16-byte LDS read.
+// differ only in strides.  Tiles of 32 x 32 outputs, 4 waves, each wave a
+// 16 x 16 block (one MFMA 16x16x32 accumulator): the 1024 x 256 products of
+// a training step then take 256 workgroups, one per compute unit, where 64 x
+// 64 tiles took 64 and left the launches to four times the latency.  The k
+// dimension is staged in LDS in blocks of 128 with operands stored
+// k-contiguous, and multiplied in chunks of 32, so each lane's 8 bfloat16
+// operand values are one 16-byte LDS read.
 //   A operand (16 x 32): lane l holds A[l % 16][8 (l / 16) .. +7]
 //   B operand (32 x 16): lane l holds B[8 (l / 16) .. +7][l % 16]
 //   D (16 x 16): register r of lane l holds D[4 (l / 16) + r][l % 16]
@@ -61,12 +63,9 @@ struct GemmArgs {
     int64_t ldz;
 };
 
-#ifndef MLP_TILE
-#define MLP_TILE 32
-#endif
 // output tiles of GM x GN per workgroup (four waves, each GM / 2 x GN / 2 in
 // 16 x 16 blocks)
-constexpr int GM = MLP_TILE, GN = MLP_TILE, GK = 32, GPAD = 8;
+constexpr int GM = 32, GN = 32, GK = 32, GPAD = 8;
 constexpr int GW = GM / 2, GSUB = GW / 16;
 constexpr int GKB = 128;  // k staged in LDS at once
 static_assert(GM == GN, "operand staging assumes square tiles");
