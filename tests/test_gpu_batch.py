@@ -111,8 +111,10 @@ def test_full_size_ragged_line_model_four_block_variant(dev):
     prepared in the workspace, one workgroup per 128-row tile walking the
     frame's column tiles) on frames at the batching workload's extreme sizes
     and ragged ones: the same bits as the persistent two-block variant and as
-    single launches; sampled rows against the oracle."""
-    shapes = [(2048, 512), (512, 256), (1500, 333), (129, 300), (640, 257)]
+    single launches; sampled rows against the oracle.  Widths run past a
+    multiple of 256 by 1, 32, 44, 77 and 88 columns, one of them into a third
+    column tile."""
+    shapes = [(2048, 512), (512, 256), (1500, 333), (129, 300), (640, 257), (150, 288), (200, 600)]
     K = 65
     kbs = [generators.normal((Z, K), seed=30 + i).astype(np.float32) for i, (Z, X) in enumerate(shapes)]
     Rs = [generators.normal((Z, X), seed=40 + i).astype(np.float32) for i, (Z, X) in enumerate(shapes)]
