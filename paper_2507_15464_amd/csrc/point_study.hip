@@ -41,7 +41,8 @@ namespace {
 
 constexpr int ST_THREADS = 256;
 constexpr int ST_RB = 4;          // delay curves per pair workgroup
-constexpr int ST_MAX_ELEM = 512;  // pair-kernel LDS: ST_RB x C x 20 + C x 8 bytes (45 KB at 512)
+constexpr int ST_UNR = 4;         // listed channels whose reads the pair kernel issues together
+constexpr int ST_MAX_ELEM = 512;  // pair-kernel LDS: ST_RB x C x 20 + C x 8 bytes (45 KB at 512) + 8 KB of lists
 
 struct StudyGeom {
     int32_t C, T, P, n_tx, Ql, Qh, Qf, focal;
@@ -99,19 +100,6 @@ __device__ double st_fixed(const StudyGeom& g, const double* rf_s, double z, dou
         acc += w * st_read(rf_s + (size_t)n * g.T, g.T, u);
     }
     return acc;
-}
-
-// Fixed-order sum over the workgroup of ST_THREADS threads; every thread gets it.
-__device__ double st_block_sum(double v, double* red) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double tot = 0.0;
-    for (int w = 0; w < ST_THREADS / 64; ++w) tot += red[w];
-    __syncthreads();
-    return tot;
 }
 
 // grid (ceil(T / 256), C, P).  The transmit arrival of every element at z_s
@@ -193,6 +181,13 @@ __global__ __launch_bounds__(ST_THREADS) void study_window_kernel(const StudyGeo
 // position of channel n for curve r is u = u0[r][n] + q, so its integer part
 // kq + q and fraction f are fixed per (r, n) and staged in LDS with the
 // weights; reads outside the echo's support are skipped (they are zeros).
+// The samples are taken 256 at a time: for each such chunk the workgroup
+// first lists, in order of r then n, the (r, n) with a non-zero weight whose
+// support meets the chunk's read positions (an interval of q per (r, n)), so
+// a thread visits only those (an echo's support spans a few hundred samples
+// of a line of thousands, so most (r, n) reach no sample of a chunk); each
+// curve's channels are still summed in increasing n, as in a plain loop over
+// the aperture, so the bits do not depend on the lists.
 // The line's sums go through a fixed-order workgroup reduction, then thread
 // 0 forms Theta and both errors from them:
 //   ||t a - b||^2 = t^2 sum a^2 - 2 t sum a b + sum b^2  (clamped at 0).
@@ -208,8 +203,12 @@ __global__ __launch_bounds__(ST_THREADS) void study_pair_kernel(const StudyGeom 
     double* f_rn = w_rn + ST_RB * g.C;                     // [ST_RB][C]
     int* k_rn = (int*)(f_rn + ST_RB * g.C);                // [ST_RB][C]
     int2* sp = (int2*)(k_rn + ST_RB * g.C);                // [C]
-    __shared__ double red[ST_THREADS / 64];
+    __shared__ double red[ST_THREADS / 64][2 + 4 * ST_RB];
+    __shared__ double tot[2 + 4 * ST_RB];
     __shared__ int n_range[2];
+    __shared__ int lst[ST_RB * ST_MAX_ELEM];
+    __shared__ int seg[ST_RB + 1];
+    __shared__ int wcnt[ST_THREADS / 64];
     const int s = blockIdx.y;
     const int r0 = blockIdx.x * ST_RB;
     const double zs = st_point(g, s);
@@ -255,66 +254,153 @@ __global__ __launch_bounds__(ST_THREADS) void study_pair_kernel(const StudyGeom 
 #pragma unroll
     for (int j = 0; j < ST_RB; ++j) ab[j] = aa[j] = abB[j] = aaB[j] = 0.0;
     const int L = 2 * g.Ql + 1;
-    for (int i = threadIdx.x; i < L; i += ST_THREADS) {
-        const int q = i - g.Ql;
-        double a[ST_RB];
+    // entries (j, n), j-major over the channels n_lo .. n_hi (none if no
+    // channel has a weight)
+    const int Cr = n_hi - n_lo + 1;
+    const int E = Cr > 0 ? ST_RB * Cr : 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = -g.Ql; c0 <= g.Ql; c0 += ST_THREADS) {
+        const int c1 = c0 + ST_THREADS - 1;
+        // the chunk's list: lst[seg[j] .. seg[j + 1]) holds, in increasing n,
+        // the channels of curve j whose read positions k_rn + q, q in
+        // [c0, c1], meet the support [su.x - 1, su.y] (an ordered compaction:
+        // per round of 256 entries a ballot per wave and the waves' counts)
+        if (threadIdx.x <= ST_RB) seg[threadIdx.x] = 0;
+        int base = 0;
+        for (int t0 = 0; t0 < E; t0 += ST_THREADS) {
+            const int idx = t0 + threadIdx.x;
+            bool keep = false;
+            int j = 0, n = 0;
+            if (idx < E) {
+                j = idx / Cr;
+                n = n_lo + idx - j * Cr;
+                const int e = j * g.C + n;
+                const int2 su = sp[n];
+                keep = w_rn[e] != 0.0 && su.x - 1 - k_rn[e] <= c1 && su.y - k_rn[e] >= c0;
+            }
+            const uint64_t m = __ballot(keep);
+            if (lane == 0) wcnt[wave] = __popcll(m);
+            __syncthreads();
+            int pos = base, tot = 0;
 #pragma unroll
-        for (int j = 0; j < ST_RB; ++j) a[j] = 0.0;
-        for (int n = n_lo; n <= n_hi; ++n) {
-            const int2 su = sp[n];
-            const double* row = rf_s + (size_t)n * g.T;
+            for (int w = 0; w < ST_THREADS / 64; ++w) {
+                pos += w < wave ? wcnt[w] : 0;
+                tot += wcnt[w];
+            }
+            pos += __popcll(m & ((1ull << lane) - 1ull));
+            if (idx < E && n == n_lo) seg[j] = pos;  // entries listed before curve j's first
+            if (keep) lst[pos] = n;
+            base += tot;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) seg[ST_RB] = base;
+        __syncthreads();
+
+        const int q = c0 + threadIdx.x;
+        if (q <= g.Ql) {
+            double a[ST_RB];
 #pragma unroll
             for (int j = 0; j < ST_RB; ++j) {
-                const int e = j * g.C + n;
-                const int k = k_rn[e] + q;
+                a[j] = 0.0;
+                const int t_end = seg[j + 1];
+                // ST_UNR listed channels at a time: their reads (at positions
+                // clamped into the record, so every one is in bounds) are
+                // issued together, then added in list order where the sample
+                // lies in the support
+                for (int t = seg[j]; t < t_end; t += ST_UNR) {
+                    bool in[ST_UNR];
+                    double s0[ST_UNR], s1[ST_UNR], fw[ST_UNR], wv[ST_UNR];
+#pragma unroll
+                    for (int u = 0; u < ST_UNR; ++u) {
+                        const int n = lst[min(t + u, t_end - 1)];
+                        const int e = j * g.C + n;
+                        const int2 su = sp[n];
+                        const int k = k_rn[e] + q;
+                        in[u] = t + u < t_end && k >= su.x - 1 && k <= su.y;
+                        const double* row = rf_s + (size_t)n * g.T;
+                        const double r0 = row[min(max(k, 0), g.T - 1)];
+                        const double r1 = row[min(max(k + 1, 0), g.T - 1)];
+                        s0[u] = k >= su.x ? r0 : 0.0;
+                        s1[u] = k + 1 <= su.y ? r1 : 0.0;
+                        fw[u] = f_rn[e];
+                        wv[u] = w_rn[e];
+                    }
+#pragma unroll
+                    for (int u = 0; u < ST_UNR; ++u)
+                        if (in[u]) a[j] += wv[u] * ((1.0 - fw[u]) * s0[u] + fw[u] * s1[u]);
+                }
+            }
 #ifdef TIDAS_DEBUG
-                // the support table: samples it leaves out are zero
-                if (k >= 0 && k < g.T && (k < su.x || k > su.y))
-                    TIDAS_DCHECK(w_rn[e] == 0.0 || row[k] == 0.0, TIDAS_DBG_STUDY_SPAN);
+            // the support table: samples it leaves out are zero
+            for (int n = n_lo; n <= n_hi; ++n) {
+                const int2 su = sp[n];
+                const double* row = rf_s + (size_t)n * g.T;
+                for (int j = 0; j < ST_RB; ++j) {
+                    const int e = j * g.C + n;
+                    const int k = k_rn[e] + q;
+                    if (k >= 0 && k < g.T && (k < su.x || k > su.y))
+                        TIDAS_DCHECK(w_rn[e] == 0.0 || row[k] == 0.0, TIDAS_DBG_STUDY_SPAN);
+                }
+            }
 #endif
-                if (k >= su.x - 1 && k <= su.y) {
-                    const double f = f_rn[e];
-                    const double s0 = k >= su.x ? row[k] : 0.0;
-                    const double s1 = k + 1 <= su.y ? row[k + 1] : 0.0;
-                    a[j] += w_rn[e] * ((1.0 - f) * s0 + f * s1);
+            const double b = bline[(size_t)s * L + (q + g.Ql)];
+            const bool inB = q >= -Qw && q <= Qw;
+            bb += b * b;
+            if (inB) bbB += b * b;
+#pragma unroll
+            for (int j = 0; j < ST_RB; ++j) {
+                ab[j] += a[j] * b;
+                aa[j] += a[j] * a[j];
+                if (inB) {
+                    abB[j] += a[j] * b;
+                    aaB[j] += a[j] * a[j];
                 }
             }
         }
-        const double b = bline[(size_t)s * L + i];
-        const bool inB = q >= -Qw && q <= Qw;
-        bb += b * b;
-        if (inB) bbB += b * b;
-#pragma unroll
-        for (int j = 0; j < ST_RB; ++j) {
-            ab[j] += a[j] * b;
-            aa[j] += a[j] * a[j];
-            if (inB) {
-                abB[j] += a[j] * b;
-                aaB[j] += a[j] * a[j];
-            }
-        }
+        __syncthreads();  // the next chunk rewrites the list
     }
-    bb = st_block_sum(bb, red);
-    bbB = st_block_sum(bbB, red);
+    // the 2 + 4 ST_RB sums over the workgroup, each in a fixed order: a
+    // shuffle tree within each wave, then the waves' partial sums in order
+    constexpr int NS = 2 + 4 * ST_RB;
+    double v[NS];
+    v[0] = bb;
+    v[1] = bbB;
 #pragma unroll
     for (int j = 0; j < ST_RB; ++j) {
-        ab[j] = st_block_sum(ab[j], red);
-        aa[j] = st_block_sum(aa[j], red);
-        abB[j] = st_block_sum(abB[j], red);
-        aaB[j] = st_block_sum(aaB[j], red);
+        v[2 + 4 * j] = ab[j];
+        v[3 + 4 * j] = aa[j];
+        v[4 + 4 * j] = abB[j];
+        v[5 + 4 * j] = aaB[j];
     }
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NS; ++i) red[wave][i] = v[i];
+    __syncthreads();
+    // thread i adds the waves' parts of sum i (thread 0 reading all of them
+    // at once held them all in registers: 144 of them)
+    if (threadIdx.x < NS) {
+        double t = 0.0;
+        for (int w = 0; w < ST_THREADS / 64; ++w) t += red[w][threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        const double sbb = tot[0], sbbB = tot[1];
 #pragma unroll
         for (int j = 0; j < ST_RB; ++j) {
             const int r = r0 + j;
             if (r >= g.P) break;
-            const double t = aaB[j] > 0.0 ? abB[j] / aaB[j] : 0.0;
-            const double el = t * t * aaB[j] - 2.0 * t * abB[j] + bbB;
-            const double eg = t * t * aa[j] - 2.0 * t * ab[j] + bb;
+            const double sab = tot[2 + 4 * j], saa = tot[3 + 4 * j], sabB = tot[4 + 4 * j], saaB = tot[5 + 4 * j];
+            const double t = saaB > 0.0 ? sabB / saaB : 0.0;
+            const double el = t * t * saaB - 2.0 * t * sabB + sbbB;
+            const double eg = t * t * saa - 2.0 * t * sab + sbb;
             const size_t o = (size_t)r * g.P + s;
             theta[o] = t;
-            err_local[o] = bbB > 0.0 ? fmax(el, 0.0) / bbB : 0.0;
-            err_global[o] = bb > 0.0 ? fmax(eg, 0.0) / bb : 0.0;
+            err_local[o] = sbbB > 0.0 ? fmax(el, 0.0) / sbbB : 0.0;
+            err_global[o] = sbb > 0.0 ? fmax(eg, 0.0) / sbb : 0.0;
         }
     }
 }
