@@ -103,37 +103,55 @@ __device__ double st_fixed(const StudyGeom& g, const double* rf_s, double z, dou
 }
 
 // grid (ceil(T / 256), C, P).  The transmit arrival of every element at z_s
-// is staged in LDS; samples whose time is more than 4 sigma from every
-// arrival skip the pulse.  Block x = 0, thread 0 also stores the echo's
-// sample support [lo, hi] (a superset: a margin of two samples each side).
+// is staged in LDS, with the earliest and the latest of them (a min / max
+// reduction, exact in any order); a sample more than 4 sigma after the latest
+// or before the earliest is more than 4 sigma from every arrival, so every
+// pulse gives exactly 0 there and the sample is stored as 0 without the loop
+// over the arrivals (most of the record: an echo spans a few hundred
+// samples).  Block x = 0, thread 0 also stores the echo's sample support
+// [lo, hi] (a superset: a margin of two samples each side).
 __global__ __launch_bounds__(ST_THREADS) void study_echo_kernel(const StudyGeom g, double* __restrict__ rf,
                                                                 int2* __restrict__ span) {
     extern __shared__ double tx_arrival[];  // [n_tx]
+    __shared__ double ext[2][ST_THREADS / 64];
     const int n = blockIdx.y, s = blockIdx.z;
     const double zs = st_point(g, s);
     const double zf = st_point(g, g.focal);
     const int first = (g.C - g.n_tx) / 2;
+    double lo_t = INFINITY, hi_t = -INFINITY;
     for (int m = threadIdx.x; m < g.n_tx; m += ST_THREADS) {
         const double xm = st_elem(g, first + m);
         const double Tm = (zf - sqrt(xm * xm + zf * zf)) / g.c;
-        tx_arrival[m] = Tm + sqrt(xm * xm + zs * zs) / g.c;
+        const double arr = Tm + sqrt(xm * xm + zs * zs) / g.c;
+        tx_arrival[m] = arr;
+        lo_t = fmin(lo_t, arr);
+        hi_t = fmax(hi_t, arr);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo_t = fmin(lo_t, __shfl_xor(lo_t, off, 64));
+        hi_t = fmax(hi_t, __shfl_xor(hi_t, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        ext[0][threadIdx.x >> 6] = lo_t;
+        ext[1][threadIdx.x >> 6] = hi_t;
     }
     __syncthreads();
+#pragma unroll
+    for (int w = 0; w < ST_THREADS / 64; ++w) {
+        lo_t = fmin(lo_t, ext[0][w]);
+        hi_t = fmax(hi_t, ext[1][w]);
+    }
     const double xn = st_elem(g, n);
     const double rx = sqrt(xn * xn + zs * zs) / g.c;
     const int k = blockIdx.x * ST_THREADS + threadIdx.x;
     if (k < g.T) {
         const double t = g.t0 + (double)k / g.fs - rx;
         double acc = 0.0;
-        for (int m = 0; m < g.n_tx; ++m) acc += st_pulse(t - tx_arrival[m], g.fc, g.sigma);
+        if (!(t - hi_t > 4.0 * g.sigma || lo_t - t > 4.0 * g.sigma))
+            for (int m = 0; m < g.n_tx; ++m) acc += st_pulse(t - tx_arrival[m], g.fc, g.sigma);
         rf[((size_t)s * g.C + n) * g.T + k] = acc;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double lo_t = tx_arrival[0], hi_t = tx_arrival[0];
-        for (int m = 1; m < g.n_tx; ++m) {
-            lo_t = fmin(lo_t, tx_arrival[m]);
-            hi_t = fmax(hi_t, tx_arrival[m]);
-        }
         const double u_lo = (lo_t + rx - 4.0 * g.sigma - g.t0) * g.fs - 2.0;
         const double u_hi = (hi_t + rx + 4.0 * g.sigma - g.t0) * g.fs + 2.0;
         // clamped in float64 before the conversion: an echo wholly outside
