@@ -164,6 +164,8 @@ __global__ __launch_bounds__(PAPER_THREADS) void paper_ref_kernel(const Setup64 
     __shared__ double env[FINE_MAX];
     __shared__ double Xr[FINE_MAX + 1];  // bins 0 .. N/2, N <= 2 FINE_MAX
     __shared__ double Xi[FINE_MAX + 1];
+    __shared__ double tc[2 * FINE_MAX];  // twiddles of the DFT length N <= 2 FINE_MAX
+    __shared__ double ts[2 * FINE_MAX];
     const int u = blockIdx.x;
     const int r = refs[u];
     const double zr = z0 + (double)r * dz;
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(PAPER_THREADS) void paper_ref_kernel(const Setup64 
         h_ref[(size_t)u * K + t] = fixed_delay(s, zr + (double)(t - h) * dz, zr, zr);
     for (int q = threadIdx.x; q < L; q += PAPER_THREADS) b[q] = unit_das(s, 0.0, zr + (double)(q - Qf) * dzf, zr);
     __syncthreads();
-    block_envelope<PAPER_THREADS>(b, L, env, Xr, Xi);
+    block_envelope<PAPER_THREADS>(b, L, env, Xr, Xi, tc, ts);
     if (threadIdx.x == 0) width[u] = env_fwhm(env, L) * dzf;
 }
 

@@ -12,21 +12,24 @@ constexpr int ENV_MAX = 1024;  // longest profile (the DFT length is at most 2 E
 // env[n] = |analytic signal of b|[n], n < L <= ENV_MAX: DFT of b zero-padded
 // to N (the first power of two >= 2 L) at bins 0 .. N/2, weighted 1 at 0 and
 // N/2 and 2 in between (the analytic signal keeps those bins), then the
-// inverse DFT at n < L.  Xr, Xi hold N/2 + 1 entries.  All THREADS threads of
-// the workgroup call it; b must be complete (a barrier before the call) and
-// env is complete on return.
+// inverse DFT at n < L.  Xr, Xi hold N/2 + 1 entries; tc, ts (2 ENV_MAX
+// entries each) take the N twiddles cos, sin of 2 pi m / N, evaluated once per
+// call and read by both transforms (each term used to evaluate its own: the
+// same values, so the same sums).  All THREADS threads of the workgroup call
+// it; b must be complete (a barrier before the call) and env is complete on
+// return.
 template <int THREADS>
-__device__ void block_envelope(const double* b, int L, double* env, double* Xr, double* Xi) {
+__device__ void block_envelope(const double* b, int L, double* env, double* Xr, double* Xi, double* tc, double* ts) {
     int N = 1;
     while (N < 2 * L) N *= 2;
+    for (int m = threadIdx.x; m < N; m += THREADS) sincospi(2.0 * (double)m / (double)N, &ts[m], &tc[m]);
+    __syncthreads();
     for (int k = threadIdx.x; k <= N / 2; k += THREADS) {
         double re = 0.0, im = 0.0;
         for (int n = 0; n < L; ++n) {
             const int m = (int)(((int64_t)k * n) & (N - 1));
-            double sn, cs;
-            sincospi(2.0 * (double)m / (double)N, &sn, &cs);
-            re += b[n] * cs;
-            im -= b[n] * sn;
+            re += b[n] * tc[m];
+            im -= b[n] * ts[m];
         }
         const double wgt = (k == 0 || k == N / 2) ? 1.0 : 2.0;
         Xr[k] = wgt * re;
@@ -37,8 +40,7 @@ __device__ void block_envelope(const double* b, int L, double* env, double* Xr, 
         double re = 0.0, im = 0.0;
         for (int k = 0; k <= N / 2; ++k) {
             const int m = (int)(((int64_t)k * n) & (N - 1));
-            double sn, cs;
-            sincospi(2.0 * (double)m / (double)N, &sn, &cs);
+            const double cs = tc[m], sn = ts[m];
             re += Xr[k] * cs - Xi[k] * sn;
             im += Xr[k] * sn + Xi[k] * cs;
         }

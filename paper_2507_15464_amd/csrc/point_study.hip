@@ -180,12 +180,14 @@ __global__ __launch_bounds__(ST_THREADS) void study_window_kernel(const StudyGeo
     __shared__ double env[ENV_MAX];
     __shared__ double Xr[ENV_MAX + 1];
     __shared__ double Xi[ENV_MAX + 1];
+    __shared__ double tc[2 * ENV_MAX];
+    __shared__ double ts[2 * ENV_MAX];
     const int L = 2 * g.Qf + 1;
     const double zf = st_point(g, g.focal);
     const double* rf_f = rf + (size_t)g.focal * g.C * g.T;
     for (int q = threadIdx.x; q < L; q += ST_THREADS) b[q] = st_das(g, rf_f, zf + (double)(q - g.Qf) * g.dzf);
     __syncthreads();
-    block_envelope<ST_THREADS>(b, L, env, Xr, Xi);
+    block_envelope<ST_THREADS>(b, L, env, Xr, Xi, tc, ts);
     if (threadIdx.x == 0) {
         const double W = env_fwhm(env, L) * g.dzf;
         win[0] = W;
@@ -434,6 +436,8 @@ __global__ __launch_bounds__(ST_THREADS) void study_stats_kernel(const StudyGeom
     __shared__ double env[ENV_MAX];
     __shared__ double Xr[ENV_MAX + 1];
     __shared__ double Xi[ENV_MAX + 1];
+    __shared__ double tc[2 * ENV_MAX];
+    __shared__ double ts[2 * ENV_MAX];
     const int s = blockIdx.x;
     const int L = 2 * g.Qh + 1;
     const double zs = st_point(g, s);
@@ -446,13 +450,13 @@ __global__ __launch_bounds__(ST_THREADS) void study_stats_kernel(const StudyGeom
         a[q] = t * st_fixed(g, rf_s, z, zf);
     }
     __syncthreads();
-    block_envelope<ST_THREADS>(b, L, env, Xr, Xi);
+    block_envelope<ST_THREADS>(b, L, env, Xr, Xi, tc, ts);
     if (threadIdx.x == 0) {
         stats[(size_t)s * 4 + 0] = env[env_peak(env, L)];
         stats[(size_t)s * 4 + 2] = env_fwhm(env, L) * g.dzf;
     }
     __syncthreads();
-    block_envelope<ST_THREADS>(a, L, env, Xr, Xi);
+    block_envelope<ST_THREADS>(a, L, env, Xr, Xi, tc, ts);
     if (threadIdx.x == 0) {
         stats[(size_t)s * 4 + 1] = env[env_peak(env, L)];
         stats[(size_t)s * 4 + 3] = env_fwhm(env, L) * g.dzf;
