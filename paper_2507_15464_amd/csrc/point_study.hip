@@ -42,6 +42,7 @@ namespace {
 constexpr int ST_THREADS = 256;
 constexpr int ST_RB = 4;          // delay curves per pair workgroup
 constexpr int ST_UNR = 4;         // listed channels whose reads the pair kernel issues together
+constexpr int ST_ECHO_PER_THREAD = 4;  // echo samples per thread (the arrival table and receive path shared)
 constexpr int ST_MAX_ELEM = 512;  // pair-kernel LDS: ST_RB x C x 20 + C x 8 bytes (45 KB at 512) + 8 KB of lists
 
 struct StudyGeom {
@@ -102,7 +103,8 @@ __device__ double st_fixed(const StudyGeom& g, const double* rf_s, double z, dou
     return acc;
 }
 
-// grid (ceil(T / 256), C, P).  The transmit arrival of every element at z_s
+// grid (ceil(T / (256 ST_ECHO_PER_THREAD)), C, P), each thread taking
+// ST_ECHO_PER_THREAD samples 256 apart.  The transmit arrival of every element at z_s
 // is staged in LDS, with the earliest and the latest of them (a min / max
 // reduction, exact in any order); a sample more than 4 sigma after the latest
 // or before the earliest is more than 4 sigma from every arrival, so every
@@ -143,13 +145,15 @@ __global__ __launch_bounds__(ST_THREADS) void study_echo_kernel(const StudyGeom 
     }
     const double xn = st_elem(g, n);
     const double rx = sqrt(xn * xn + zs * zs) / g.c;
-    const int k = blockIdx.x * ST_THREADS + threadIdx.x;
-    if (k < g.T) {
-        const double t = g.t0 + (double)k / g.fs - rx;
-        double acc = 0.0;
-        if (!(t - hi_t > 4.0 * g.sigma || lo_t - t > 4.0 * g.sigma))
-            for (int m = 0; m < g.n_tx; ++m) acc += st_pulse(t - tx_arrival[m], g.fc, g.sigma);
-        rf[((size_t)s * g.C + n) * g.T + k] = acc;
+    for (int e = 0; e < ST_ECHO_PER_THREAD; ++e) {
+        const int k = (blockIdx.x * ST_ECHO_PER_THREAD + e) * ST_THREADS + threadIdx.x;
+        if (k < g.T) {
+            const double t = g.t0 + (double)k / g.fs - rx;
+            double acc = 0.0;
+            if (!(t - hi_t > 4.0 * g.sigma || lo_t - t > 4.0 * g.sigma))
+                for (int m = 0; m < g.n_tx; ++m) acc += st_pulse(t - tx_arrival[m], g.fc, g.sigma);
+            rf[((size_t)s * g.C + n) * g.T + k] = acc;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const double u_lo = (lo_t + rx - 4.0 * g.sigma - g.t0) * g.fs - 2.0;
@@ -567,7 +571,9 @@ extern "C" int32_t tidas_point_study(const tidas_array* array, const tidas_tx* t
     double* win = (double*)(ws + lay.win);
     hipStream_t s = (hipStream_t)stream;
 
-    hipLaunchKernelGGL(study_echo_kernel, dim3((uint32_t)((n_samples + ST_THREADS - 1) / ST_THREADS), C, n_points),
+    hipLaunchKernelGGL(study_echo_kernel,
+                       dim3((uint32_t)((n_samples + ST_THREADS * ST_ECHO_PER_THREAD - 1) / (ST_THREADS * ST_ECHO_PER_THREAD)),
+                            C, n_points),
                        dim3(ST_THREADS), (size_t)n_tx * sizeof(double), s, g, rf, span);
     if (int32_t st = check_launch("tidas_point_study(echo)")) return st;
     const int64_t L = 2 * (int64_t)line_half + 1;
