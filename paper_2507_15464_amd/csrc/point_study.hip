@@ -41,7 +41,6 @@ namespace {
 
 constexpr int ST_THREADS = 256;
 constexpr int ST_RB = 4;          // delay curves per pair workgroup
-constexpr int ST_UNR = 4;         // listed channels whose reads the pair kernel issues together
 constexpr int ST_ECHO_PER_THREAD = 4;  // echo samples per thread (the arrival table and receive path shared)
 constexpr int ST_MAX_ELEM = 512;  // pair-kernel LDS: ST_RB x C x 20 + C x 8 bytes (45 KB at 512) + 8 KB of lists
 
@@ -209,9 +208,10 @@ __global__ __launch_bounds__(ST_THREADS) void study_window_kernel(const StudyGeo
 // first lists, in order of r then n, the (r, n) with a non-zero weight whose
 // support meets the chunk's read positions (an interval of q per (r, n)), so
 // a thread visits only those (an echo's support spans a few hundred samples
-// of a line of thousands, so most (r, n) reach no sample of a chunk); each
-// curve's channels are still summed in increasing n, as in a plain loop over
-// the aperture, so the bits do not depend on the lists.
+// of a line of thousands, so most (r, n) reach no sample of a chunk), and a
+// wave passes over the listed entries that reach none of its own 64 samples;
+// each curve's channels are still summed in increasing n, as in a plain loop
+// over the aperture, so the bits do not depend on the lists.
 // The line's sums go through a fixed-order workgroup reduction, then thread
 // 0 forms Theta and both errors from them:
 //   ||t a - b||^2 = t^2 sum a^2 - 2 t sum a b + sum b^2  (clamped at 0).
@@ -321,37 +321,33 @@ __global__ __launch_bounds__(ST_THREADS) void study_pair_kernel(const StudyGeom 
         __syncthreads();
 
         const int q = c0 + threadIdx.x;
+        const int wq0 = c0 + 64 * wave, wq1 = wq0 + 63;  // this wave's samples
         if (q <= g.Ql) {
             double a[ST_RB];
 #pragma unroll
             for (int j = 0; j < ST_RB; ++j) {
                 a[j] = 0.0;
                 const int t_end = seg[j + 1];
-                // ST_UNR listed channels at a time: their reads (at positions
-                // clamped into the record, so every one is in bounds) are
-                // issued together, then added in list order where the sample
-                // lies in the support
-                for (int t = seg[j]; t < t_end; t += ST_UNR) {
-                    bool in[ST_UNR];
-                    double s0[ST_UNR], s1[ST_UNR], fw[ST_UNR], wv[ST_UNR];
-#pragma unroll
-                    for (int u = 0; u < ST_UNR; ++u) {
-                        const int n = lst[min(t + u, t_end - 1)];
-                        const int e = j * g.C + n;
-                        const int2 su = sp[n];
-                        const int k = k_rn[e] + q;
-                        in[u] = t + u < t_end && k >= su.x - 1 && k <= su.y;
-                        const double* row = rf_s + (size_t)n * g.T;
-                        const double r0 = row[min(max(k, 0), g.T - 1)];
-                        const double r1 = row[min(max(k + 1, 0), g.T - 1)];
-                        s0[u] = k >= su.x ? r0 : 0.0;
-                        s1[u] = k + 1 <= su.y ? r1 : 0.0;
-                        fw[u] = f_rn[e];
-                        wv[u] = w_rn[e];
+                for (int t = seg[j]; t < t_end; ++t) {
+                    const int n = lst[t];
+                    const int e = j * g.C + n;
+                    const int2 su = sp[n];
+                    const int kr = k_rn[e];
+                    // the same for every lane of the wave: an entry whose
+                    // reads miss the wave's 64 samples adds nothing to them
+                    if (su.x - 1 - kr > wq1 || su.y - kr < wq0) continue;
+                    // reads at positions clamped into the record (every one in
+                    // bounds), added where the sample lies in the support
+                    const int k = kr + q;
+                    const double* row = rf_s + (size_t)n * g.T;
+                    const double r0 = row[min(max(k, 0), g.T - 1)];
+                    const double r1 = row[min(max(k + 1, 0), g.T - 1)];
+                    if (k >= su.x - 1 && k <= su.y) {
+                        const double f = f_rn[e];
+                        const double s0 = k >= su.x ? r0 : 0.0;
+                        const double s1 = k + 1 <= su.y ? r1 : 0.0;
+                        a[j] += w_rn[e] * ((1.0 - f) * s0 + f * s1);
                     }
-#pragma unroll
-                    for (int u = 0; u < ST_UNR; ++u)
-                        if (in[u]) a[j] += wv[u] * ((1.0 - fw[u]) * s0[u] + fw[u] * s1[u]);
                 }
             }
 #ifdef TIDAS_DEBUG
