@@ -81,7 +81,7 @@ def parse():
                     help="time the CPU oracle on one core only (no worker processes)")
     ap.add_argument("--only", choices=["tidas", "das"], default=None, help="time one op only (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="after timing, run one plain device copy of the input batch (known byte count) so "
+                    help="after timing, run one plain device copy of known byte count (main: the input batch; batch: 64 MiB) so "
                          "hardware byte counters can be calibrated against it")
     return ap.parse_args()
 
@@ -91,18 +91,19 @@ def log(msg):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tidas_b4_kernel_256x1024_k129_b64_traffic.json")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tidas_b4_batch_kernel_ragged64_k65_traffic.json")
 BF16_MFMA_TFLOPS = 2500.0                                    # dense bf16 matrix peak
 FP32_MFMA_TFLOPS = 157.3                                     # dense fp32 matrix peak
 
 
-def measured_traffic(batch):
+def measured_traffic(batch, path=TRAFFIC_FILE):
     """HBM bytes per launch of the line-model kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a plain copy of known
     size), or None when the kernel source changed since they were taken or the
     batch differs from the profiled one."""
     import hashlib
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
         with open(os.path.join(ROOT, rec["source"]), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
@@ -508,6 +509,12 @@ def run_batch(args):
     app_prep = _events_ms(pb.apply, args.steps, args.warmup)
     app_loop = _events_ms(lambda: [td.apply(kbs[f], maps[f], out=outs_t[f]) for f in range(n)],
                           max(1, args.steps // 4), 1)
+    if args.copy_probe:
+        # a plain device copy of known size, for scaling the traffic counters
+        src = torch.zeros(16 * 1024 * 1024, device=dev)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {src.numel() * 4} bytes read, {src.numel() * 4} bytes written")
     px = sum(a * b for a, b in sizes)
     batch_bytes = float(sum(8 * a * b + 4 * a * base.K for a, b in sizes))
     out = {
@@ -528,7 +535,8 @@ def run_batch(args):
         # the prepared batch's one launch: read every map, write every image,
         # read every bank once (8 Z X + 4 Z K bytes per frame)
         "roofline": {"bound": "hbm", "achieved": batch_bytes / (app_prep * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": batch_bytes / (app_prep * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": batch_bytes / (app_prep * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(n, BATCH_TRAFFIC_FILE),
                      "kernel": "tidas_b4_kernel<false,6,true,true> (prepared batch)", "bytes_per_launch": batch_bytes},
     }
     print(json.dumps(out), flush=True)
