@@ -92,6 +92,7 @@ def log(msg):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tidas_b4_kernel_256x1024_k129_b64_traffic.json")
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tidas_b4_batch_kernel_ragged64_k65_traffic.json")
+LATERAL_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lateral_pass_kernel_1024x256_k33_b64_traffic.json")
 BF16_MFMA_TFLOPS = 2500.0                                    # dense bf16 matrix peak
 FP32_MFMA_TFLOPS = 157.3                                     # dense fp32 matrix peak
 
@@ -726,7 +727,8 @@ def run_separable(args):
                    "global_batch": B},
         "lateral_pass": {"ms_per_step": lat_ms, "frames_per_s": B / (lat_ms * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": lat_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": lat_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "lateral_pass_kernel",
+                     "frac": lat_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(B, LATERAL_TRAFFIC_FILE),
+                     "kernel": "lateral_pass_kernel",
                      "bytes_per_launch": lat_bytes},
         "rel_l2_vs_das_2d": errors,
     }
