@@ -288,7 +288,7 @@ __global__ __launch_bounds__(ST_THREADS) void study_pair_kernel(const StudyGeom 
         // the chunk's list: lst[seg[j] .. seg[j + 1]) holds, in increasing n,
         // the channels of curve j whose read positions k_rn + q, q in
         // [c0, c1], meet the support [su.x - 1, su.y] (an ordered compaction:
-        // per round of 256 entries a ballot per wave and the waves' counts)
+        // per pass over 256 entries a ballot per wave and the waves' counts)
         if (threadIdx.x <= ST_RB) seg[threadIdx.x] = 0;
         int base = 0;
         for (int t0 = 0; t0 < E; t0 += ST_THREADS) {
